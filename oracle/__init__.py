@@ -1,0 +1,296 @@
+"""CPU oracle of the REGC method (arXiv:1908.11118) -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 C code (regc_oracle.c: Philox, LJ energies, the GC/displacement chain,
+the replica-exchange step; mbar_oracle.c: the naive multistate reweighting) plus a
+ctypes wrapper.  Only tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It never imports the HIP package and shares no code with it.
+
+Any object with the attributes of a workload (slab, lx, ly, zlo, zhi, t, mu, n_max,
+eps_gg, sig_gg, eps_gs, sig_gs, rc, shifted, mode, hc_frac, lambda1, seed, p_disp,
+p_ins, max_disp, trials_per_sweep, swap_every, sample_every, swap_scheme, sites)
+describes a problem.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_DIR = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_DIR, "liboracle.so")
+_SOURCES = ["regc_oracle.c", "mbar_oracle.c"]
+NSTAT = 10
+STAT_NAMES = ["disp_att", "disp_acc", "ins_att", "ins_acc", "del_att", "del_acc",
+              "cap_rej", "empty_rej", "wall_rej", "core_rej"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc: -O2, no FP contraction, no fast-math, OpenMP."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", _LIB_PATH] + [os.path.join(_DIR, s) for s in _SOURCES] + ["-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u32p = C.POINTER(C.c_uint32)
+
+
+class _Config(C.Structure):
+    _fields_ = [("eps_gg", C.c_double), ("sig_gg", C.c_double), ("eps_gs", C.c_double),
+                ("sig_gs", C.c_double), ("rc", C.c_double), ("shifted", C.c_int), ("mode", C.c_int),
+                ("hc_frac", C.c_double), ("n_slab", C.c_int), ("slab", _dp),
+                ("lx", C.c_double), ("ly", C.c_double), ("zlo", C.c_double), ("zhi", C.c_double),
+                ("n_sites", C.c_int), ("sites", _dp), ("lambda1", C.c_double), ("n_max", C.c_int),
+                ("n_t", C.c_int), ("n_mu", C.c_int), ("t", _dp), ("mu", _dp),
+                ("seed", C.c_uint64), ("p_disp", C.c_double), ("p_ins", C.c_double),
+                ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
+                ("sample_every", C.c_int), ("swap_scheme", C.c_int)]
+
+
+class _Walkers(C.Structure):
+    _fields_ = [("n", _i32p), ("e", _dp), ("label", _i32p), ("wos", _i32p), ("xyz", _dp),
+                ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p)]
+
+
+def _declare(L):
+    L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_lj.argtypes = [C.c_double] * 4 + [C.c_int]
+    L.orc_lj.restype = C.c_double
+    L.orc_state_lnz.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
+    L.orc_state_lnz.restype = C.c_double
+    L.orc_total_energy.argtypes = [C.POINTER(_Config), C.c_int, _dp]
+    L.orc_total_energy.restype = C.c_double
+    L.orc_run.argtypes = [C.POINTER(_Config), C.POINTER(_Walkers), _i64p, C.c_int64,
+                          _dp, _i32p, _i32p, C.c_int64, _i64p, _u32p, _i32p, C.c_int]
+    L.orc_run.restype = C.c_int
+    L.orc_swap_step.argtypes = [C.POINTER(_Config), C.POINTER(_Walkers), C.c_int64]
+    L.orc_swap_lnratio.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_int, C.c_double, C.c_int]
+    L.orc_swap_lnratio.restype = C.c_double
+    L.orc_mbar_solve.argtypes = [C.c_int, _dp, _dp, _i64p, C.c_int64, _dp, _i32p, C.c_double,
+                                 C.c_int, _dp, _dp, C.POINTER(C.c_int), _dp, C.c_int]
+    L.orc_mbar_solve.restype = C.c_int
+    L.orc_mbar_iterate.argtypes = [C.c_int, _dp, _dp, _i64p, C.c_int64, _dp, _i32p, _dp, _dp,
+                                   _dp, C.c_int]
+    L.orc_mbar_targets.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _i32p, _dp, C.c_int, _dp,
+                                   _dp, _dp, _dp, _dp, _i32p, C.c_int]
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+# ----------------------------------------------------------------------------
+def philox4x32_10(counter, key) -> np.ndarray:
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def lj(r2: float, eps: float = 1.0, sig: float = 1.0, rc: float = 2.5, shifted: int = 1) -> float:
+    return lib().orc_lj(r2, eps, sig, rc, shifted)
+
+
+def state_lnz(T: float, mu: float, lambda1: float = 1.0, mode: int = 0) -> float:
+    return lib().orc_state_lnz(T, mu, lambda1, mode)
+
+
+def state_arrays(w):
+    """beta_s and lnz_s of every state s = l*n_mu + m."""
+    t = np.asarray(w.t, dtype=np.float64)
+    mu = np.asarray(w.mu, dtype=np.float64)
+    beta = np.empty(len(t) * len(mu))
+    lnz = np.empty_like(beta)
+    for l, T in enumerate(t):
+        for m, u in enumerate(mu):
+            beta[l * len(mu) + m] = 1.0 / T
+            lnz[l * len(mu) + m] = state_lnz(float(T), float(u), w.lambda1, w.mode)
+    return beta, lnz
+
+
+class Chain:
+    """All walkers of one REGC simulation, advanced by the C oracle."""
+
+    def __init__(self, w, n_threads: int | None = None):
+        self.w = w
+        self.S = len(w.t) * len(w.mu)
+        self.n_max = int(w.n_max)
+        self.K = w.trials_per_sweep if w.trials_per_sweep > 0 else self.n_max + 1
+        self.n_threads = n_threads or default_threads()
+        self._slab = np.ascontiguousarray(w.slab, dtype=np.float64).reshape(-1, 3)
+        sites = getattr(w, "sites", None)
+        self._sites = (np.ascontiguousarray(sites, dtype=np.float64).reshape(-1, 3)
+                       if sites is not None else np.zeros((0, 3)))
+        self._t = np.ascontiguousarray(w.t, dtype=np.float64)
+        self._mu = np.ascontiguousarray(w.mu, dtype=np.float64)
+        c = _Config()
+        c.eps_gg, c.sig_gg, c.eps_gs, c.sig_gs, c.rc = w.eps_gg, w.sig_gg, w.eps_gs, w.sig_gs, w.rc
+        c.shifted, c.mode, c.hc_frac = w.shifted, w.mode, w.hc_frac
+        c.n_slab = self._slab.shape[0]
+        c.slab = _p(self._slab, _dp)
+        c.lx, c.ly, c.zlo, c.zhi = w.lx, w.ly, w.zlo, w.zhi
+        c.n_sites = self._sites.shape[0]
+        c.sites = _p(self._sites, _dp)
+        c.lambda1, c.n_max = w.lambda1, w.n_max
+        c.n_t, c.n_mu = len(self._t), len(self._mu)
+        c.t, c.mu = _p(self._t, _dp), _p(self._mu, _dp)
+        c.seed = w.seed
+        c.p_disp, c.p_ins, c.max_disp = w.p_disp, w.p_ins, w.max_disp
+        c.trials_per_sweep, c.swap_every = w.trials_per_sweep, w.swap_every
+        c.sample_every, c.swap_scheme = w.sample_every, w.swap_scheme
+        self.cfg = c
+        S = self.S
+        # initial state: empty walkers, walker w holds state w
+        self.n = np.zeros(S, dtype=np.int32)
+        self.e = np.zeros(S, dtype=np.float64)
+        self.label = np.arange(S, dtype=np.int32)
+        self.wos = np.arange(S, dtype=np.int32)
+        self.xyz = np.zeros((S, self.n_max, 3), dtype=np.float64)
+        self.site = np.full((S, self.n_max), -1, dtype=np.int32)
+        self.stats = np.zeros((S, NSTAT), dtype=np.int64)
+        self.swap_att = np.zeros((4, S), dtype=np.int64)
+        self.swap_acc = np.zeros((4, S), dtype=np.int64)
+        self.sweep = np.zeros(1, dtype=np.int64)
+
+    def _walkers(self):
+        W = _Walkers()
+        W.n, W.e = _p(self.n, _i32p), _p(self.e, _dp)
+        W.label, W.wos = _p(self.label, _i32p), _p(self.wos, _i32p)
+        W.xyz = _p(self.xyz, _dp)
+        W.site = _p(self.site, _i32p) if self.w.mode == 2 else None
+        W.stats = _p(self.stats, _i64p)
+        W.swap_att, W.swap_acc = _p(self.swap_att, _i64p), _p(self.swap_acc, _i64p)
+        return W
+
+    def set_walkers(self, n, xyz, e=None, label=None):
+        """Load explicit configurations (energies recomputed unless given)."""
+        self.n[:] = n
+        self.xyz[:] = 0.0
+        for w in range(self.S):
+            self.xyz[w, : n[w]] = xyz[w][: n[w]]
+        if e is None:
+            e = [self.energy(self.xyz[w, : n[w]]) for w in range(self.S)]
+        self.e[:] = e
+        if label is not None:
+            self.label[:] = label
+            self.wos[self.label] = np.arange(self.S, dtype=np.int32)
+
+    def energy(self, xyz) -> float:
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        return lib().orc_total_energy(C.byref(self.cfg), x.shape[0], _p(x, _dp))
+
+    def run(self, n_sweeps: int, trace: bool = False):
+        """Advance n_sweeps sweeps.  Returns dict with samples (e, n, state) and,
+        when trace is set, accept bits [n_sweeps, S, words] and N [n_sweeps, S]."""
+        S = self.S
+        every = self.w.sample_every
+        s0 = int(self.sweep[0])
+        n_samp = 0
+        if every > 0:
+            n_samp = ((s0 + n_sweeps) // every - s0 // every) * S
+        se = np.zeros(max(n_samp, 1), dtype=np.float64)
+        sn = np.zeros(max(n_samp, 1), dtype=np.int32)
+        ss = np.zeros(max(n_samp, 1), dtype=np.int32)
+        cnt = np.zeros(1, dtype=np.int64)
+        words = (self.K + 31) // 32
+        tb = np.zeros((n_sweeps, S, words), dtype=np.uint32) if trace else None
+        tn = np.zeros((n_sweeps, S), dtype=np.int32) if trace else None
+        W = self._walkers()
+        rc = lib().orc_run(C.byref(self.cfg), C.byref(W), _p(self.sweep, _i64p), n_sweeps,
+                           _p(se, _dp), _p(sn, _i32p), _p(ss, _i32p), n_samp, _p(cnt, _i64p),
+                           _p(tb, _u32p), _p(tn, _i32p), self.n_threads)
+        if rc != 0:
+            raise RuntimeError(f"oracle run failed ({rc})")
+        k = int(cnt[0])
+        out = {"e": se[:k], "n": sn[:k], "state": ss[:k]}
+        if trace:
+            out["bits"], out["trace_n"] = tb, tn
+        return out
+
+    def swap_step(self, q: int):
+        W = self._walkers()
+        lib().orc_swap_step(C.byref(self.cfg), C.byref(W), q)
+
+
+def swap_lnratio(beta_a, lnz_a, beta_b, lnz_b, e_i, n_i, e_j, n_j) -> float:
+    return lib().orc_swap_lnratio(beta_a, lnz_a, beta_b, lnz_b, e_i, int(n_i), e_j, int(n_j))
+
+
+# ----------------------------------------------------------------------------
+def mbar_solve(beta, lnz, omega, e, n, tol=1e-10, max_iter=10000, f0=None, n_threads=None):
+    """Naive self-consistent solution.  Returns (f, logd, converged, iters, delta)."""
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    lnz = np.ascontiguousarray(lnz, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.int64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    S = len(beta)
+    f = np.zeros(S) if f0 is None else np.array(f0, dtype=np.float64)
+    logd = np.zeros(len(e))
+    it = C.c_int(0)
+    delta = np.zeros(1)
+    rc = lib().orc_mbar_solve(S, _p(beta, _dp), _p(lnz, _dp), _p(omega, _i64p), len(e), _p(e, _dp),
+                              _p(n, _i32p), tol, max_iter, _p(f, _dp), _p(logd, _dp), C.byref(it),
+                              _p(delta, _dp), n_threads or default_threads())
+    return f, logd, rc == 0, it.value, float(delta[0])
+
+
+def mbar_iterate(beta, lnz, omega, e, n, f_in, n_threads=None):
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    lnz = np.ascontiguousarray(lnz, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.int64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    f_in = np.ascontiguousarray(f_in, dtype=np.float64)
+    f_out = np.zeros_like(f_in)
+    logd = np.zeros(len(e))
+    lib().orc_mbar_iterate(len(beta), _p(beta, _dp), _p(lnz, _dp), _p(omega, _i64p), len(e),
+                           _p(e, _dp), _p(n, _i32p), _p(f_in, _dp), _p(f_out, _dp), _p(logd, _dp),
+                           n_threads or default_threads())
+    return f_out, logd
+
+
+def mbar_targets(tbeta, tlnz, e, n, logd, n_max, n_threads=None):
+    """Returns dict f, mean_n, mean_e, mean_e2, p_n [T, n_max+1], phase."""
+    tbeta = np.ascontiguousarray(tbeta, dtype=np.float64)
+    tlnz = np.ascontiguousarray(tlnz, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    logd = np.ascontiguousarray(logd, dtype=np.float64)
+    T = len(tbeta)
+    f = np.zeros(T)
+    mn, me, me2 = np.zeros(T), np.zeros(T), np.zeros(T)
+    pn = np.zeros((T, n_max + 1))
+    ph = np.zeros(T, dtype=np.int32)
+    lib().orc_mbar_targets(T, _p(tbeta, _dp), _p(tlnz, _dp), len(e), _p(e, _dp), _p(n, _i32p),
+                           _p(logd, _dp), n_max, _p(f, _dp), _p(mn, _dp), _p(me, _dp), _p(me2, _dp),
+                           _p(pn, _dp), _p(ph, _i32p), n_threads or default_threads())
+    return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "p_n": pn, "phase": ph}

@@ -1,0 +1,498 @@
+/*
+ * regc_oracle.c -- plain FP64 CPU oracle of the replica-exchange grand-canonical
+ * (REGC) Monte Carlo method of Zhou, Scheffler and Ghiringhelli,
+ * "Determining Surface Phase Diagrams Including Anharmonic Effects" (arXiv:1908.11118).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct reference
+ * that the HIP library is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or constant generator with the HIP path.
+ *
+ * Everything is double precision, compiled without FP contraction and without
+ * fast-math.  Each walker's chain is a plain sequential loop; OpenMP only runs
+ * different walkers side by side between two sweep boundaries (walkers never
+ * read each other's state there).
+ *
+ * What each function follows in the paper:
+ *   - target distribution: Sec. II.A.1, Eq. (1) (GC probability density);
+ *   - removal acceptance: Sec. II.A.1, Eq. (2); insertion acceptance: Eq. (3),
+ *     read with the exponent beta*[mu - (E_{N+1} - E_N)] (the printed signs are
+ *     garbled; this is the detailed-balance ratio of Eq. (1));
+ *   - particle choice for removal: i = floor(y*N), Sec. II.A.1;
+ *   - replica-exchange acceptance: Sec. II.A.2, Eq. (6), read as
+ *     ln A = (b_a - b_b)(E_i - E_j) + (N_j - N_i)(lnz_a - lnz_b) with
+ *     lnz = b*mu - 3 ln Lambda(T), Lambda = Lambda1/sqrt(T) (Eq. (1) again);
+ *   - four collective neighbour-swap types chosen with probability 1/4,
+ *     Sec. II.A.2 (Fig. 2 is not available; the types are read as even/odd
+ *     T-axis pairs and even/odd mu-axis pairs);
+ *   - displacement acceptance: Sec. II.A.3, Eq. (7), cube of half-width delta;
+ *   - LJ 12-6 pair potential: Appendix, truncated and shifted at rc.
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written
+ * here from its published definition.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NSTAT 10
+enum {
+    ST_DISP_ATT = 0, ST_DISP_ACC, ST_INS_ATT, ST_INS_ACC, ST_DEL_ATT, ST_DEL_ACC,
+    ST_CAP_REJ, ST_EMPTY_REJ, ST_WALL_REJ, ST_CORE_REJ
+};
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10                                                             */
+/* ------------------------------------------------------------------------- */
+/* One round maps (c0,c1,c2,c3) with key (k0,k1) to
+ *   (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0))
+ * with A = 0xD2511F53, B = 0xCD9E8D57; between rounds the key is advanced by
+ * the Weyl increments 0x9E3779B9 and 0xBB67AE85. Ten rounds. */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void philox_words(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t out[4])
+{
+    uint32_t ctr[4] = {a, b, c, d};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* open-interval uniform from one 32-bit word: (w + 1/2) / 2^32 (exact in FP64) */
+static double u32_open(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/* 53-bit uniform in [0,1) from two words (exact in FP64) */
+static double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Configuration                                                             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    /* pair potential (Appendix): phi(r) = 4 eps [(sig/r)^12 - (sig/r)^6] - shift, r < rc */
+    double eps_gg, sig_gg, eps_gs, sig_gs, rc;
+    int shifted;          /* 1: subtract phi(rc) so phi is continuous at rc */
+    int mode;             /* 0 LJ gas on frozen LJ slab, 1 ideal gas (no interactions), 2 site lattice */
+    double hc_frac;       /* new pairs closer than hc_frac*sigma are rejected outright */
+    /* surface and gas region */
+    int n_slab;
+    const double *slab;   /* [n_slab][3] */
+    double lx, ly, zlo, zhi;
+    int n_sites;          /* mode 2 only */
+    const double *sites;  /* [n_sites][3] */
+    double lambda1;       /* thermal wavelength at T = 1 */
+    int n_max;
+    /* state grid: state s = l*n_mu + m */
+    int n_t, n_mu;
+    const double *t, *mu;
+    /* schedule */
+    uint64_t seed;
+    double p_disp, p_ins, max_disp;
+    int trials_per_sweep;
+    int swap_every, sample_every, swap_scheme;
+} orc_config;
+
+/* derived per-state constants */
+typedef struct {
+    double beta, lnz;
+} orc_statec;
+
+static void state_constants(const orc_config *c, orc_statec *sc)
+{
+    for (int l = 0; l < c->n_t; ++l) {
+        for (int m = 0; m < c->n_mu; ++m) {
+            double T = c->t[l];
+            double beta = 1.0 / T;
+            double lnz;
+            if (c->mode == 2) {
+                lnz = beta * c->mu[m];                 /* site lattice: Lambda taken as 1 */
+            } else {
+                double lam = c->lambda1 / sqrt(T);     /* Lambda(T) = Lambda1 / sqrt(T) */
+                lnz = beta * c->mu[m] - 3.0 * log(lam);
+            }
+            sc[l * c->n_mu + m].beta = beta;
+            sc[l * c->n_mu + m].lnz = lnz;
+        }
+    }
+}
+
+double orc_state_lnz(double T, double mu, double lambda1, int mode)
+{
+    double beta = 1.0 / T;
+    if (mode == 2) return beta * mu;
+    return beta * mu - 3.0 * log(lambda1 / sqrt(T));
+}
+
+/* truncated (and optionally shifted) LJ 12-6 */
+double orc_lj(double r2, double eps, double sig, double rc, int shifted)
+{
+    if (r2 >= rc * rc) return 0.0;
+    double s2 = (sig * sig) / r2;
+    double s6 = s2 * s2 * s2;
+    double v = 4.0 * eps * (s6 * s6 - s6);
+    if (shifted) {
+        double c2 = (sig * sig) / (rc * rc);
+        double c6 = c2 * c2 * c2;
+        v -= 4.0 * eps * (c6 * c6 - c6);
+    }
+    return v;
+}
+
+static double min_image(double d, double box)
+{
+    if (d > 0.5 * box) return d - box;
+    if (d < -0.5 * box) return d + box;
+    return d;
+}
+
+static double dist2(const orc_config *c, const double *a, const double *b)
+{
+    double dx = min_image(a[0] - b[0], c->lx);
+    double dy = min_image(a[1] - b[1], c->ly);
+    double dz = a[2] - b[2];
+    return dx * dx + dy * dy + dz * dz;
+}
+
+/* Interaction energy of a particle at p with the other gas particles (skip index `skip`)
+ * and with the slab.  *core is set when a pair closer than the hard-core radius is found. */
+static double particle_energy(const orc_config *c, const double *p, const double *xyz, int n,
+                              int skip, int *core)
+{
+    double e = 0.0;
+    double hg = c->hc_frac * c->sig_gg, hs = c->hc_frac * c->sig_gs;
+    *core = 0;
+    for (int j = 0; j < n; ++j) {
+        if (j == skip) continue;
+        double r2 = dist2(c, p, xyz + 3 * j);
+        if (r2 < hg * hg) *core = 1;
+        e += orc_lj(r2, c->eps_gg, c->sig_gg, c->rc, c->shifted);
+    }
+    for (int a = 0; a < c->n_slab; ++a) {
+        double r2 = dist2(c, p, c->slab + 3 * a);
+        if (r2 < hs * hs) *core = 1;
+        e += orc_lj(r2, c->eps_gs, c->sig_gs, c->rc, c->shifted);
+    }
+    return e;
+}
+
+/* Total configurational energy: gas-gas pairs plus gas-slab pairs; the frozen
+ * slab has no internal interaction (Sec. III.A). */
+double orc_total_energy(const orc_config *c, int n, const double *xyz)
+{
+    if (c->mode == 1) return 0.0;
+    double e = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = i + 1; j < n; ++j)
+            e += orc_lj(dist2(c, xyz + 3 * i, xyz + 3 * j), c->eps_gg, c->sig_gg, c->rc, c->shifted);
+        for (int a = 0; a < c->n_slab; ++a)
+            e += orc_lj(dist2(c, xyz + 3 * i, c->slab + 3 * a), c->eps_gs, c->sig_gs, c->rc, c->shifted);
+    }
+    return e;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One trial move of one walker                                              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t *n;        /* [S] */
+    double *e;         /* [S] */
+    int32_t *label;    /* [S] state held by walker */
+    int32_t *wos;      /* [S] walker holding state */
+    double *xyz;       /* [S][n_max][3] */
+    int32_t *site;     /* [S][n_max] site index (mode 2), may be NULL otherwise */
+    int64_t *stats;    /* [S][ORC_NSTAT] by state */
+    int64_t *swap_att; /* [4][S] by swap type and lower state of the pair */
+    int64_t *swap_acc;
+} orc_walkers;
+
+/* Metropolis decision on x = ln(acceptance ratio): accept when x >= 0, else
+ * when the uniform U is below exp(x). */
+static int metropolis(double x, double U)
+{
+    if (x >= 0.0) return 1;
+    return U < exp(x);
+}
+
+static int site_occupied(const int32_t *site, int n, int k)
+{
+    for (int j = 0; j < n; ++j)
+        if (site[j] == k) return 1;
+    return 0;
+}
+
+/* Returns 1 if the trial was accepted.  `lnk` holds log(k) for k = 0..n_max+1. */
+static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, double lnv,
+                 orc_walkers *W, int w, int64_t sweep, int t)
+{
+    uint32_t A[4], B[4];
+    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, (uint32_t)w, 0u, A);
+    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, (uint32_t)w, 1u, B);
+
+    const int s = W->label[w];
+    const double beta = sc[s].beta, lnz = sc[s].lnz;
+    int64_t *st = W->stats + (int64_t)s * ORC_NSTAT;
+    int n = W->n[w];
+    double *xyz = W->xyz + (int64_t)w * c->n_max * 3;
+    int32_t *site = W->site ? W->site + (int64_t)w * c->n_max : NULL;
+    const double U = u53(B[1], B[2]);
+
+    const uint64_t th_disp = (uint64_t)llround(c->p_disp * 4294967296.0);
+    const uint64_t th_ins = th_disp + (uint64_t)llround(c->p_ins * 4294967296.0);
+    const uint64_t a0 = A[0];
+
+    if (a0 < th_disp) {
+        /* ---- displacement, Eq. (7) ---- */
+        st[ST_DISP_ATT]++;
+        if (n == 0) { st[ST_EMPTY_REJ]++; return 0; }
+        int i = (int)(((uint64_t)A[1] * (uint64_t)n) >> 32);
+        double *ri = xyz + 3 * i;
+        double de;
+        double p[3];
+        int core_new = 0, core_old = 0;
+        if (c->mode == 2) {
+            int k = (int)(((uint64_t)A[2] * (uint64_t)c->n_sites) >> 32);
+            if (site_occupied(site, n, k)) { return 0; }
+            memcpy(p, c->sites + 3 * k, sizeof p);
+            double e_new = particle_energy(c, p, xyz, n, i, &core_new);
+            double e_old = particle_energy(c, ri, xyz, n, i, &core_old);
+            de = e_new - e_old;
+            double x = -beta * de;
+            if (metropolis(x, U)) {
+                memcpy(ri, p, sizeof p);
+                site[i] = k;
+                W->e[w] += de;
+                st[ST_DISP_ACC]++;
+                return 1;
+            }
+            return 0;
+        }
+        double d = c->max_disp;
+        p[0] = ri[0] + d * (2.0 * u32_open(A[2]) - 1.0);
+        p[1] = ri[1] + d * (2.0 * u32_open(A[3]) - 1.0);
+        p[2] = ri[2] + d * (2.0 * u32_open(B[0]) - 1.0);
+        if (p[0] < 0.0) p[0] += c->lx; else if (p[0] >= c->lx) p[0] -= c->lx;
+        if (p[1] < 0.0) p[1] += c->ly; else if (p[1] >= c->ly) p[1] -= c->ly;
+        if (p[2] < c->zlo || p[2] > c->zhi) { st[ST_WALL_REJ]++; return 0; }
+        if (c->mode == 1) {
+            de = 0.0;
+        } else {
+            double e_new = particle_energy(c, p, xyz, n, i, &core_new);
+            if (core_new) { st[ST_CORE_REJ]++; return 0; }
+            double e_old = particle_energy(c, ri, xyz, n, i, &core_old);
+            de = e_new - e_old;
+        }
+        double x = -beta * de;
+        if (metropolis(x, U)) {
+            memcpy(ri, p, sizeof p);
+            W->e[w] += de;
+            st[ST_DISP_ACC]++;
+            return 1;
+        }
+        return 0;
+    } else if (a0 < th_ins) {
+        /* ---- insertion, Eq. (3) with the corrected exponent ---- */
+        st[ST_INS_ATT]++;
+        if (n >= c->n_max) { st[ST_CAP_REJ]++; return 0; }
+        double p[3];
+        int core = 0, k = -1;
+        if (c->mode == 2) {
+            k = (int)(((uint64_t)A[2] * (uint64_t)c->n_sites) >> 32);
+            if (site_occupied(site, n, k)) return 0;
+            memcpy(p, c->sites + 3 * k, sizeof p);
+        } else {
+            p[0] = c->lx * u32_open(A[2]);
+            p[1] = c->ly * u32_open(A[3]);
+            p[2] = c->zlo + (c->zhi - c->zlo) * u32_open(B[0]);
+        }
+        double de = 0.0;
+        if (c->mode != 1) {
+            de = particle_energy(c, p, xyz, n, -1, &core);
+            if (core && c->mode == 0) { st[ST_CORE_REJ]++; return 0; }
+        }
+        /* ln A = ln z + ln V - ln(N+1) - beta dE  (V -> number of sites in mode 2) */
+        double x = ((lnz + lnv) - lnk[n + 1]) - beta * de;
+        if (metropolis(x, U)) {
+            memcpy(xyz + 3 * n, p, sizeof p);
+            if (site) site[n] = k;
+            W->n[w] = n + 1;
+            W->e[w] += de;
+            st[ST_INS_ACC]++;
+            return 1;
+        }
+        return 0;
+    } else {
+        /* ---- removal, Eq. (2) ---- */
+        st[ST_DEL_ATT]++;
+        if (n == 0) { st[ST_EMPTY_REJ]++; return 0; }
+        int i = (int)(((uint64_t)A[1] * (uint64_t)n) >> 32);
+        double de = 0.0;
+        int core = 0;
+        if (c->mode != 1) de = -particle_energy(c, xyz + 3 * i, xyz, n, i, &core);
+        /* ln A = ln N - ln z - ln V - beta dE,  dE = E_{N-1} - E_N */
+        double x = (lnk[n] - (lnz + lnv)) - beta * de;
+        if (metropolis(x, U)) {
+            /* the removed slot is refilled by the last particle */
+            if (i != n - 1) {
+                memcpy(xyz + 3 * i, xyz + 3 * (n - 1), 3 * sizeof(double));
+                if (site) site[i] = site[n - 1];
+            }
+            W->n[w] = n - 1;
+            W->e[w] += de;
+            st[ST_DEL_ACC]++;
+            return 1;
+        }
+        return 0;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Replica-exchange step                                                     */
+/* ------------------------------------------------------------------------- */
+/* Collective neighbour swaps (Sec. II.A.2).  One of four pair types is drawn
+ * with probability 1/4; all its disjoint pairs are attempted independently.
+ *   scheme 0: type 0 T-pairs (2a,2a+1), type 1 T-pairs (2a+1,2a+2),
+ *             type 2 mu-pairs (2b,2b+1), type 3 mu-pairs (2b+1,2b+2).
+ *   scheme 1: within 2x2 blocks: type 0 along T, type 1 along mu,
+ *             type 2 main diagonal, type 3 anti-diagonal.
+ * Pair acceptance from Eq. (1) of both walkers in both states. */
+static void swap_pair(const orc_config *c, const orc_statec *sc, orc_walkers *W, int64_t q,
+                      int type, int sa, int sb)
+{
+    int S = c->n_t * c->n_mu;
+    int lo = sa < sb ? sa : sb;
+    uint32_t R[4];
+    philox_words(c->seed, (uint32_t)lo, (uint32_t)q, 0xFFFFFFFFu, 4u, R);
+    int i = W->wos[sa], j = W->wos[sb];
+    double x = (sc[sa].beta - sc[sb].beta) * (W->e[i] - W->e[j])
+             + (double)(W->n[j] - W->n[i]) * (sc[sa].lnz - sc[sb].lnz);
+    W->swap_att[(int64_t)type * S + lo]++;
+    if (metropolis(x, u53(R[0], R[1]))) {
+        W->label[i] = sb;
+        W->label[j] = sa;
+        W->wos[sa] = j;
+        W->wos[sb] = i;
+        W->swap_acc[(int64_t)type * S + lo]++;
+    }
+}
+
+static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W, int64_t q)
+{
+    uint32_t R[4];
+    philox_words(c->seed, 0u, (uint32_t)q, 0xFFFFFFFFu, 3u, R);
+    int type = (int)(R[0] >> 30);
+    int L = c->n_t, M = c->n_mu;
+    if (c->swap_scheme == 0) {
+        if (type < 2) {
+            for (int l = type; l + 1 < L; l += 2)
+                for (int m = 0; m < M; ++m) swap_pair(c, sc, W, q, type, l * M + m, (l + 1) * M + m);
+        } else {
+            for (int l = 0; l < L; ++l)
+                for (int m = type - 2; m + 1 < M; m += 2) swap_pair(c, sc, W, q, type, l * M + m, l * M + m + 1);
+        }
+    } else {
+        for (int l = 0; l + 1 < L; l += 2) {
+            for (int m = 0; m + 1 < M; m += 2) {
+                int s00 = l * M + m, s01 = l * M + m + 1, s10 = (l + 1) * M + m, s11 = (l + 1) * M + m + 1;
+                if (type == 0) { swap_pair(c, sc, W, q, type, s00, s10); swap_pair(c, sc, W, q, type, s01, s11); }
+                if (type == 1) { swap_pair(c, sc, W, q, type, s00, s01); swap_pair(c, sc, W, q, type, s10, s11); }
+                if (type == 2) { swap_pair(c, sc, W, q, type, s00, s11); }
+                if (type == 3) { swap_pair(c, sc, W, q, type, s01, s10); }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Driver                                                                    */
+/* ------------------------------------------------------------------------- */
+/* Runs sweeps [*sweep, *sweep + n_sweeps) of the whole REGC simulation.
+ * After every sweep s: samples (E, N, state) of all walkers are appended when
+ * (s+1) % sample_every == 0; then the replica-exchange step q = (s+1)/swap_every - 1
+ * runs when (s+1) % swap_every == 0.
+ * trace_bits: [n_sweeps][S][ceil(K/32)] accept bits (may be NULL);
+ * trace_n:    [n_sweeps][S] N at each sweep end (may be NULL).
+ * Returns 0, or -4 when the sample buffer is too small (nothing is lost: the
+ * run stops before the sweep whose samples would not fit). */
+int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweeps,
+            double *samp_e, int32_t *samp_n, int32_t *samp_s, int64_t samp_cap, int64_t *samp_count,
+            uint32_t *trace_bits, int32_t *trace_n, int n_threads)
+{
+    const int S = c->n_t * c->n_mu;
+    const int K = c->trials_per_sweep > 0 ? c->trials_per_sweep : c->n_max + 1;
+    const int words = (K + 31) / 32;
+    orc_statec *sc = (orc_statec *)malloc(sizeof(orc_statec) * S);
+    double *lnk = (double *)malloc(sizeof(double) * (c->n_max + 2));
+    state_constants(c, sc);
+    lnk[0] = 0.0;
+    for (int k = 1; k <= c->n_max + 1; ++k) lnk[k] = log((double)k);
+    double lnv = (c->mode == 2) ? log((double)c->n_sites)
+                                : log(c->lx * c->ly * (c->zhi - c->zlo));
+    int rc = 0;
+    for (int64_t it = 0; it < n_sweeps; ++it) {
+        const int64_t s = *sweep;
+        if (c->sample_every > 0 && (s + 1) % c->sample_every == 0 && *samp_count + S > samp_cap) {
+            rc = -4;
+            break;
+        }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+        for (int w = 0; w < S; ++w) {
+            uint32_t *bits = trace_bits ? trace_bits + ((int64_t)it * S + w) * words : NULL;
+            if (bits) memset(bits, 0, sizeof(uint32_t) * words);
+            for (int t = 0; t < K; ++t) {
+                int acc = trial(c, sc, lnk, lnv, W, w, s, t);
+                if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
+            }
+            if (trace_n) trace_n[(int64_t)it * S + w] = W->n[w];
+        }
+        if (c->sample_every > 0 && (s + 1) % c->sample_every == 0) {
+            for (int w = 0; w < S; ++w) {
+                samp_e[*samp_count] = W->e[w];
+                samp_n[*samp_count] = W->n[w];
+                samp_s[*samp_count] = W->label[w];
+                (*samp_count)++;
+            }
+        }
+        if (c->swap_every > 0 && (s + 1) % c->swap_every == 0)
+            swap_step(c, sc, W, (s + 1) / c->swap_every - 1);
+        *sweep = s + 1;
+    }
+    free(sc);
+    free(lnk);
+    return rc;
+}
+
+/* Single replica-exchange step, exposed for the detailed-balance tests. */
+void orc_swap_step(const orc_config *c, orc_walkers *W, int64_t q)
+{
+    int S = c->n_t * c->n_mu;
+    orc_statec *sc = (orc_statec *)malloc(sizeof(orc_statec) * S);
+    state_constants(c, sc);
+    swap_step(c, sc, W, q);
+    free(sc);
+}
+
+/* ln of the swap acceptance ratio for walker i (in state a) and walker j (in state b). */
+double orc_swap_lnratio(double beta_a, double lnz_a, double beta_b, double lnz_b,
+                        double e_i, int n_i, double e_j, int n_j)
+{
+    return (beta_a - beta_b) * (e_i - e_j) + (double)(n_j - n_i) * (lnz_a - lnz_b);
+}

@@ -1,0 +1,298 @@
+"""Pins of the CPU oracle against facts fixed outside it: a library Philox, LJ
+closed-form values, brute-force image sums, the ideal-gas Poisson law, the swap
+ratio written from the GC density, exact lattice-gas enumeration and one-particle
+quadrature.  CPU only."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_11118_amd import workloads as W
+from tests.stats_util import (batch_means, energy_image_sum, lj_ts, per_state_series,
+                              truncated_poisson)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND's host engine
+# ---------------------------------------------------------------------------
+def _rocrand_ref(cases, tmp_path):
+    inc = "/opt/rocm/include"
+    if not os.path.exists(os.path.join(inc, "rocrand", "rocrand_philox4x32_10.h")) or not shutil.which("g++"):
+        pytest.skip("rocRAND headers or g++ not available")
+    exe = str(tmp_path / "philox_ref")
+    subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", f"-I{inc}",
+                    os.path.join(HERE, "philox_rocrand_ref.cpp"), "-o", exe], check=True)
+    inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return [list(map(int, line.split())) for line in out.strip().splitlines()]
+
+
+def test_philox_matches_rocrand(tmp_path):
+    rng = np.random.default_rng(7)
+    cases = [(0, 0, 0, 0, 0, 0), (1, 0, 0, 0, 0, 0), (0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0x3FFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF),
+             (1, 0, 5, 123, 0xFFFFFFFF, 3), (1, 0, 40, 9999, 63, 1), (2, 0, 200, 99999, 1023, 0)]
+    for _ in range(20):
+        k = rng.integers(0, 2**32, size=2)
+        c = rng.integers(0, 2**32, size=4)
+        c[1] %= 2**30
+        cases.append(tuple(int(v) for v in (*k, *c)))
+    ref = _rocrand_ref(cases, tmp_path)
+    for case, r in zip(cases, ref):
+        got = oracle.philox4x32_10(case[2:], case[:2])
+        assert list(map(int, got)) == r, case
+
+
+# ---------------------------------------------------------------------------
+# Lennard-Jones pair term (Appendix): textbook values
+# ---------------------------------------------------------------------------
+def test_lj_closed_form():
+    # unshifted: zero at r = sigma, minimum -eps at r = 2^(1/6) sigma
+    assert oracle.lj(1.0, 1.0, 1.0, 2.5, 0) == 0.0
+    assert abs(oracle.lj(2.0 ** (1.0 / 3.0), 1.0, 1.0, 2.5, 0) + 1.0) < 1e-14
+    # value at the cutoff 2.5: 4 (0.4^12 - 0.4^6) = -0.016316891136
+    assert abs(oracle.lj(2.5 ** 2 * (1 - 1e-15), 1.0, 1.0, 2.5, 0) + 0.016316891136) < 1e-12
+    # shifted form vanishes at the cutoff and is 0 beyond it
+    assert abs(oracle.lj(2.5 ** 2 * (1 - 1e-15), 1.0, 1.0, 2.5, 1)) < 1e-12
+    assert oracle.lj(6.25, 1.0, 1.0, 2.5, 1) == 0.0
+    assert oracle.lj(10.0, 1.0, 1.0, 2.5, 1) == 0.0
+    # shifted minimum: -1 + 0.016316891136
+    assert abs(oracle.lj(2.0 ** (1.0 / 3.0), 1.0, 1.0, 2.5, 1) - (-1.0 + 0.016316891136)) < 1e-12
+    # scaling with eps and sigma: phi(r; eps, sig) = eps * phi(r/sig; 1, 1)
+    assert abs(oracle.lj(1.3 ** 2 * 1.2 ** 2, 0.7, 1.2, 2.5 * 1.2, 1) - 0.7 * oracle.lj(1.3 ** 2, 1.0, 1.0, 2.5, 1)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Energies against brute-force image sums
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_total_energy_vs_image_sum(cfg):
+    w = W.config1(10) if cfg == "c1" else W.config2(10)
+    ch = oracle.Chain(w.replace(t=w.t[:1], mu=w.mu[:1]))
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 7, 25):
+        xyz = W.random_configuration(rng, w, n, min_dist=0.8)
+        ref = energy_image_sum(xyz, w.slab, w.lx, w.ly)
+        got = ch.energy(xyz)
+        assert abs(got - ref) <= 1e-11 * (1 + abs(ref)), (n, got, ref)
+
+
+def test_running_energy_matches_recompute():
+    """E is a running total of accepted dE; it must equal a full recompute."""
+    w = W.config1(300)
+    ch = oracle.Chain(w)
+    ch.run(300)
+    assert ch.n.max() > 5
+    for k in range(ch.S):
+        ref = ch.energy(ch.xyz[k, : ch.n[k]])
+        assert abs(ch.e[k] - ref) <= 1e-9 * (1 + abs(ref)), (k, ch.e[k], ref)
+    st = ch.stats.sum(0)
+    # the 50/25/25 move mix of the schedule
+    att = st[[0, 2, 4]].astype(float)
+    assert np.allclose(att / att.sum(), [0.5, 0.25, 0.25], atol=0.01)
+
+
+# ---------------------------------------------------------------------------
+# Ideal gas (eps = 0): Poisson N of mean z V, truncated at n_max
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("swap_every", [0, 10])
+def test_ideal_gas_poisson(swap_every):
+    w = W.ideal_gas(n_sweeps=20000).replace(t=np.array([1.0, 1.5]), mu=np.array([-4.5, -3.5]),
+                                           swap_every=swap_every)
+    ch = oracle.Chain(w)
+    ch.run(2000)
+    out = ch.run(w.n_sweeps)
+    n_ser, _ = per_state_series(out, ch.S)
+    for s in range(ch.S):
+        T, mu = w.t[s // 2], w.mu[s % 2]
+        zv = math.exp(mu / T) * T ** 1.5 * w.volume     # Lambda = 1/sqrt(T)
+        p = truncated_poisson(zv, w.n_max)
+        mean_ref = float((np.arange(w.n_max + 1) * p).sum())
+        m, se = batch_means(n_ser[:, s])
+        assert abs(m - mean_ref) < 4 * se + 1e-9, (s, m, mean_ref, se)
+        hist = np.bincount(n_ser[:, s], minlength=w.n_max + 1)[: w.n_max + 1] / len(n_ser)
+        assert 0.5 * np.abs(hist - p).sum() < 0.03, s
+    if swap_every:
+        att = ch.swap_att.sum()
+        acc = ch.swap_acc.sum()
+        assert att > 0 and 0 < acc < att
+        # states of the product measure are independent
+        rho = np.corrcoef(n_ser[:, 0], n_ser[:, 3])[0, 1]
+        assert abs(rho) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# Replica exchange: the acceptance ratio is the ratio of Eq. (1) densities
+# ---------------------------------------------------------------------------
+def _log_gc_density(beta, mu, lam, V, n, e):
+    """log of Eq. (1): exp(beta mu N) V^N / (Lambda^(3N) N!) exp(-beta E)."""
+    return beta * mu * n + n * math.log(V) - 3 * n * math.log(lam) - math.lgamma(n + 1) - beta * e
+
+
+def test_swap_ratio_is_density_ratio():
+    rng = np.random.default_rng(11)
+    lam1, V = 1.3, 288.0
+    for _ in range(200):
+        Ta, Tb = rng.uniform(0.4, 3.0, 2)
+        mua, mub = rng.uniform(-9, -1, 2)
+        ni, nj = rng.integers(0, 60, 2)
+        ei, ej = rng.uniform(-300, 50, 2)
+        la, lb = lam1 / math.sqrt(Ta), lam1 / math.sqrt(Tb)
+        ref = (_log_gc_density(1 / Ta, mua, la, V, nj, ej) + _log_gc_density(1 / Tb, mub, lb, V, ni, ei)
+               - _log_gc_density(1 / Ta, mua, la, V, ni, ei) - _log_gc_density(1 / Tb, mub, lb, V, nj, ej))
+        za = oracle.state_lnz(Ta, mua, lam1)
+        zb = oracle.state_lnz(Tb, mub, lam1)
+        got = oracle.swap_lnratio(1 / Ta, za, 1 / Tb, zb, ei, ni, ej, nj)
+        assert abs(got - ref) < 1e-9 * (1 + abs(ref))
+        # reverse move has the inverse ratio; equal T removes the Lambda factor
+        back = oracle.swap_lnratio(1 / Ta, za, 1 / Tb, zb, ej, nj, ei, ni)
+        assert abs(got + back) < 1e-9 * (1 + abs(ref))
+    # equal temperature: (beta_l/beta_k)^(3/2 dN) is exactly 1
+    za = oracle.state_lnz(1.0, -3.0, 1.7)
+    zb = oracle.state_lnz(1.0, -2.0, 1.7)
+    assert abs(oracle.swap_lnratio(1.0, za, 1.0, zb, -5.0, 3, -9.0, 7) - 4 * (-1.0)) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_swap_step_pairs_are_neighbours(scheme):
+    w = W.ideal_gas().replace(t=W.linear_grid(0.5, 2.0, 4), mu=W.linear_grid(-8, -2, 6), swap_scheme=scheme)
+    ch = oracle.Chain(w)
+    L, M = 4, 6
+    rng = np.random.default_rng(5)
+    ch.n[:] = rng.integers(0, 10, ch.S)
+    ch.e[:] = rng.uniform(-50, 0, ch.S)
+    seen_types = set()
+    for q in range(64):
+        before = ch.label.copy()
+        att0 = ch.swap_att.copy()
+        ch.swap_step(q)
+        assert sorted(ch.label) == list(range(ch.S))
+        assert np.all(ch.wos[ch.label] == np.arange(ch.S))
+        d = ch.swap_att - att0
+        types = np.nonzero(d.sum(1))[0]
+        assert len(types) == 1
+        t = int(types[0])
+        seen_types.add(t)
+        moved = np.nonzero(before != ch.label)[0]
+        for wk in moved:
+            a, b = before[wk], ch.label[wk]
+            la, ma, lb, mb = a // M, a % M, b // M, b % M
+            assert max(abs(la - lb), abs(ma - mb)) == 1
+            if scheme == 0:
+                assert (la == lb) == (t >= 2)
+        if scheme == 0:
+            expect = {0: (L // 2) * M, 1: ((L - 1) // 2) * M, 2: L * (M // 2), 3: L * ((M - 1) // 2)}[t]
+        else:
+            expect = {0: 2, 1: 2, 2: 1, 3: 1}[t] * (L // 2) * (M // 2)
+        assert d.sum() == expect
+    assert seen_types == {0, 1, 2, 3}
+
+
+# ---------------------------------------------------------------------------
+# Interacting lattice gas: exact enumeration of all 2^M site subsets
+# ---------------------------------------------------------------------------
+def _lattice_setup():
+    box = 6.0
+    slab = W.fcc100_slab(4, 2, box, rc=2.5)
+    sites = W.hollow_sites(4, box, 0.55)
+    M = len(sites)
+    eps_site = np.zeros(M)
+    J = np.zeros((M, M))
+    shifts = np.array([[a * box, b * box, 0.0] for a in (-1, 0, 1) for b in (-1, 0, 1)])
+    for i in range(M):
+        d = sites[i][None, None, :] - (slab[:, None, :] + shifts[None])
+        eps_site[i] = lj_ts((d * d).sum(2), 1.0, 1.0, 2.5).sum()
+        for j in range(M):
+            if i != j:
+                d = sites[i] - (sites[j] + shifts)
+                J[i, j] = lj_ts((d * d).sum(1), 1.0, 1.0, 2.5).sum()
+    return box, slab, sites, eps_site, J
+
+
+def _enumerate(eps_site, J, T, mu):
+    M = len(eps_site)
+    idx = np.arange(2 ** M, dtype=np.int64)
+    bits = ((idx[:, None] >> np.arange(M)) & 1).astype(np.float64)
+    E = bits @ eps_site + 0.5 * np.einsum("ni,ij,nj->n", bits, J, bits)
+    N = bits.sum(1)
+    logw = (mu * N - E) / T
+    logw -= logw.max()
+    p = np.exp(logw)
+    p /= p.sum()
+    pn = np.bincount(N.astype(int), weights=p, minlength=M + 1)
+    return float((p * N).sum()), pn
+
+
+def test_lattice_gas_exact_enumeration():
+    box, slab, sites, eps_site, J = _lattice_setup()
+    assert J.min() < -0.3        # neighbouring sites do interact
+    w = W.Workload(name="lattice", slab=slab, lx=box, ly=box, zlo=0.0, zhi=4.0,
+                   t=np.array([0.8, 1.2]), mu=np.array([-4.2, -3.4]), n_max=len(sites), mode=2,
+                   sites=sites, swap_every=10, n_sweeps=30000)
+    ch = oracle.Chain(w)
+    ch.run(2000)
+    out = ch.run(w.n_sweeps)
+    n_ser, e_ser = per_state_series(out, ch.S)
+    for s in range(ch.S):
+        T, mu = w.t[s // 2], w.mu[s % 2]
+        ref, pn = _enumerate(eps_site, J, T, mu)
+        m, se = batch_means(n_ser[:, s])
+        assert 0.5 < ref < len(sites) - 0.5
+        assert abs(m - ref) < 4 * se + 1e-9, (s, m, ref, se)
+    # the running energies are the lattice-gas energies of the occupied sites
+    for k in range(ch.S):
+        occ = np.zeros(len(sites))
+        occ[ch.site[k, : ch.n[k]]] = 1
+        ref = occ @ eps_site + 0.5 * occ @ J @ occ
+        assert abs(ch.e[k] - ref) < 1e-9 * (1 + abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# One particle in the slab field: <N> = zI/(1+zI), I = int_V exp(-beta U) d^3r
+# ---------------------------------------------------------------------------
+def _slab_integral(slab, box, cell, zlo, zhi, T, rc=2.5, nxy=48, dz=0.005):
+    """Midpoint rule over one surface unit cell (the slab is periodic with `cell`),
+    z from zlo to zlo + rc; above that the integrand is exactly 1."""
+    xs = (np.arange(nxy) + 0.5) * cell / nxy
+    zs = zlo + (np.arange(int(round(rc / dz))) + 0.5) * dz
+    X, Y, Z = np.meshgrid(xs, xs, zs, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    U = np.zeros(len(P))
+    for a in slab:
+        d = P - a
+        d[:, 0] -= box * np.round(d[:, 0] / box)
+        d[:, 1] -= box * np.round(d[:, 1] / box)
+        r2 = (d * d).sum(1)
+        U += lj_ts(np.maximum(r2, 1e-6), 1.0, 1.0, rc)
+    f = np.exp(np.minimum(-U / T, 700.0))
+    ncell = (box / cell) ** 2
+    I_low = f.mean() * cell * cell * rc * ncell
+    return I_low + box * box * (zhi - zlo - rc)
+
+
+@pytest.mark.parametrize("T", [0.7, 1.2])
+def test_single_particle_quadrature(T):
+    box = 6.0
+    slab = W.fcc100_slab(4, 2, box, rc=2.5)
+    I = _slab_integral(slab, box, 1.5, 0.0, 8.0, T)
+    # choose mu so that z I = 1 (<N> = 1/2), z = exp(mu/T) T^1.5
+    mu = T * math.log(1.0 / (I * T ** 1.5))
+    w = W.Workload(name="one", slab=slab, lx=box, ly=box, zlo=0.0, zhi=8.0, t=np.array([T]),
+                   mu=np.array([mu]), n_max=1, swap_every=0, n_sweeps=400000, max_disp=0.4)
+    ch = oracle.Chain(w)
+    out = ch.run(w.n_sweeps)
+    m, se = batch_means(out["n"].astype(float), 40)
+    assert abs(m - 0.5) < 4 * se + 2e-3, (m, se)
+    st = ch.stats.sum(0)
+    assert st[oracle.STAT_NAMES.index("wall_rej")] > 0
+    assert st[oracle.STAT_NAMES.index("cap_rej")] > 0
