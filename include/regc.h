@@ -1,0 +1,283 @@
+/*
+ * regc.h -- C ABI of libregc_hip.so: replica-exchange grand-canonical (REGC)
+ * Metropolis sampling of a Lennard-Jones gas on a frozen LJ slab, and multistate
+ * reweighting of the samples, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhou, Scheffler, Ghiringhelli, "Determining Surface Phase Diagrams
+ * Including Anharmonic Effects", arXiv:1908.11118.  The problem statement the
+ * interface follows (Sec. I and Sec. IV): the inputs are the potential energy
+ * function and the T and mu ranges; the outputs are per-state samples, partition
+ * function estimates (free energies), phase probabilities and the phase map.
+ *
+ * Conventions
+ *  - Reduced LJ units, k_B = 1, beta = 1/T.  Thermal wavelength
+ *    Lambda(T) = lambda1 / sqrt(T) (Sec. II.A.1, Eq. (1)), so the activity of
+ *    state s is ln z_s = beta_s mu_s - 3 ln Lambda(T_s).
+ *  - State grid: state s = l * n_mu + m for temperature T[l] and chemical
+ *    potential mu[m] (Sec. II.A.2, the L x M extended ensemble).
+ *  - A walker w is one configuration slot; label[w] is the state it currently
+ *    samples.  Replica exchange permutes labels, never coordinates.
+ *  - Every pointer argument is a HOST pointer unless its name ends in _dev.
+ *    Inputs are read during the call and copied; the caller keeps ownership.
+ *    Output buffers are allocated by the caller.  The context owns all device
+ *    memory it allocates and frees it in regc_destroy.
+ *  - Every function returns REGC_OK (0) or a negative error code; nothing is
+ *    thrown across the ABI.  regc_last_error() gives a thread-local message
+ *    for the last failure on the calling thread.
+ *  - Work is enqueued on the context's stream (regc_set_stream; default: the
+ *    null stream).  Functions that return data to the host synchronise that
+ *    stream first.  Calls on one context must not overlap.
+ */
+#ifndef REGC_H
+#define REGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define REGC_OK 0
+#define REGC_EINVAL (-1)       /* bad sizes or parameters (see each function) */
+#define REGC_ENOMEM (-2)       /* device or host allocation failed */
+#define REGC_EHIP (-3)         /* a HIP runtime call failed; message has hipGetErrorString */
+#define REGC_ECAPACITY (-4)    /* sample or trace buffer too small; nothing was run */
+#define REGC_ESTATE (-5)       /* call made in the wrong order */
+#define REGC_EUNSUPPORTED (-6) /* option not supported by this build */
+#define REGC_ENOCONV (-7)      /* reweighting did not converge; last iterate returned */
+
+/* ---- enumerations --------------------------------------------------------- */
+#define REGC_MODE_LJ 0     /* LJ gas on a frozen LJ slab */
+#define REGC_MODE_IDEAL 1  /* no interactions (epsilon = 0): ideal gas */
+
+#define REGC_FP64 0        /* all arithmetic in FP64 (trajectory-parity mode) */
+#define REGC_FP32PAIR 1    /* pair terms in FP32; energies, decisions, swaps in FP64 */
+
+/* per-state counters returned by regc_get_stats, REGC_NSTAT per state */
+#define REGC_NSTAT 10
+#define REGC_ST_DISP_ATT 0
+#define REGC_ST_DISP_ACC 1
+#define REGC_ST_INS_ATT 2
+#define REGC_ST_INS_ACC 3
+#define REGC_ST_DEL_ATT 4
+#define REGC_ST_DEL_ACC 5
+#define REGC_ST_CAP_REJ 6    /* insertion attempted at N = n_max */
+#define REGC_ST_EMPTY_REJ 7  /* displacement or removal attempted at N = 0 */
+#define REGC_ST_WALL_REJ 8   /* displacement left the gas region in z */
+#define REGC_ST_CORE_REJ 9   /* new pair closer than hc_frac * sigma */
+
+/* ---- problem description -------------------------------------------------- */
+/* Pair potential (Appendix): phi(r) = 4 eps [(sig/r)^12 - (sig/r)^6], truncated
+ * at rcut and, when shifted != 0, shifted by -phi(rcut).  gg: gas-gas,
+ * gs: gas-slab.  The frozen slab atoms do not interact with each other
+ * (Sec. III.A).  A trial that creates a pair closer than hc_frac * sigma is
+ * rejected without evaluating exp (exact whenever beta*phi(hc_frac*sigma)
+ * exceeds ~745 plus the largest attraction, e.g. hc_frac = 0.5, eps = 1, T <= 2). */
+typedef struct {
+    double eps_gg, sig_gg, eps_gs, sig_gs;
+    double rcut;
+    double hc_frac;
+    int shifted;
+    int mode;            /* REGC_MODE_* */
+} regc_potential;
+
+/* Surface and gas region.  slab_xyz: n_slab x 3 doubles (x, y, z), copied at
+ * create.  Gas region [0,lx) x [0,ly) x [z_lo, z_hi], periodic in x and y,
+ * hard walls in z (Sec. III.A: insertion zone above the topmost surface atoms).
+ * lx and ly must be at least 2*rcut (minimum image).  n_max caps N. */
+typedef struct {
+    int n_slab;
+    const double *slab_xyz;
+    double lx, ly, z_lo, z_hi;
+    double lambda1;
+    int n_max;
+} regc_system;
+
+/* Explicit grid values: T[n_t] > 0, mu[n_mu]. */
+typedef struct {
+    int n_t, n_mu;
+    const double *t, *mu;
+} regc_grid;
+
+/* Schedule and implementation options.
+ *  seed            Philox4x32-10 key (low word, high word).
+ *  precision       REGC_FP64 or REGC_FP32PAIR.
+ *  p_disp, p_ins   move mix; removal gets 1 - p_disp - p_ins.  p_ins must equal
+ *                  the removal probability (detailed balance, Sec. II.A.1).
+ *  max_disp        half-width of the cubic displacement (Sec. II.A.3).
+ *  trials_per_sweep  K trials per sweep, independent of the state; 0 -> n_max+1.
+ *  swap_every      replica-exchange step after every swap_every sweeps (0: never).
+ *  sample_every    record (E, N, state) of all walkers every sample_every sweeps
+ *                  (0: never), before that sweep's exchange step.
+ *  swap_scheme     0: even/odd T pairs and even/odd mu pairs; 1: T, mu and the two
+ *                  diagonals inside 2x2 blocks (four types, p = 1/4 each, Sec. II.A.2).
+ *  sample_capacity samples the context can hold (records x walkers); 0 -> enough
+ *                  for 1024 records.
+ *  trace_capacity  sweeps of accept-bit trace the context can hold (0: no trace).
+ *  walkers_per_block  waves (one walker each) per workgroup, 1..8; 0 -> auto.
+ *  sweeps_per_launch  upper bound of sweeps per kernel launch; 0 -> swap_every.
+ *  slab_bins       -1 off, 1 on, 0 auto: slab atoms sorted into x-y columns no
+ *                  narrower than rcut + max_disp; each trial scans the 3x3 stencil. */
+typedef struct {
+    uint64_t seed;
+    int precision;
+    double p_disp, p_ins, max_disp;
+    int trials_per_sweep;
+    int swap_every, sample_every, swap_scheme;
+    int64_t sample_capacity;
+    int64_t trace_capacity;
+    int walkers_per_block;
+    int sweeps_per_launch;
+    int slab_bins;
+} regc_opts;
+
+typedef struct regc_ctx regc_ctx;
+typedef struct regc_mbar regc_mbar;
+
+/* ---- sampling --------------------------------------------------------------- */
+/* Fills *o with the defaults named above (seed 1, FP64, 0.5/0.25/0.2, ...). */
+void regc_default_opts(regc_opts *o);
+
+/* Creates a context for one REGC simulation on the current HIP device: all
+ * walkers start empty (N = 0, E = 0) with label[w] = w (a reading; the paper
+ * does not state the initial state).  EINVAL on bad sizes, T <= 0, lx or ly
+ * below 2 rcut, p_ins != removal probability, z_hi <= z_lo.
+ * EUNSUPPORTED for an unknown mode or precision. */
+int regc_create(const regc_potential *pot, const regc_system *sys, const regc_grid *grid,
+                const regc_opts *opts, regc_ctx **out);
+
+/* Uneven batch: n_class independent REGC simulations (own slab, box, n_max and
+ * grid each; shared potential and options) advanced by the same kernel launches.
+ * Walkers of class c follow those of class c-1; exchanges stay within a class;
+ * samples are stored per class.  Class c, walker w of that class is global
+ * walker offset_c + w (see regc_get_layout). */
+int regc_create_batch(int n_class, const regc_potential *pot, const regc_system *sys,
+                      const regc_grid *grid, const regc_opts *opts, regc_ctx **out);
+
+/* n_class, and for each class its first global walker and its walker count. */
+int regc_get_layout(const regc_ctx *ctx, int *n_class, int *offsets, int *counts);
+
+/* Work of this context goes to stream (a hipStream_t, e.g. torch's current
+ * stream handle); NULL selects the null stream. */
+int regc_set_stream(regc_ctx *ctx, void *stream);
+
+/* Advances every walker by n_sweeps sweeps (Sec. II.A: GC insertion/removal and
+ * displacement trials, then replica exchange every swap_every sweeps).  Returns
+ * after enqueueing; ECAPACITY (and runs nothing) when the samples or trace of
+ * these sweeps would not fit. */
+int regc_run(regc_ctx *ctx, int64_t n_sweeps);
+
+/* Waits for all enqueued work of the context. */
+int regc_sync(regc_ctx *ctx);
+
+/* Global sweep counter (sweeps done since create or restore). */
+int regc_get_sweep(const regc_ctx *ctx, int64_t *sweep);
+
+/* Walker state: n[W], e[W] (running FP64 total energy), label[W]; xyz may be
+ * NULL, else W x n_max x 3 doubles (rows beyond n[w] are zero). */
+int regc_get_walkers(regc_ctx *ctx, int32_t *n, double *e, int32_t *label, double *xyz);
+
+/* Replaces all walker configurations: n[W], xyz W x n_max x 3.  Energies are
+ * recomputed on the device in the context's precision.  label may be NULL
+ * (unchanged); otherwise it must be a permutation within each class. */
+int regc_set_walkers(regc_ctx *ctx, const int32_t *n, const double *xyz, const int32_t *label);
+
+/* Full recomputation of every walker's energy from its coordinates in the
+ * context's precision (pairs in FP32 or FP64, sums in FP64): e_out[W]. */
+int regc_energies(regc_ctx *ctx, double *e_out);
+
+/* Number of samples held (records x walkers of all classes). */
+int regc_sample_count(const regc_ctx *ctx, int64_t *count);
+
+/* Copies up to cap samples in record order (each record lists all walkers in
+ * walker order): e (FP64 energy), n (particle count), state (label at record
+ * time, within the class).  *n_out receives the number copied. */
+int regc_get_samples(regc_ctx *ctx, double *e, int32_t *n, int32_t *state, int64_t cap,
+                     int64_t *n_out);
+
+/* Device addresses of the sample arrays (valid until destroy or clear). */
+int regc_samples_device(regc_ctx *ctx, const double **e_dev, const int32_t **n_dev,
+                        const int32_t **state_dev, int64_t *count);
+
+/* Drops all stored samples and histograms (the sweep counter is kept). */
+int regc_clear_samples(regc_ctx *ctx);
+
+/* stats: S_total x REGC_NSTAT counters by state; swap_att/swap_acc: 4 x S_total
+ * attempts/acceptances by swap type and lower state of the pair.  S_total is the
+ * total number of states (sum over classes); any pointer may be NULL. */
+int regc_get_stats(regc_ctx *ctx, int64_t *stats, int64_t *swap_att, int64_t *swap_acc);
+
+/* Histogram of recorded N per state: S_total x (n_max_class + 1) counts, classes
+ * concatenated (class c uses its own n_max). */
+int regc_get_histograms(regc_ctx *ctx, int64_t *n_hist);
+
+/* Accept-bit trace of the sweeps run since create/clear_trace:
+ * bits [sweeps][W][ceil(K/32)], n_per_sweep [sweeps][W] (N at each sweep end).
+ * *n_out receives the number of sweeps copied (at most cap_sweeps). */
+int regc_get_trace(regc_ctx *ctx, uint32_t *bits, int32_t *n_per_sweep, int64_t cap_sweeps,
+                   int64_t *n_out);
+
+/* Per-kernel timing with HIP events on the context stream (for benchmarks).
+ * enable != 0 starts recording and resets the totals. */
+int regc_timing_enable(regc_ctx *ctx, int enable);
+/* ms_sweep: summed duration of the sweep-kernel launches, n_sweep: their count;
+ * ms_swap / n_swap the same for exchange launches (any pointer may be NULL). */
+int regc_timing_get(regc_ctx *ctx, double *ms_sweep, int64_t *n_sweep, double *ms_swap,
+                    int64_t *n_swap);
+
+/* Serialises the complete sampling state (walkers, labels, sweep counter,
+ * counters) into buf.  With buf == NULL only *size is set.  Samples and traces
+ * are not included.  restore requires a context created with the same inputs. */
+int regc_checkpoint(regc_ctx *ctx, void *buf, size_t cap, size_t *size);
+int regc_restore(regc_ctx *ctx, const void *buf, size_t size);
+
+void regc_destroy(regc_ctx *ctx);
+
+/* ---- multistate reweighting (Sec. II.B) ------------------------------------ */
+/* A reweighting problem on an n_t x n_mu grid (state s = l*n_mu + m), with
+ * reduced potential u_s(E, N) = beta_s E - N ln z_s (Eq. (8) with the paper's
+ * sign of mu N, plus the Lambda(T) term of Eq. (1)).  n_max bounds N. */
+int regc_mbar_create(const regc_grid *grid, double lambda1, int n_max, regc_mbar **out);
+int regc_mbar_set_stream(regc_mbar *mb, void *stream);
+
+/* Loads ns samples (E, N, state).  With on_device != 0 the three pointers are
+ * device addresses (read during the call); otherwise host.  N outside 0..n_max
+ * or a state outside the grid gives EINVAL. */
+int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e, const int32_t *n,
+                          const int32_t *state, int on_device);
+
+/* Loads the samples of class cls of a sampling context (device to device),
+ * dropping the first skip_records records (burn-in).  The reweighting grid
+ * must be that class's grid.  EINVAL when nothing is left. */
+int regc_mbar_load_run(regc_mbar *mb, regc_ctx *ctx, int cls, int64_t skip_records);
+
+/* Solves the self-consistent equations (Eq. (9)) for the free energies f_s =
+ * -ln c_s of the sampled states, gauge f = 0 at the first sampled state, until
+ * max |delta f| < tol or max_iter iterations.  f_out[S] (unsampled states get
+ * their reweighted value).  iters/delta may be NULL.  ENOCONV if not converged. */
+int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters,
+                    double *delta);
+
+/* Reweighted averages on a target grid (Eq. (9) at new states and Eq. (10)/(11)):
+ * f[t] = -ln c_t, mean_n, mean_e, mean_e2 (for C = beta^2 var E), p_n [t][n_max+1]
+ * = probability of each N (phase), phase[t] = most probable N (smallest on ties).
+ * t = l*n_mu' + m over the target grid.  Any output may be NULL except mean_n. */
+int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
+                      double *mean_e, double *mean_e2, double *p_n, int32_t *phase);
+
+/* Timing of the last solve: milliseconds in the iteration kernels and their
+ * iteration count. */
+int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter);
+
+void regc_mbar_destroy(regc_mbar *mb);
+
+/* ---- errors ---------------------------------------------------------------- */
+const char *regc_strerror(int code);
+const char *regc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REGC_H */

@@ -1,0 +1,872 @@
+// api.cpp -- host runtime of libregc_hip.so: contexts, launch schedule of the
+// sweep and exchange kernels, sample/trace/counter buffers, checkpointing.
+// The public contract is include/regc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_util.h"
+#include "regc_dev.h"
+
+namespace regc {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+struct ClassHost {
+    regc_system sys;
+    std::vector<double> slab, t, mu;
+    int S = 0, off = 0, K = 0;
+    int bins = 0, ncx = 1, ncy = 1, cap = 0;
+    std::vector<double> packed;   // xyz of the packed (binned or plain) slab, 3 per entry
+    std::vector<int16_t> stencil;
+};
+
+struct TimingPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace regc
+
+using namespace regc;
+
+struct regc_ctx {
+    regc_potential pot{};
+    regc_opts opts{};
+    std::vector<ClassHost> cls;
+    int W = 0, nmax_all = 0, kmax = 0, words = 1;
+    PotDev potd{};
+    hipStream_t stream = nullptr;
+    int wpb = 1, nblocks = 0, max_slab_len = 0, max_stencil = 0;
+    size_t smem = 0;
+
+    DevBuf<ClassDev> cls_d;
+    DevBuf<int> block_class_d, block_w0_d, block_nw_d, walker_class_d, unb_off_d, unb_len_d;
+    DevBuf<int32_t> n_d, label_d, wos_d;
+    DevBuf<double> e_d, xyz_d, beta_d, lnz_d, lnk_d, slab4_d, unb_d;
+    DevBuf<float> slab4f_d;
+    DevBuf<int16_t> stencil_d;
+    DevBuf<double> samp_e;
+    DevBuf<int32_t> samp_n, samp_s;
+    int64_t rec_cap = 0, rec_base = 0, n_rec = 0;
+    DevBuf<unsigned long long> hist_d, stats_d, att_d, acc_d;
+    DevBuf<uint32_t> trace_bits_d;
+    DevBuf<int32_t> trace_n_d;
+    int64_t trace_cap = 0, trace_sweep0 = 0;
+    int64_t sweep = 0;
+    std::vector<int> walker_class;
+
+    bool timing = false;
+    std::vector<TimingPair> ev_sweep, ev_swap;
+
+    ~regc_ctx()
+    {
+        for (auto &p : ev_sweep) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (auto &p : ev_swap) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    }
+};
+
+// ---------------------------------------------------------------------------
+extern "C" const char *regc_last_error(void) { return g_err; }
+
+extern "C" const char *regc_strerror(int code)
+{
+    switch (code) {
+    case REGC_OK: return "ok";
+    case REGC_EINVAL: return "invalid argument";
+    case REGC_ENOMEM: return "out of memory";
+    case REGC_EHIP: return "HIP runtime error";
+    case REGC_ECAPACITY: return "buffer capacity exceeded";
+    case REGC_ESTATE: return "call made in the wrong order";
+    case REGC_EUNSUPPORTED: return "unsupported option";
+    case REGC_ENOCONV: return "reweighting did not converge";
+    default: return "unknown error";
+    }
+}
+
+extern "C" void regc_default_opts(regc_opts *o)
+{
+    std::memset(o, 0, sizeof *o);
+    o->seed = 1;
+    o->precision = REGC_FP64;
+    o->p_disp = 0.5;
+    o->p_ins = 0.25;
+    o->max_disp = 0.2;
+    o->trials_per_sweep = 0;
+    o->swap_every = 10;
+    o->sample_every = 1;
+    o->swap_scheme = 0;
+    o->sample_capacity = 0;
+    o->trace_capacity = 0;
+    o->walkers_per_block = 0;
+    o->sweeps_per_launch = 0;
+    o->slab_bins = 0;
+}
+
+static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
+{
+    REGC_CHECK(pot && sys && grid && o, REGC_EINVAL, "null argument");
+    REGC_CHECK(pot->mode == REGC_MODE_LJ || pot->mode == REGC_MODE_IDEAL, REGC_EUNSUPPORTED,
+               "unsupported potential mode %d", pot->mode);
+    REGC_CHECK(o->precision == REGC_FP64 || o->precision == REGC_FP32PAIR, REGC_EUNSUPPORTED,
+               "unsupported precision %d", o->precision);
+    REGC_CHECK(pot->rcut > 0 && pot->sig_gg > 0 && pot->sig_gs > 0 && pot->hc_frac >= 0, REGC_EINVAL,
+               "rcut and sigmas must be positive");
+    REGC_CHECK(grid->n_t > 0 && grid->n_mu > 0 && grid->t && grid->mu, REGC_EINVAL, "empty state grid");
+    for (int l = 0; l < grid->n_t; ++l) REGC_CHECK(grid->t[l] > 0, REGC_EINVAL, "T must be positive");
+    REGC_CHECK(sys->n_max >= 1 && sys->n_max <= 4095, REGC_EINVAL, "n_max must be in 1..4095");
+    REGC_CHECK(sys->lx >= 2 * pot->rcut && sys->ly >= 2 * pot->rcut, REGC_EINVAL, "lx, ly must be >= 2 rcut");
+    REGC_CHECK(sys->z_hi > sys->z_lo, REGC_EINVAL, "z_hi must exceed z_lo");
+    REGC_CHECK(sys->lambda1 > 0, REGC_EINVAL, "lambda1 must be positive");
+    REGC_CHECK(sys->n_slab >= 0 && (sys->n_slab == 0 || sys->slab_xyz), REGC_EINVAL, "slab coordinates missing");
+    REGC_CHECK(o->p_disp >= 0 && o->p_ins >= 0 && o->p_disp + o->p_ins <= 1.0, REGC_EINVAL, "bad move mix");
+    REGC_CHECK(std::fabs(o->p_ins - (1.0 - o->p_disp - o->p_ins)) < 1e-12, REGC_EINVAL,
+               "insertion and removal probabilities must be equal");
+    REGC_CHECK(o->max_disp >= 0 && o->max_disp < 0.5 * std::min(sys->lx, sys->ly), REGC_EINVAL, "bad max_disp");
+    REGC_CHECK(o->swap_every >= 0 && o->sample_every >= 0 && o->trials_per_sweep >= 0, REGC_EINVAL,
+               "negative schedule value");
+    REGC_CHECK(o->swap_scheme == 0 || o->swap_scheme == 1, REGC_EUNSUPPORTED, "unknown swap scheme");
+    REGC_CHECK(o->walkers_per_block >= 0 && o->walkers_per_block <= kMaxWalkersPerBlock, REGC_EINVAL,
+               "walkers_per_block must be 0..%d", kMaxWalkersPerBlock);
+    return REGC_OK;
+}
+
+static void pack_slab(ClassHost &c, const regc_potential *pot, const regc_opts *o)
+{
+    const int ns = c.sys.n_slab;
+    const double lx = c.sys.lx, ly = c.sys.ly;
+    const int ncx = (int)std::floor(lx / (pot->rcut + o->max_disp));
+    const int ncy = (int)std::floor(ly / (pot->rcut + o->max_disp));
+    const bool bins = ns > 0 && ncx >= 3 && ncy >= 3 && o->slab_bins >= 0;
+    c.bins = bins ? 1 : 0;
+    c.packed.clear();
+    c.stencil.clear();
+    if (!bins) {
+        c.ncx = c.ncy = 1;
+        c.cap = ns;
+        c.packed = c.slab;
+        return;
+    }
+    c.ncx = ncx;
+    c.ncy = ncy;
+    const double cwx = lx / ncx, cwy = ly / ncy;
+    std::vector<std::vector<int>> col(ncx * ncy);
+    for (int a = 0; a < ns; ++a) {
+        double x = std::fmod(c.slab[3 * a], lx), y = std::fmod(c.slab[3 * a + 1], ly);
+        if (x < 0) x += lx;
+        if (y < 0) y += ly;
+        int cx = std::min(ncx - 1, std::max(0, (int)(x / cwx)));
+        int cy = std::min(ncy - 1, std::max(0, (int)(y / cwy)));
+        col[cy * ncx + cx].push_back(a);
+    }
+    int cap = 1;
+    for (auto &v : col) cap = std::max(cap, (int)v.size());
+    c.cap = cap;
+    c.packed.assign((size_t)ncx * ncy * cap * 3, 0.0);
+    for (int k = 0; k < ncx * ncy; ++k)
+        for (int j = 0; j < cap; ++j) {
+            double *d = &c.packed[((size_t)k * cap + j) * 3];
+            if (j < (int)col[k].size()) {
+                const int a = col[k][j];
+                d[0] = c.slab[3 * a]; d[1] = c.slab[3 * a + 1]; d[2] = c.slab[3 * a + 2];
+            } else {
+                d[0] = 0.0; d[1] = 0.0; d[2] = -1.0e4;   // padding, beyond any cutoff
+            }
+        }
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int cx = 0; cx < ncx; ++cx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    c.stencil.push_back((int16_t)(((cy + dy + ncy) % ncy) * ncx + (cx + dx + ncx) % ncx));
+}
+
+static int upload(void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return REGC_OK;
+    REGC_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return REGC_OK;
+}
+
+static int ctx_alloc_and_init(regc_ctx *c)
+{
+    const regc_opts &o = c->opts;
+    int rc;
+    int W = 0, kmax = 0, nmax = 0, n_class = (int)c->cls.size();
+    for (auto &k : c->cls) {
+        k.off = W;
+        k.S = (int)(k.t.size() * k.mu.size());
+        k.K = o.trials_per_sweep > 0 ? o.trials_per_sweep : k.sys.n_max + 1;
+        W += k.S;
+        kmax = std::max(kmax, k.K);
+        nmax = std::max(nmax, k.sys.n_max);
+        pack_slab(k, &c->pot, &o);
+    }
+    c->W = W;
+    c->kmax = kmax;
+    c->nmax_all = nmax;
+    c->words = (kmax + 31) / 32;
+
+    // potential constants (same arithmetic order as the definitions in regc.h)
+    const regc_potential &p = c->pot;
+    PotDev &pd = c->potd;
+    auto shift = [&](double eps, double sig) {
+        if (!p.shifted) return 0.0;
+        const double c2 = (sig * sig) / (p.rcut * p.rcut);
+        const double c6 = c2 * c2 * c2;
+        return 4.0 * eps * (c6 * c6 - c6);
+    };
+    pd.sig2_gg = p.sig_gg * p.sig_gg; pd.eps4_gg = 4.0 * p.eps_gg; pd.shift_gg = shift(p.eps_gg, p.sig_gg);
+    pd.sig2_gs = p.sig_gs * p.sig_gs; pd.eps4_gs = 4.0 * p.eps_gs; pd.shift_gs = shift(p.eps_gs, p.sig_gs);
+    pd.rc2 = p.rcut * p.rcut;
+    pd.hc2_gg = (p.hc_frac * p.sig_gg) * (p.hc_frac * p.sig_gg);
+    pd.hc2_gs = (p.hc_frac * p.sig_gs) * (p.hc_frac * p.sig_gs);
+    pd.ideal = p.mode == REGC_MODE_IDEAL;
+
+    // per-class device constants, packed slabs, stencils
+    std::vector<ClassDev> cd(n_class);
+    std::vector<double> slab4, unb4;
+    std::vector<float> slab4f;
+    std::vector<int16_t> stencil;
+    std::vector<int> unb_off(n_class), unb_len(n_class);
+    int max_slab_len = 0, max_stencil = 0;
+    for (int k = 0; k < n_class; ++k) {
+        ClassHost &h = c->cls[k];
+        ClassDev &d = cd[k];
+        d.lx = h.sys.lx; d.ly = h.sys.ly; d.zlo = h.sys.z_lo; d.zhi = h.sys.z_hi;
+        d.half_lx = 0.5 * h.sys.lx; d.half_ly = 0.5 * h.sys.ly;
+        d.inv_lx = 1.0 / h.sys.lx; d.inv_ly = 1.0 / h.sys.ly;
+        d.lnv = std::log(h.sys.lx * h.sys.ly * (h.sys.z_hi - h.sys.z_lo));
+        double top = -1.0e30;
+        for (int a = 0; a < h.sys.n_slab; ++a) top = std::max(top, h.slab[3 * a + 2]);
+        d.slab_top = top;
+        d.n_max = h.sys.n_max;
+        d.trials = h.K;
+        d.walker_off = h.off; d.n_walkers = h.S; d.state_off = h.off;
+        d.n_t = (int)h.t.size(); d.n_mu = (int)h.mu.size();
+        const int len = (int)(h.packed.size() / 3);
+        d.slab_off = (int)(slab4.size() / 4);
+        d.slab_len = len;
+        for (int j = 0; j < len; ++j) {
+            for (int q = 0; q < 3; ++q) { slab4.push_back(h.packed[3 * j + q]); slab4f.push_back((float)h.packed[3 * j + q]); }
+            slab4.push_back(0.0);
+            slab4f.push_back(0.f);
+        }
+        unb_off[k] = (int)(unb4.size() / 4);
+        unb_len[k] = h.sys.n_slab;
+        for (int j = 0; j < h.sys.n_slab; ++j) {
+            for (int q = 0; q < 3; ++q) unb4.push_back(h.slab[3 * j + q]);
+            unb4.push_back(0.0);
+        }
+        d.bins = h.bins; d.ncx = h.ncx; d.ncy = h.ncy; d.cap = h.cap;
+        d.inv_cw_x = h.bins ? h.ncx / h.sys.lx : 0.0;
+        d.inv_cw_y = h.bins ? h.ncy / h.sys.ly : 0.0;
+        d.stencil_off = (int)stencil.size();
+        stencil.insert(stencil.end(), h.stencil.begin(), h.stencil.end());
+        max_slab_len = std::max(max_slab_len, len);
+        max_stencil = std::max(max_stencil, (int)h.stencil.size());
+    }
+    c->max_slab_len = max_slab_len;
+    c->max_stencil = max_stencil;
+
+    // launch shape: walkers per block, LDS
+    int dev = 0;
+    REGC_HIP(hipGetDevice(&dev));
+    int lds_max = 0;
+    REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t real4 = o.precision == REGC_FP64 ? 32 : 16;
+    auto smem_for = [&](int wpb) {
+        return (size_t)max_slab_len * real4 + (((size_t)max_stencil * 2 + 31) & ~(size_t)31) +
+               (size_t)wpb * nmax * real4;
+    };
+    int wpb = o.walkers_per_block;
+    if (wpb == 0) wpb = W >= 1024 ? 4 : 1;
+    while (wpb > 1 && smem_for(wpb) > (size_t)lds_max) --wpb;
+    REGC_CHECK(smem_for(wpb) <= (size_t)lds_max, REGC_EUNSUPPORTED,
+               "one walker needs %zu bytes of LDS, the device allows %d", smem_for(wpb), lds_max);
+    c->wpb = wpb;
+    c->smem = smem_for(wpb);
+    std::vector<int> bcls, bw0, bnw;
+    c->walker_class.assign(W, 0);
+    for (int k = 0; k < n_class; ++k) {
+        const ClassHost &h = c->cls[k];
+        for (int w = 0; w < h.S; w += wpb) {
+            bcls.push_back(k);
+            bw0.push_back(h.off + w);
+            bnw.push_back(std::min(wpb, h.S - w));
+        }
+        for (int w = 0; w < h.S; ++w) c->walker_class[h.off + w] = k;
+    }
+    c->nblocks = (int)bcls.size();
+
+    // state constants: ln z = beta mu - 3 ln(lambda1 / sqrt(T))
+    std::vector<double> beta(W), lnz(W);
+    std::vector<int32_t> label(W), wos(W);
+    for (auto &h : c->cls) {
+        const int M = (int)h.mu.size();
+        for (int l = 0; l < (int)h.t.size(); ++l)
+            for (int m = 0; m < M; ++m) {
+                const double T = h.t[l];
+                const double b = 1.0 / T;
+                beta[h.off + l * M + m] = b;
+                lnz[h.off + l * M + m] = b * h.mu[m] - 3.0 * std::log(h.sys.lambda1 / std::sqrt(T));
+            }
+        for (int w = 0; w < h.S; ++w) { label[h.off + w] = w; wos[h.off + w] = h.off + w; }
+    }
+    std::vector<double> lnk(nmax + 2);
+    lnk[0] = 0.0;
+    for (int k = 1; k <= nmax + 1; ++k) lnk[k] = std::log((double)k);
+
+    const int64_t rec_cap = o.sample_every > 0 ? std::max<int64_t>(1, o.sample_capacity > 0 ? o.sample_capacity / W : 1024) : 0;
+    c->rec_cap = rec_cap;
+    c->trace_cap = o.trace_capacity;
+
+    if ((rc = c->cls_d.alloc(n_class)) || (rc = c->block_class_d.alloc(c->nblocks)) ||
+        (rc = c->block_w0_d.alloc(c->nblocks)) || (rc = c->block_nw_d.alloc(c->nblocks)) ||
+        (rc = c->walker_class_d.alloc(W)) || (rc = c->unb_off_d.alloc(n_class)) || (rc = c->unb_len_d.alloc(n_class)) ||
+        (rc = c->n_d.alloc(W)) || (rc = c->label_d.alloc(W)) || (rc = c->wos_d.alloc(W)) || (rc = c->e_d.alloc(W)) ||
+        (rc = c->xyz_d.alloc((size_t)W * nmax * 3)) || (rc = c->beta_d.alloc(W)) || (rc = c->lnz_d.alloc(W)) ||
+        (rc = c->lnk_d.alloc(nmax + 2)) || (rc = c->slab4_d.alloc(slab4.size())) ||
+        (rc = c->slab4f_d.alloc(slab4f.size())) || (rc = c->unb_d.alloc(unb4.size())) ||
+        (rc = c->stencil_d.alloc(stencil.size())) || (rc = c->samp_e.alloc((size_t)rec_cap * W)) ||
+        (rc = c->samp_n.alloc((size_t)rec_cap * W)) || (rc = c->samp_s.alloc((size_t)rec_cap * W)) ||
+        (rc = c->hist_d.alloc((size_t)W * (nmax + 1))) || (rc = c->stats_d.alloc((size_t)W * kNStat)) ||
+        (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) ||
+        (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
+        (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)))
+        return rc;
+    if ((rc = upload(c->cls_d.p, cd.data(), sizeof(ClassDev) * n_class)) ||
+        (rc = upload(c->block_class_d.p, bcls.data(), sizeof(int) * bcls.size())) ||
+        (rc = upload(c->block_w0_d.p, bw0.data(), sizeof(int) * bw0.size())) ||
+        (rc = upload(c->block_nw_d.p, bnw.data(), sizeof(int) * bnw.size())) ||
+        (rc = upload(c->walker_class_d.p, c->walker_class.data(), sizeof(int) * W)) ||
+        (rc = upload(c->unb_off_d.p, unb_off.data(), sizeof(int) * n_class)) ||
+        (rc = upload(c->unb_len_d.p, unb_len.data(), sizeof(int) * n_class)) ||
+        (rc = upload(c->label_d.p, label.data(), sizeof(int32_t) * W)) ||
+        (rc = upload(c->wos_d.p, wos.data(), sizeof(int32_t) * W)) ||
+        (rc = upload(c->beta_d.p, beta.data(), sizeof(double) * W)) ||
+        (rc = upload(c->lnz_d.p, lnz.data(), sizeof(double) * W)) ||
+        (rc = upload(c->lnk_d.p, lnk.data(), sizeof(double) * lnk.size())) ||
+        (rc = upload(c->slab4_d.p, slab4.data(), sizeof(double) * slab4.size())) ||
+        (rc = upload(c->slab4f_d.p, slab4f.data(), sizeof(float) * slab4f.size())) ||
+        (rc = upload(c->unb_d.p, unb4.data(), sizeof(double) * unb4.size())) ||
+        (rc = upload(c->stencil_d.p, stencil.data(), sizeof(int16_t) * stencil.size())))
+        return rc;
+    REGC_HIP(hipMemset(c->n_d.p, 0, sizeof(int32_t) * W));
+    REGC_HIP(hipMemset(c->e_d.p, 0, sizeof(double) * W));
+    REGC_HIP(hipMemset(c->xyz_d.p, 0, sizeof(double) * (size_t)W * nmax * 3));
+    REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * (size_t)W * (nmax + 1)));
+    REGC_HIP(hipMemset(c->stats_d.p, 0, sizeof(unsigned long long) * (size_t)W * kNStat));
+    REGC_HIP(hipMemset(c->att_d.p, 0, sizeof(unsigned long long) * 4 * W));
+    REGC_HIP(hipMemset(c->acc_d.p, 0, sizeof(unsigned long long) * 4 * W));
+    REGC_HIP(hipDeviceSynchronize());
+    return REGC_OK;
+}
+
+static int create_common(int n_class, const regc_potential *pot, const regc_system *sys, const regc_grid *grid,
+                         const regc_opts *opts, regc_ctx **out)
+{
+    REGC_CHECK(out, REGC_EINVAL, "null output pointer");
+    REGC_CHECK(n_class >= 1, REGC_EINVAL, "need at least one class");
+    *out = nullptr;
+    for (int k = 0; k < n_class; ++k) {
+        int rc = validate(pot, sys + k, grid + k, opts);
+        if (rc) return rc;
+    }
+    regc_ctx *c = new regc_ctx();
+    c->pot = *pot;
+    c->opts = *opts;
+    for (int k = 0; k < n_class; ++k) {
+        ClassHost h;
+        h.sys = sys[k];
+        h.slab.assign(sys[k].slab_xyz, sys[k].slab_xyz + 3 * (size_t)sys[k].n_slab);
+        h.sys.slab_xyz = nullptr;
+        h.t.assign(grid[k].t, grid[k].t + grid[k].n_t);
+        h.mu.assign(grid[k].mu, grid[k].mu + grid[k].n_mu);
+        c->cls.push_back(std::move(h));
+    }
+    int rc = ctx_alloc_and_init(c);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return REGC_OK;
+}
+
+extern "C" int regc_create(const regc_potential *pot, const regc_system *sys, const regc_grid *grid,
+                           const regc_opts *opts, regc_ctx **out)
+{
+    return create_common(1, pot, sys, grid, opts, out);
+}
+
+extern "C" int regc_create_batch(int n_class, const regc_potential *pot, const regc_system *sys,
+                                 const regc_grid *grid, const regc_opts *opts, regc_ctx **out)
+{
+    REGC_CHECK(sys && grid, REGC_EINVAL, "null argument");
+    return create_common(n_class, pot, sys, grid, opts, out);
+}
+
+extern "C" int regc_get_layout(const regc_ctx *c, int *n_class, int *offsets, int *counts)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    if (n_class) *n_class = (int)c->cls.size();
+    for (size_t k = 0; k < c->cls.size(); ++k) {
+        if (offsets) offsets[k] = c->cls[k].off;
+        if (counts) counts[k] = c->cls[k].S;
+    }
+    return REGC_OK;
+}
+
+extern "C" int regc_set_stream(regc_ctx *c, void *stream)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    c->stream = (hipStream_t)stream;
+    return REGC_OK;
+}
+
+static int record_event(regc_ctx *c, std::vector<TimingPair> &v, bool start)
+{
+    if (start) {
+        TimingPair p;
+        REGC_HIP(hipEventCreate(&p.a));
+        REGC_HIP(hipEventCreate(&p.b));
+        REGC_HIP(hipEventRecord(p.a, c->stream));
+        v.push_back(p);
+    } else {
+        REGC_HIP(hipEventRecord(v.back().b, c->stream));
+    }
+    return REGC_OK;
+}
+
+static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
+{
+    SweepArgs a{};
+    a.cls = c->cls_d.p;
+    a.block_class = c->block_class_d.p;
+    a.block_w0 = c->block_w0_d.p;
+    a.block_nw = c->block_nw_d.p;
+    a.n_walkers = c->W;
+    a.pot = c->potd;
+    a.n = c->n_d.p;
+    a.e = c->e_d.p;
+    a.label = c->label_d.p;
+    a.xyz = c->xyz_d.p;
+    a.xyz_stride = c->nmax_all;
+    a.beta = c->beta_d.p;
+    a.lnz = c->lnz_d.p;
+    a.lnk = c->lnk_d.p;
+    a.slab4 = c->slab4_d.p;
+    a.slab4f = c->slab4f_d.p;
+    a.stencil = c->stencil_d.p;
+    a.key0 = (uint32_t)c->opts.seed;
+    a.key1 = (uint32_t)(c->opts.seed >> 32);
+    a.th_disp = (uint64_t)std::llround(c->opts.p_disp * 4294967296.0);
+    a.th_ins = a.th_disp + (uint64_t)std::llround(c->opts.p_ins * 4294967296.0);
+    a.max_disp = c->opts.max_disp;
+    a.sweep0 = sweep0;
+    a.n_sweeps = n;
+    a.sample_every = c->opts.sample_every;
+    a.rec_base = c->rec_base;
+    a.samp_e = c->samp_e.p;
+    a.samp_n = c->samp_n.p;
+    a.samp_s = c->samp_s.p;
+    a.hist = c->hist_d.p;
+    a.hist_stride = c->nmax_all + 1;
+    a.stats = c->stats_d.p;
+    a.trace_bits = c->trace_cap > 0 ? c->trace_bits_d.p : nullptr;
+    a.trace_n = c->trace_cap > 0 ? c->trace_n_d.p : nullptr;
+    a.trace_sweep0 = c->trace_sweep0;
+    a.trace_cap = c->trace_cap;
+    a.trace_words = c->words;
+    a.max_slab_len = c->max_slab_len;
+    a.max_stencil = c->max_stencil;
+    a.gas_stride = c->nmax_all;
+    int rc;
+    if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
+    if (c->opts.precision == REGC_FP64)
+        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb, c->smem, c->stream));
+    else
+        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb, c->smem, c->stream));
+    if (c->timing && (rc = record_event(c, c->ev_sweep, false))) return rc;
+    return REGC_OK;
+}
+
+static int launch_exchange(regc_ctx *c, int64_t q)
+{
+    SwapArgs a{};
+    a.cls = c->cls_d.p;
+    a.label = c->label_d.p;
+    a.wos = c->wos_d.p;
+    a.n = c->n_d.p;
+    a.e = c->e_d.p;
+    a.beta = c->beta_d.p;
+    a.lnz = c->lnz_d.p;
+    a.key0 = (uint32_t)c->opts.seed;
+    a.key1 = (uint32_t)(c->opts.seed >> 32);
+    a.q = q;
+    a.scheme = c->opts.swap_scheme;
+    a.att = c->att_d.p;
+    a.acc = c->acc_d.p;
+    a.S_total = c->W;
+    int rc;
+    if (c->timing && (rc = record_event(c, c->ev_swap, true))) return rc;
+    REGC_HIP(launch_swap(a, (int)c->cls.size(), c->stream));
+    if (c->timing && (rc = record_event(c, c->ev_swap, false))) return rc;
+    return REGC_OK;
+}
+
+extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_CHECK(n_sweeps >= 0, REGC_EINVAL, "negative sweep count");
+    const regc_opts &o = c->opts;
+    if (o.sample_every > 0) {
+        const int64_t recs = (c->sweep + n_sweeps) / o.sample_every - c->sweep / o.sample_every;
+        REGC_CHECK(c->n_rec + recs <= c->rec_cap, REGC_ECAPACITY,
+                   "samples of %lld more records do not fit (%lld of %lld held)", (long long)recs,
+                   (long long)c->n_rec, (long long)c->rec_cap);
+    }
+    if (c->trace_cap > 0)
+        REGC_CHECK(c->sweep + n_sweeps - c->trace_sweep0 <= c->trace_cap, REGC_ECAPACITY,
+                   "trace capacity of %lld sweeps exceeded", (long long)c->trace_cap);
+    int64_t left = n_sweeps;
+    while (left > 0) {
+        int64_t chunk = left;
+        if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
+        const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
+        chunk = std::min<int64_t>(chunk, spl);
+        int rc = launch_sweeps(c, c->sweep, (int)chunk);
+        if (rc) return rc;
+        c->sweep += chunk;
+        left -= chunk;
+        if (o.swap_every > 0 && c->sweep % o.swap_every == 0) {
+            rc = launch_exchange(c, c->sweep / o.swap_every - 1);
+            if (rc) return rc;
+        }
+    }
+    if (o.sample_every > 0) c->n_rec = c->sweep / o.sample_every - c->rec_base;
+    return REGC_OK;
+}
+
+extern "C" int regc_sync(regc_ctx *c)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    return REGC_OK;
+}
+
+extern "C" int regc_get_sweep(const regc_ctx *c, int64_t *sweep)
+{
+    REGC_CHECK(c && sweep, REGC_EINVAL, "null argument");
+    *sweep = c->sweep;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_walkers(regc_ctx *c, int32_t *n, double *e, int32_t *label, double *xyz)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (n) REGC_HIP(hipMemcpy(n, c->n_d.p, sizeof(int32_t) * c->W, hipMemcpyDeviceToHost));
+    if (e) REGC_HIP(hipMemcpy(e, c->e_d.p, sizeof(double) * c->W, hipMemcpyDeviceToHost));
+    if (label) REGC_HIP(hipMemcpy(label, c->label_d.p, sizeof(int32_t) * c->W, hipMemcpyDeviceToHost));
+    if (xyz) {
+        REGC_HIP(hipMemcpy(xyz, c->xyz_d.p, sizeof(double) * (size_t)c->W * c->nmax_all * 3, hipMemcpyDeviceToHost));
+        std::vector<int32_t> nn(c->W);
+        REGC_HIP(hipMemcpy(nn.data(), c->n_d.p, sizeof(int32_t) * c->W, hipMemcpyDeviceToHost));
+        for (int w = 0; w < c->W; ++w)
+            std::fill(xyz + ((size_t)w * c->nmax_all + nn[w]) * 3, xyz + ((size_t)w + 1) * c->nmax_all * 3, 0.0);
+    }
+    return REGC_OK;
+}
+
+static int run_energy(regc_ctx *c, double *e_dev)
+{
+    EnergyArgs a{};
+    a.cls = c->cls_d.p;
+    a.walker_class = c->walker_class_d.p;
+    a.n_walkers = c->W;
+    a.pot = c->potd;
+    a.n = c->n_d.p;
+    a.xyz = c->xyz_d.p;
+    a.xyz_stride = c->nmax_all;
+    a.slab4 = c->unb_d.p;
+    a.unb_off = c->unb_off_d.p;
+    a.unb_len = c->unb_len_d.p;
+    a.e_out = e_dev;
+    if (c->opts.precision == REGC_FP64)
+        REGC_HIP(launch_energy_f64(a, c->stream));
+    else
+        REGC_HIP(launch_energy_f32(a, c->stream));
+    return REGC_OK;
+}
+
+extern "C" int regc_set_walkers(regc_ctx *c, const int32_t *n, const double *xyz, const int32_t *label)
+{
+    REGC_CHECK(c && n && xyz, REGC_EINVAL, "null argument");
+    for (int w = 0; w < c->W; ++w) {
+        const ClassHost &h = c->cls[c->walker_class[w]];
+        REGC_CHECK(n[w] >= 0 && n[w] <= h.sys.n_max, REGC_EINVAL, "walker %d: N out of range", w);
+        for (int k = 0; k < n[w]; ++k) {
+            const double *p = xyz + ((size_t)w * c->nmax_all + k) * 3;
+            REGC_CHECK(p[0] >= 0 && p[0] <= h.sys.lx && p[1] >= 0 && p[1] <= h.sys.ly && p[2] >= h.sys.z_lo &&
+                           p[2] <= h.sys.z_hi,
+                       REGC_EINVAL, "walker %d particle %d outside the gas region", w, k);
+        }
+    }
+    std::vector<int32_t> wos;
+    if (label) {
+        wos.assign(c->W, -1);
+        for (auto &h : c->cls)
+            for (int w = 0; w < h.S; ++w) {
+                const int s = label[h.off + w];
+                REGC_CHECK(s >= 0 && s < h.S && wos[h.off + s] < 0, REGC_EINVAL, "labels are not a permutation");
+                wos[h.off + s] = h.off + w;
+            }
+    }
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy(c->n_d.p, n, sizeof(int32_t) * c->W, hipMemcpyHostToDevice));
+    REGC_HIP(hipMemcpy(c->xyz_d.p, xyz, sizeof(double) * (size_t)c->W * c->nmax_all * 3, hipMemcpyHostToDevice));
+    if (label) {
+        REGC_HIP(hipMemcpy(c->label_d.p, label, sizeof(int32_t) * c->W, hipMemcpyHostToDevice));
+        REGC_HIP(hipMemcpy(c->wos_d.p, wos.data(), sizeof(int32_t) * c->W, hipMemcpyHostToDevice));
+    }
+    int rc = run_energy(c, c->e_d.p);
+    if (rc) return rc;
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    return REGC_OK;
+}
+
+extern "C" int regc_energies(regc_ctx *c, double *e_out)
+{
+    REGC_CHECK(c && e_out, REGC_EINVAL, "null argument");
+    DevBuf<double> tmp;
+    int rc;
+    if ((rc = tmp.alloc(c->W))) return rc;
+    if ((rc = run_energy(c, tmp.p))) return rc;
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy(e_out, tmp.p, sizeof(double) * c->W, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_sample_count(const regc_ctx *c, int64_t *count)
+{
+    REGC_CHECK(c && count, REGC_EINVAL, "null argument");
+    *count = c->n_rec * c->W;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_samples(regc_ctx *c, double *e, int32_t *n, int32_t *state, int64_t cap, int64_t *n_out)
+{
+    REGC_CHECK(c && n_out, REGC_EINVAL, "null argument");
+    const int64_t cnt = std::min<int64_t>(cap, c->n_rec * c->W);
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (cnt > 0) {
+        if (e) REGC_HIP(hipMemcpy(e, c->samp_e.p, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+        if (n) REGC_HIP(hipMemcpy(n, c->samp_n.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+        if (state) REGC_HIP(hipMemcpy(state, c->samp_s.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    }
+    *n_out = cnt;
+    return REGC_OK;
+}
+
+extern "C" int regc_samples_device(regc_ctx *c, const double **e_dev, const int32_t **n_dev,
+                                   const int32_t **state_dev, int64_t *count)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    if (e_dev) *e_dev = c->samp_e.p;
+    if (n_dev) *n_dev = c->samp_n.p;
+    if (state_dev) *state_dev = c->samp_s.p;
+    if (count) *count = c->n_rec * c->W;
+    return REGC_OK;
+}
+
+extern "C" int regc_clear_samples(regc_ctx *c)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    c->rec_base = c->opts.sample_every > 0 ? c->sweep / c->opts.sample_every : 0;
+    c->n_rec = 0;
+    REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * (size_t)c->W * (c->nmax_all + 1)));
+    c->trace_sweep0 = c->sweep;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_stats(regc_ctx *c, int64_t *stats, int64_t *swap_att, int64_t *swap_acc)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (stats) REGC_HIP(hipMemcpy(stats, c->stats_d.p, sizeof(int64_t) * (size_t)c->W * kNStat, hipMemcpyDeviceToHost));
+    if (swap_att) REGC_HIP(hipMemcpy(swap_att, c->att_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
+    if (swap_acc) REGC_HIP(hipMemcpy(swap_acc, c->acc_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_get_histograms(regc_ctx *c, int64_t *n_hist)
+{
+    REGC_CHECK(c && n_hist, REGC_EINVAL, "null argument");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy(n_hist, c->hist_d.p, sizeof(int64_t) * (size_t)c->W * (c->nmax_all + 1), hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_get_trace(regc_ctx *c, uint32_t *bits, int32_t *n_per_sweep, int64_t cap_sweeps, int64_t *n_out)
+{
+    REGC_CHECK(c && n_out, REGC_EINVAL, "null argument");
+    REGC_CHECK(c->trace_cap > 0, REGC_ESTATE, "context created without a trace buffer");
+    const int64_t have = std::min<int64_t>(c->sweep - c->trace_sweep0, c->trace_cap);
+    const int64_t cnt = std::min<int64_t>(have, cap_sweeps);
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (cnt > 0) {
+        if (bits)
+            REGC_HIP(hipMemcpy(bits, c->trace_bits_d.p, sizeof(uint32_t) * (size_t)cnt * c->W * c->words,
+                               hipMemcpyDeviceToHost));
+        if (n_per_sweep)
+            REGC_HIP(hipMemcpy(n_per_sweep, c->trace_n_d.p, sizeof(int32_t) * (size_t)cnt * c->W, hipMemcpyDeviceToHost));
+    }
+    *n_out = cnt;
+    return REGC_OK;
+}
+
+extern "C" int regc_timing_enable(regc_ctx *c, int enable)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    for (auto &p : c->ev_sweep) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto &p : c->ev_swap) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    c->ev_sweep.clear();
+    c->ev_swap.clear();
+    c->timing = enable != 0;
+    return REGC_OK;
+}
+
+extern "C" int regc_timing_get(regc_ctx *c, double *ms_sweep, int64_t *n_sweep, double *ms_swap, int64_t *n_swap)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    double a = 0, b = 0;
+    for (auto &p : c->ev_sweep) {
+        float ms = 0;
+        REGC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        a += ms;
+    }
+    for (auto &p : c->ev_swap) {
+        float ms = 0;
+        REGC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        b += ms;
+    }
+    if (ms_sweep) *ms_sweep = a;
+    if (n_sweep) *n_sweep = (int64_t)c->ev_sweep.size();
+    if (ms_swap) *ms_swap = b;
+    if (n_swap) *n_swap = (int64_t)c->ev_swap.size();
+    return REGC_OK;
+}
+
+// checkpoint layout: header, then n, e, label, wos, xyz, stats, att, acc
+namespace {
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version, W, nmax, n_class;
+    int64_t sweep;
+    uint64_t seed;
+};
+constexpr uint64_t kMagic = 0x3143474552ULL;   // "REGC1"
+}  // namespace
+
+static size_t ckpt_size(const regc_ctx *c)
+{
+    const size_t W = c->W;
+    return sizeof(CkptHeader) + W * (4 + 8 + 4 + 4) + W * c->nmax_all * 3 * 8 + W * kNStat * 8 + 2 * 4 * W * 8;
+}
+
+extern "C" int regc_checkpoint(regc_ctx *c, void *buf, size_t cap, size_t *size)
+{
+    REGC_CHECK(c && size, REGC_EINVAL, "null argument");
+    *size = ckpt_size(c);
+    if (!buf) return REGC_OK;
+    REGC_CHECK(cap >= *size, REGC_ECAPACITY, "checkpoint needs %zu bytes", *size);
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    char *p = (char *)buf;
+    CkptHeader h{kMagic, 1u, (uint32_t)c->W, (uint32_t)c->nmax_all, (uint32_t)c->cls.size(), c->sweep, c->opts.seed};
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const size_t W = c->W;
+    REGC_HIP(hipMemcpy(p, c->n_d.p, W * 4, hipMemcpyDeviceToHost)); p += W * 4;
+    REGC_HIP(hipMemcpy(p, c->e_d.p, W * 8, hipMemcpyDeviceToHost)); p += W * 8;
+    REGC_HIP(hipMemcpy(p, c->label_d.p, W * 4, hipMemcpyDeviceToHost)); p += W * 4;
+    REGC_HIP(hipMemcpy(p, c->wos_d.p, W * 4, hipMemcpyDeviceToHost)); p += W * 4;
+    REGC_HIP(hipMemcpy(p, c->xyz_d.p, W * c->nmax_all * 3 * 8, hipMemcpyDeviceToHost)); p += W * c->nmax_all * 3 * 8;
+    REGC_HIP(hipMemcpy(p, c->stats_d.p, W * kNStat * 8, hipMemcpyDeviceToHost)); p += W * kNStat * 8;
+    REGC_HIP(hipMemcpy(p, c->att_d.p, 4 * W * 8, hipMemcpyDeviceToHost)); p += 4 * W * 8;
+    REGC_HIP(hipMemcpy(p, c->acc_d.p, 4 * W * 8, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_restore(regc_ctx *c, const void *buf, size_t size)
+{
+    REGC_CHECK(c && buf, REGC_EINVAL, "null argument");
+    REGC_CHECK(size == ckpt_size(c), REGC_EINVAL, "checkpoint size does not match this context");
+    const char *p = (const char *)buf;
+    CkptHeader h;
+    std::memcpy(&h, p, sizeof h);
+    p += sizeof h;
+    REGC_CHECK(h.magic == kMagic && h.version == 1 && h.W == (uint32_t)c->W && h.nmax == (uint32_t)c->nmax_all &&
+                   h.n_class == (uint32_t)c->cls.size() && h.seed == c->opts.seed,
+               REGC_EINVAL, "checkpoint was written by a different context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    const size_t W = c->W;
+    REGC_HIP(hipMemcpy(c->n_d.p, p, W * 4, hipMemcpyHostToDevice)); p += W * 4;
+    REGC_HIP(hipMemcpy(c->e_d.p, p, W * 8, hipMemcpyHostToDevice)); p += W * 8;
+    REGC_HIP(hipMemcpy(c->label_d.p, p, W * 4, hipMemcpyHostToDevice)); p += W * 4;
+    REGC_HIP(hipMemcpy(c->wos_d.p, p, W * 4, hipMemcpyHostToDevice)); p += W * 4;
+    REGC_HIP(hipMemcpy(c->xyz_d.p, p, W * c->nmax_all * 3 * 8, hipMemcpyHostToDevice)); p += W * c->nmax_all * 3 * 8;
+    REGC_HIP(hipMemcpy(c->stats_d.p, p, W * kNStat * 8, hipMemcpyHostToDevice)); p += W * kNStat * 8;
+    REGC_HIP(hipMemcpy(c->att_d.p, p, 4 * W * 8, hipMemcpyHostToDevice)); p += 4 * W * 8;
+    REGC_HIP(hipMemcpy(c->acc_d.p, p, 4 * W * 8, hipMemcpyHostToDevice));
+    c->sweep = h.sweep;
+    c->rec_base = c->opts.sample_every > 0 ? c->sweep / c->opts.sample_every : 0;
+    c->n_rec = 0;
+    c->trace_sweep0 = c->sweep;
+    REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * W * (c->nmax_all + 1)));
+    return REGC_OK;
+}
+
+extern "C" void regc_destroy(regc_ctx *c)
+{
+    if (c) {
+        (void)hipStreamSynchronize(c->stream);
+        delete c;
+    }
+}
+
+extern "C" int regc_mbar_load_run(regc_mbar *mb, regc_ctx *c, int cls, int64_t skip_records)
+{
+    REGC_CHECK(mb && c, REGC_EINVAL, "null argument");
+    REGC_CHECK(cls >= 0 && cls < (int)c->cls.size(), REGC_EINVAL, "class index out of range");
+    REGC_CHECK(skip_records >= 0 && skip_records < c->n_rec, REGC_EINVAL, "no records after the skipped ones");
+    const int64_t recs = c->n_rec - skip_records;
+    const int off = c->cls[cls].off, cnt = c->cls[cls].S;
+    const size_t W = c->W;
+    DevBuf<double> e;
+    DevBuf<int32_t> n, s;
+    int rc;
+    if ((rc = e.alloc(recs * cnt)) || (rc = n.alloc(recs * cnt)) || (rc = s.alloc(recs * cnt))) return rc;
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy2D(e.p, cnt * sizeof(double), c->samp_e.p + skip_records * W + off, W * sizeof(double),
+                         cnt * sizeof(double), recs, hipMemcpyDeviceToDevice));
+    REGC_HIP(hipMemcpy2D(n.p, cnt * sizeof(int32_t), c->samp_n.p + skip_records * W + off, W * sizeof(int32_t),
+                         cnt * sizeof(int32_t), recs, hipMemcpyDeviceToDevice));
+    REGC_HIP(hipMemcpy2D(s.p, cnt * sizeof(int32_t), c->samp_s.p + skip_records * W + off, W * sizeof(int32_t),
+                         cnt * sizeof(int32_t), recs, hipMemcpyDeviceToDevice));
+    return regc_mbar_set_samples(mb, recs * cnt, e.p, n.p, s.p, 1);
+}

@@ -1,0 +1,595 @@
+// mbar.hip -- multistate reweighting of REGC samples (arXiv:1908.11118, Sec. II.B).
+//
+// Reduced potential of sample n in state s = (l, m):  u_s(n) = beta_l E_n - N_n ln z_lm
+// (Eq. (8) with the paper's sign of mu N plus the 3N ln Lambda(T) term of Eq. (1)).
+// Self-consistent equations (Eq. (9)) in log form, f_s = -ln c_s:
+//     log D_n = logsumexp_k [ln Omega_k + f_k - u_k(n)],   f_s = -logsumexp_n [-u_s(n) - log D_n].
+//
+// On a T x mu product grid the state sum factorises exactly (the algebra is
+// ours, not the paper's):
+//     D_n = sum_l exp(-beta_l E_n) A_l(N_n),       A_l(N) = sum_m Omega_lm exp(f_lm + N ln z_lm),
+//     exp(-f_lm) = sum_N z_lm^N P_l(N) / A_l(N),   P_l(N) = sum_{n: N_n = N} p_l(n),
+// where p_l(n) = exp(-beta_l E_n) A_l(N_n) / D_n is the softmax over temperatures of
+// x_l(n) = -beta_l E_n + log A_l(N_n).  One iteration therefore costs L exponentials
+// per sample instead of 2 L M, and every partial sum lies in [0, count]: no overflow.
+// Samples are sorted by N once (stable radix sort) and cut into chunks of one N
+// each; each chunk writes its L partial sums and they are added in chunk order,
+// so results are deterministic.
+//
+// Averages at a target (T', mu'): with y(n) = -beta' E_n - log D_n,
+//     G(N) = logsumexp_{n: N_n = N} y(n),   P(N) proportional to exp(N ln z' + G(N)),
+//     <N> = sum N P(N),  <E^k> = sum_N P(N) [sum_{N_n=N} E_n^k e^{y}] / [sum_{N_n=N} e^{y}],
+//     f' = -logsumexp_N (N ln z' + G(N)),  phase = argmax_N P(N) (Eq. (10)/(11), smallest N on ties).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "host_util.h"
+#include "regc_dev.h"
+
+namespace regc {
+
+constexpr int kChunk = 2048;
+constexpr int kMbarThreads = 256;
+constexpr int kMaxL = 64;
+
+__global__ void mbar_count(int64_t ns, const int32_t *n, const int32_t *st, int nN, int S,
+                           unsigned long long *omega, unsigned long long *seg, int *bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        const int N = n[i], s = st[i];
+        if (N < 0 || N >= nN || s < 0 || s >= S) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        atomicAdd(omega + s, 1ull);
+        atomicAdd(seg + N, 1ull);
+    }
+}
+
+__global__ void mbar_iota_gather(int64_t ns, const int32_t *n_in, uint32_t *keys, int32_t *idx)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = (uint32_t)n_in[i];
+        idx[i] = (int32_t)i;
+    }
+}
+
+__global__ void mbar_gather_e(int64_t ns, const int32_t *perm, const double *e_in, double *e_out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x)
+        e_out[i] = e_in[perm[i]];
+}
+
+// log A_l(N) for every l (block) and N (threads)
+__global__ void mbar_loga(int M, int nN, const double *lnomega, const double *f, const double *lnz, double *logA)
+{
+    const int l = blockIdx.x;
+    for (int N = threadIdx.x; N < nN; N += blockDim.x) {
+        double mx = -INFINITY;
+        for (int m = 0; m < M; ++m) {
+            const int s = l * M + m;
+            if (lnomega[s] == -INFINITY) continue;
+            const double v = lnomega[s] + f[s] + (double)N * lnz[s];
+            mx = v > mx ? v : mx;
+        }
+        double sum = 0.0;
+        if (mx != -INFINITY)
+            for (int m = 0; m < M; ++m) {
+                const int s = l * M + m;
+                if (lnomega[s] == -INFINITY) continue;
+                sum += exp(lnomega[s] + f[s] + (double)N * lnz[s] - mx);
+            }
+        logA[(size_t)l * nN + N] = mx == -INFINITY ? -INFINITY : mx + log(sum);
+    }
+}
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One chunk (samples of a single N) per block: softmax over temperatures per
+// sample, partial sums of p_l(n) per chunk; log D_n when requested.
+template <int LMAX>
+__global__ void __launch_bounds__(kMbarThreads) mbar_chunk(int L, int nN, const double *beta_l, const double *logA,
+                                                        const double *e, const int *chunk_n, const int *chunk_b,
+                                                        const int *chunk_e, double *partial, double *logd_out)
+{
+    __shared__ double red[kMbarThreads / 64][LMAX];
+    const int c = blockIdx.x;
+    const int N = chunk_n[c];
+    double la[LMAX], nb[LMAX], acc[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+        la[l] = l < L ? logA[(size_t)l * nN + N] : -INFINITY;
+        nb[l] = l < L ? -beta_l[l] : 0.0;
+        acc[l] = 0.0;
+    }
+    const int end = chunk_e[c];
+    for (int i = chunk_b[c] + threadIdx.x; i < end; i += blockDim.x) {
+        const double E = e[i];
+        double x[LMAX];
+        double mx = -INFINITY;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            x[l] = l < L ? nb[l] * E + la[l] : -INFINITY;
+            mx = x[l] > mx ? x[l] : mx;
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            x[l] = l < L ? exp(x[l] - mx) : 0.0;
+            sum += x[l];
+        }
+        const double inv = 1.0 / sum;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) acc[l] += x[l] * inv;
+        if (logd_out) logd_out[i] = mx + log(sum);
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+        const double v = wsum(acc[l]);
+        if (lane == 0) red[wave][l] = v;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double v = 0.0;
+        for (int wv = 0; wv < kMbarThreads / 64; ++wv) v += red[wv][l];
+        partial[(size_t)c * L + l] = v;
+    }
+}
+
+// New free energies: one block per temperature l.
+__global__ void mbar_fnew(int L, int M, int nN, const double *partial, const int *seg_c0, const int *seg_c1,
+                          const double *logA, const double *lnz, double *fnew)
+{
+    extern __shared__ double logB[];
+    const int l = blockIdx.x;
+    for (int N = threadIdx.x; N < nN; N += blockDim.x) {
+        double P = 0.0;
+        for (int c = seg_c0[N]; c < seg_c1[N]; ++c) P += partial[(size_t)c * L + l];
+        logB[N] = P > 0.0 ? log(P) - logA[(size_t)l * nN + N] : -INFINITY;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        const double lz = lnz[l * M + m];
+        double mx = -INFINITY;
+        for (int N = 0; N < nN; ++N) {
+            if (logB[N] == -INFINITY) continue;
+            const double v = (double)N * lz + logB[N];
+            mx = v > mx ? v : mx;
+        }
+        double sum = 0.0;
+        for (int N = 0; N < nN; ++N) {
+            if (logB[N] == -INFINITY) continue;
+            sum += exp((double)N * lz + logB[N] - mx);
+        }
+        fnew[l * M + m] = -(mx + log(sum));
+    }
+}
+
+// Gauge (f = 0 at state g) and max |delta f| over sampled states; f <- fnew.
+__global__ void mbar_gauge(int S, int g, const double *lnomega, double *fnew, double *f, double *delta)
+{
+    __shared__ double red[16];
+    const double f0 = fnew[g];
+    double d = 0.0;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        const double v = fnew[s] - f0;
+        if (lnomega[s] != -INFINITY) {
+            const double a = fabs(v - f[s]);
+            d = a > d ? a : d;
+        }
+        f[s] = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(d, o);
+        d = t > d ? t : d;
+    }
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) m = red[k] > m ? red[k] : m;
+        *delta = m;
+    }
+}
+
+// Target temperatures: per chunk and target temperature the online (max, s0, s1, s2).
+__global__ void __launch_bounds__(kMbarThreads) mbar_target_chunk(int nT, const double *tbeta, const double *e,
+                                                               const double *logd, const int *chunk_b,
+                                                               const int *chunk_e, double *tpart)
+{
+    __shared__ double red[kMbarThreads / 64][4];
+    const int c = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int t = 0; t < nT; ++t) {
+        const double b = tbeta[t];
+        double mx = -INFINITY, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int i = chunk_b[c] + threadIdx.x; i < chunk_e[c]; i += blockDim.x) {
+            const double E = e[i];
+            const double y = -b * E - logd[i];
+            if (y > mx) {
+                const double sc = exp(mx - y);
+                s0 *= sc; s1 *= sc; s2 *= sc;
+                mx = y;
+            }
+            const double w = exp(y - mx);
+            s0 += w; s1 += w * E; s2 += w * E * E;
+        }
+        // wave combine
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double om = __shfl_xor(mx, o), o0 = __shfl_xor(s0, o), o1 = __shfl_xor(s1, o),
+                         o2 = __shfl_xor(s2, o);
+            const double nm = om > mx ? om : mx;
+            const double a = nm == -INFINITY ? 0.0 : exp(mx - nm), bb = nm == -INFINITY ? 0.0 : exp(om - nm);
+            s0 = s0 * a + o0 * bb; s1 = s1 * a + o1 * bb; s2 = s2 * a + o2 * bb;
+            mx = nm;
+        }
+        if (lane == 0) { red[wave][0] = mx; red[wave][1] = s0; red[wave][2] = s1; red[wave][3] = s2; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double M = -INFINITY;
+            for (int k = 0; k < kMbarThreads / 64; ++k) M = red[k][0] > M ? red[k][0] : M;
+            double a0 = 0, a1 = 0, a2 = 0;
+            if (M != -INFINITY)
+                for (int k = 0; k < kMbarThreads / 64; ++k) {
+                    if (red[k][0] == -INFINITY) continue;
+                    const double sc = exp(red[k][0] - M);
+                    a0 += red[k][1] * sc; a1 += red[k][2] * sc; a2 += red[k][3] * sc;
+                }
+            double *o = tpart + ((size_t)c * nT + t) * 4;
+            o[0] = M; o[1] = a0; o[2] = a1; o[3] = a2;
+        }
+        __syncthreads();
+    }
+}
+
+// Per target temperature (block): combine chunk partials by N, then every mu'.
+__global__ void mbar_target_eval(int nT, int nMu, int nN, const double *tpart, const int *seg_c0, const int *seg_c1,
+                                 const double *tlnz, double *f, double *mean_n, double *mean_e, double *mean_e2,
+                                 double *p_n, int32_t *phase)
+{
+    extern __shared__ double sh[];
+    double *G = sh, *E1 = sh + nN, *E2 = sh + 2 * nN;
+    const int t = blockIdx.x;
+    for (int N = threadIdx.x; N < nN; N += blockDim.x) {
+        double M = -INFINITY;
+        for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+            const double m = tpart[((size_t)c * nT + t) * 4];
+            M = m > M ? m : M;
+        }
+        double a0 = 0, a1 = 0, a2 = 0;
+        if (M != -INFINITY)
+            for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+                const double *o = tpart + ((size_t)c * nT + t) * 4;
+                if (o[0] == -INFINITY) continue;
+                const double sc = exp(o[0] - M);
+                a0 += o[1] * sc; a1 += o[2] * sc; a2 += o[3] * sc;
+            }
+        G[N] = (M == -INFINITY || a0 <= 0.0) ? -INFINITY : M + log(a0);
+        E1[N] = a0 > 0.0 ? a1 / a0 : 0.0;
+        E2[N] = a0 > 0.0 ? a2 / a0 : 0.0;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < nMu; m += blockDim.x) {
+        const int k = t * nMu + m;
+        const double lz = tlnz[k];
+        double mx = -INFINITY;
+        int best = 0;
+        for (int N = 0; N < nN; ++N) {
+            if (G[N] == -INFINITY) continue;
+            const double v = (double)N * lz + G[N];
+            if (v > mx) { mx = v; best = N; }
+        }
+        double sum = 0.0;
+        for (int N = 0; N < nN; ++N)
+            if (G[N] != -INFINITY) sum += exp((double)N * lz + G[N] - mx);
+        const double lse = mx + log(sum);
+        double sn = 0, se = 0, se2 = 0;
+        for (int N = 0; N < nN; ++N) {
+            const double p = G[N] == -INFINITY ? 0.0 : exp((double)N * lz + G[N] - lse);
+            sn += p * (double)N; se += p * E1[N]; se2 += p * E2[N];
+            if (p_n) p_n[(size_t)k * nN + N] = p;
+        }
+        if (f) f[k] = -lse;
+        mean_n[k] = sn;
+        if (mean_e) mean_e[k] = se;
+        if (mean_e2) mean_e2[k] = se2;
+        if (phase) phase[k] = best;
+    }
+}
+
+}  // namespace regc
+
+using namespace regc;
+
+struct regc_mbar {
+    int L = 0, M = 0, S = 0, nN = 0;
+    double lambda1 = 1.0;
+    std::vector<double> t, mu, beta_l, lnz;
+    hipStream_t stream = nullptr;
+    DevBuf<double> beta_d, lnz_d, lnomega_d, f_d, fnew_d, logA_d, partial_d, delta_d, e_d, logd_d;
+    DevBuf<int> chunk_n_d, chunk_b_d, chunk_e_d, seg_c0_d, seg_c1_d;
+    int64_t ns = 0;
+    int nchunks = 0;
+    int gauge = -1;
+    std::vector<double> lnomega;
+    bool have_samples = false, solved = false;
+    double ms_iter = 0.0;
+    int64_t n_iter = 0;
+};
+
+static double lnz_of(double T, double mu, double lambda1)
+{
+    return mu / T - 3.0 * std::log(lambda1 / std::sqrt(T));
+}
+
+extern "C" int regc_mbar_create(const regc_grid *grid, double lambda1, int n_max, regc_mbar **out)
+{
+    REGC_CHECK(grid && out && grid->t && grid->mu, REGC_EINVAL, "null argument");
+    REGC_CHECK(grid->n_t > 0 && grid->n_mu > 0 && n_max >= 0, REGC_EINVAL, "empty grid or negative n_max");
+    REGC_CHECK(grid->n_t <= kMaxL, REGC_EUNSUPPORTED, "at most %d temperatures per reweighting grid", kMaxL);
+    REGC_CHECK(n_max < 2048, REGC_EUNSUPPORTED, "n_max above 2047");
+    REGC_CHECK(lambda1 > 0, REGC_EINVAL, "lambda1 must be positive");
+    regc_mbar *mb = new regc_mbar();
+    mb->L = grid->n_t; mb->M = grid->n_mu; mb->S = mb->L * mb->M; mb->nN = n_max + 1;
+    mb->lambda1 = lambda1;
+    mb->t.assign(grid->t, grid->t + mb->L);
+    mb->mu.assign(grid->mu, grid->mu + mb->M);
+    for (int l = 0; l < mb->L; ++l) {
+        if (!(mb->t[l] > 0)) { delete mb; set_error("temperatures must be positive"); return REGC_EINVAL; }
+        mb->beta_l.push_back(1.0 / mb->t[l]);
+        for (int m = 0; m < mb->M; ++m) mb->lnz.push_back(lnz_of(mb->t[l], mb->mu[m], lambda1));
+    }
+    int rc;
+    if ((rc = mb->beta_d.alloc(mb->L)) || (rc = mb->lnz_d.alloc(mb->S)) || (rc = mb->lnomega_d.alloc(mb->S)) ||
+        (rc = mb->f_d.alloc(mb->S)) || (rc = mb->fnew_d.alloc(mb->S)) ||
+        (rc = mb->logA_d.alloc((size_t)mb->L * mb->nN)) || (rc = mb->delta_d.alloc(1)) ||
+        (rc = mb->seg_c0_d.alloc(mb->nN)) || (rc = mb->seg_c1_d.alloc(mb->nN))) {
+        delete mb;
+        return rc;
+    }
+    if (hipMemcpy(mb->beta_d.p, mb->beta_l.data(), sizeof(double) * mb->L, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mb->lnz_d.p, mb->lnz.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice) != hipSuccess) {
+        delete mb;
+        set_error("hipMemcpy failed");
+        return REGC_EHIP;
+    }
+    *out = mb;
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_set_stream(regc_mbar *mb, void *stream)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    mb->stream = (hipStream_t)stream;
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e, const int32_t *n,
+                                     const int32_t *state, int on_device)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    REGC_CHECK(ns > 0 && e && n && state, REGC_EINVAL, "no samples");
+    REGC_CHECK(ns < (int64_t)1 << 31, REGC_EUNSUPPORTED, "more than 2^31 - 1 samples");
+    hipStream_t s = mb->stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    DevBuf<double> e_in;
+    DevBuf<int32_t> n_in, s_in, idx, idx_out;
+    DevBuf<uint32_t> keys, keys_out;
+    DevBuf<unsigned long long> omega, seg;
+    DevBuf<int> bad;
+    int rc;
+    if ((rc = e_in.alloc(ns)) || (rc = n_in.alloc(ns)) || (rc = s_in.alloc(ns)) || (rc = keys.alloc(ns)) ||
+        (rc = keys_out.alloc(ns)) || (rc = idx.alloc(ns)) || (rc = idx_out.alloc(ns)) || (rc = omega.alloc(mb->S)) ||
+        (rc = seg.alloc(mb->nN)) || (rc = bad.alloc(1)) || (rc = mb->e_d.alloc(ns)) || (rc = mb->logd_d.alloc(ns)))
+        return rc;
+    REGC_HIP(hipMemcpyAsync(e_in.p, e, sizeof(double) * ns, kind, s));
+    REGC_HIP(hipMemcpyAsync(n_in.p, n, sizeof(int32_t) * ns, kind, s));
+    REGC_HIP(hipMemcpyAsync(s_in.p, state, sizeof(int32_t) * ns, kind, s));
+    REGC_HIP(hipMemsetAsync(omega.p, 0, sizeof(unsigned long long) * mb->S, s));
+    REGC_HIP(hipMemsetAsync(seg.p, 0, sizeof(unsigned long long) * mb->nN, s));
+    REGC_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    const int grid = (int)std::min<int64_t>((ns + 255) / 256, 4096);
+    hipLaunchKernelGGL(mbar_count, dim3(grid), dim3(256), 0, s, ns, n_in.p, s_in.p, mb->nN, mb->S, omega.p, seg.p,
+                       bad.p);
+    REGC_HIP(hipGetLastError());
+    int h_bad = 0;
+    std::vector<unsigned long long> h_omega(mb->S), h_seg(mb->nN);
+    REGC_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipMemcpyAsync(h_omega.data(), omega.p, sizeof(unsigned long long) * mb->S, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipMemcpyAsync(h_seg.data(), seg.p, sizeof(unsigned long long) * mb->nN, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipStreamSynchronize(s));
+    REGC_CHECK(!h_bad, REGC_EINVAL, "sample with N outside 0..n_max or state outside the grid");
+
+    // stable sort by N
+    hipLaunchKernelGGL(mbar_iota_gather, dim3(grid), dim3(256), 0, s, ns, n_in.p, keys.p, idx.p);
+    REGC_HIP(hipGetLastError());
+    int end_bit = 1;
+    while ((1 << end_bit) < mb->nN) ++end_bit;
+    size_t temp_bytes = 0;
+    REGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
+                                                end_bit, s));
+    DevBuf<unsigned char> temp;
+    if ((rc = temp.alloc(temp_bytes))) return rc;
+    REGC_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
+                                                end_bit, s));
+    hipLaunchKernelGGL(mbar_gather_e, dim3(grid), dim3(256), 0, s, ns, idx_out.p, e_in.p, mb->e_d.p);
+    REGC_HIP(hipGetLastError());
+
+    // chunks of one N each
+    std::vector<int> cn, cb, ce, c0(mb->nN), c1(mb->nN);
+    int64_t pos = 0;
+    for (int N = 0; N < mb->nN; ++N) {
+        c0[N] = (int)cn.size();
+        const int64_t cnt = (int64_t)h_seg[N];
+        for (int64_t k = 0; k < cnt; k += kChunk) {
+            cn.push_back(N);
+            cb.push_back((int)(pos + k));
+            ce.push_back((int)(pos + std::min<int64_t>(cnt, k + kChunk)));
+        }
+        pos += cnt;
+        c1[N] = (int)cn.size();
+    }
+    mb->nchunks = (int)cn.size();
+    if ((rc = mb->chunk_n_d.alloc(mb->nchunks)) || (rc = mb->chunk_b_d.alloc(mb->nchunks)) ||
+        (rc = mb->chunk_e_d.alloc(mb->nchunks)) || (rc = mb->partial_d.alloc((size_t)mb->nchunks * mb->L)))
+        return rc;
+    REGC_HIP(hipMemcpyAsync(mb->chunk_n_d.p, cn.data(), sizeof(int) * cn.size(), hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(mb->chunk_b_d.p, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(mb->chunk_e_d.p, ce.data(), sizeof(int) * ce.size(), hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(mb->seg_c0_d.p, c0.data(), sizeof(int) * mb->nN, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(mb->seg_c1_d.p, c1.data(), sizeof(int) * mb->nN, hipMemcpyHostToDevice, s));
+    mb->lnomega.assign(mb->S, -INFINITY);
+    mb->gauge = -1;
+    for (int k = 0; k < mb->S; ++k)
+        if (h_omega[k] > 0) {
+            mb->lnomega[k] = std::log((double)h_omega[k]);
+            if (mb->gauge < 0) mb->gauge = k;
+        }
+    REGC_HIP(hipMemcpyAsync(mb->lnomega_d.p, mb->lnomega.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipStreamSynchronize(s));
+    mb->ns = ns;
+    mb->have_samples = true;
+    mb->solved = false;
+    return REGC_OK;
+}
+
+static hipError_t launch_chunk(regc_mbar *mb, double *logd)
+{
+    const int L = mb->L;
+    hipStream_t s = mb->stream;
+#define CHUNK_CASE(LM)                                                                                      \
+    hipLaunchKernelGGL(mbar_chunk<LM>, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, L, mb->nN, mb->beta_d.p, \
+                       mb->logA_d.p, mb->e_d.p, mb->chunk_n_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p,         \
+                       mb->partial_d.p, logd)
+    if (L <= 8) CHUNK_CASE(8);
+    else if (L <= 16) CHUNK_CASE(16);
+    else if (L <= 32) CHUNK_CASE(32);
+    else CHUNK_CASE(64);
+#undef CHUNK_CASE
+    return hipGetLastError();
+}
+
+static hipError_t mbar_iteration(regc_mbar *mb)
+{
+    hipStream_t s = mb->stream;
+    hipLaunchKernelGGL(mbar_loga, dim3(mb->L), dim3(256), 0, s, mb->M, mb->nN, mb->lnomega_d.p, mb->f_d.p,
+                       mb->lnz_d.p, mb->logA_d.p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_chunk(mb, nullptr)) != hipSuccess) return e;
+    hipLaunchKernelGGL(mbar_fnew, dim3(mb->L), dim3(256), sizeof(double) * mb->nN, s, mb->L, mb->M, mb->nN,
+                       mb->partial_d.p, mb->seg_c0_d.p, mb->seg_c1_d.p, mb->logA_d.p, mb->lnz_d.p, mb->fnew_d.p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(mbar_gauge, dim3(1), dim3(1024), 0, s, mb->S, mb->gauge, mb->lnomega_d.p, mb->fnew_d.p,
+                       mb->f_d.p, mb->delta_d.p);
+    return hipGetLastError();
+}
+
+extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters, double *delta)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    REGC_CHECK(mb->have_samples, REGC_ESTATE, "no samples loaded");
+    REGC_CHECK(max_iter > 0 && tol > 0, REGC_EINVAL, "max_iter and tol must be positive");
+    hipStream_t s = mb->stream;
+    REGC_HIP(hipMemsetAsync(mb->f_d.p, 0, sizeof(double) * mb->S, s));
+    hipEvent_t e0, e1;
+    REGC_HIP(hipEventCreate(&e0));
+    REGC_HIP(hipEventCreate(&e1));
+    REGC_HIP(hipEventRecord(e0, s));
+    const int check = 10;
+    double d = INFINITY;
+    int it = 0;
+    bool conv = false;
+    for (it = 0; it < max_iter;) {
+        REGC_HIP(mbar_iteration(mb));
+        ++it;
+        if (it % check == 0 || it == max_iter) {
+            REGC_HIP(hipMemcpyAsync(&d, mb->delta_d.p, sizeof(double), hipMemcpyDeviceToHost, s));
+            REGC_HIP(hipStreamSynchronize(s));
+            if (d < tol) { conv = true; break; }
+        }
+    }
+    REGC_HIP(hipEventRecord(e1, s));
+    // log D consistent with the final f
+    hipLaunchKernelGGL(mbar_loga, dim3(mb->L), dim3(256), 0, s, mb->M, mb->nN, mb->lnomega_d.p, mb->f_d.p,
+                       mb->lnz_d.p, mb->logA_d.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(launch_chunk(mb, mb->logd_d.p));
+    REGC_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    REGC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    mb->ms_iter = ms;
+    mb->n_iter = it;
+    if (f_out) REGC_HIP(hipMemcpy(f_out, mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
+    if (iters) *iters = it;
+    if (delta) *delta = d;
+    mb->solved = true;
+    if (!conv) {
+        set_error("reweighting did not converge: max |delta f| = %g after %d iterations", d, it);
+        return REGC_ENOCONV;
+    }
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
+                                 double *mean_e, double *mean_e2, double *p_n, int32_t *phase)
+{
+    REGC_CHECK(mb && targets && mean_n && targets->t && targets->mu, REGC_EINVAL, "null argument");
+    REGC_CHECK(mb->solved, REGC_ESTATE, "solve first");
+    const int nT = targets->n_t, nMu = targets->n_mu, nK = nT * nMu;
+    REGC_CHECK(nT > 0 && nMu > 0, REGC_EINVAL, "empty target grid");
+    std::vector<double> tb(nT), tz(nK);
+    for (int l = 0; l < nT; ++l) {
+        REGC_CHECK(targets->t[l] > 0, REGC_EINVAL, "target temperatures must be positive");
+        tb[l] = 1.0 / targets->t[l];
+        for (int m = 0; m < nMu; ++m) tz[l * nMu + m] = lnz_of(targets->t[l], targets->mu[m], mb->lambda1);
+    }
+    hipStream_t s = mb->stream;
+    DevBuf<double> tb_d, tz_d, tpart, f_d, mn_d, me_d, me2_d, pn_d;
+    DevBuf<int32_t> ph_d;
+    int rc;
+    if ((rc = tb_d.alloc(nT)) || (rc = tz_d.alloc(nK)) || (rc = tpart.alloc((size_t)mb->nchunks * nT * 4)) ||
+        (rc = f_d.alloc(nK)) || (rc = mn_d.alloc(nK)) || (rc = me_d.alloc(nK)) || (rc = me2_d.alloc(nK)) ||
+        (rc = ph_d.alloc(nK)) || (rc = pn_d.alloc(p_n ? (size_t)nK * mb->nN : 1)))
+        return rc;
+    REGC_HIP(hipMemcpyAsync(tb_d.p, tb.data(), sizeof(double) * nT, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(tz_d.p, tz.data(), sizeof(double) * nK, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(mbar_target_chunk, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, nT, tb_d.p, mb->e_d.p,
+                       mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, tpart.p);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mbar_target_eval, dim3(nT), dim3(256), sizeof(double) * 3 * mb->nN, s, nT, nMu, mb->nN,
+                       tpart.p, mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d.p, f_d.p, mn_d.p, me_d.p, me2_d.p,
+                       p_n ? pn_d.p : nullptr, ph_d.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    if (f) REGC_HIP(hipMemcpy(f, f_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    REGC_HIP(hipMemcpy(mean_n, mn_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (mean_e) REGC_HIP(hipMemcpy(mean_e, me_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (mean_e2) REGC_HIP(hipMemcpy(mean_e2, me2_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (phase) REGC_HIP(hipMemcpy(phase, ph_d.p, sizeof(int32_t) * nK, hipMemcpyDeviceToHost));
+    if (p_n) REGC_HIP(hipMemcpy(p_n, pn_d.p, sizeof(double) * nK * mb->nN, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    if (ms_iter_total) *ms_iter_total = mb->ms_iter;
+    if (n_iter) *n_iter = mb->n_iter;
+    return REGC_OK;
+}
+
+extern "C" void regc_mbar_destroy(regc_mbar *mb) { delete mb; }

@@ -1,0 +1,114 @@
+// regc_dev.h -- data layouts shared by the HIP kernels and the host runtime of
+// libregc_hip.so (internal; the public interface is include/regc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace regc {
+
+constexpr int kNStat = 10;
+constexpr int kWave = 64;
+constexpr int kMaxWalkersPerBlock = 8;
+
+// Per-class constants (one class = one REGC simulation: slab, box, grid).
+struct ClassDev {
+    double lx, ly, zlo, zhi;
+    double half_lx, half_ly, inv_lx, inv_ly;
+    double lnv;              // ln V, V = lx * ly * (zhi - zlo)
+    double slab_top;         // highest slab z (slab skipped above slab_top + rcut)
+    int n_max;
+    int trials;              // K trials per sweep
+    int walker_off, n_walkers;   // global walkers [walker_off, walker_off + n_walkers)
+    int state_off;           // global state index of this class's state 0 (== walker_off)
+    int n_t, n_mu;
+    // packed slab: entries [slab_off, slab_off + slab_len) of the slab arrays.
+    // Without bins: the atoms in input order.  With bins: ncx*ncy columns of
+    // `cap` entries each (padding entries sit at z = -1e4).
+    int slab_off, slab_len;
+    int bins;                // 0/1
+    int ncx, ncy, cap;
+    double inv_cw_x, inv_cw_y;
+    int stencil_off;         // offset into the stencil table: ncx*ncy*9 column ids
+};
+
+// Pair-potential constants, precomputed on the host.
+struct PotDev {
+    double sig2_gg, eps4_gg, shift_gg;
+    double sig2_gs, eps4_gs, shift_gs;
+    double rc2;
+    double hc2_gg, hc2_gs;   // (hc_frac * sigma)^2
+    int ideal;
+};
+
+struct SweepArgs {
+    const ClassDev *cls;
+    const int *block_class;      // per block
+    const int *block_w0;         // first global walker of the block
+    const int *block_nw;         // walkers in the block
+    int n_walkers;               // total walkers
+    PotDev pot;
+    int32_t *n;
+    double *e;
+    const int32_t *label;        // state index within the class
+    double *xyz;                 // [W][xyz_stride][3]
+    int xyz_stride;
+    const double *beta, *lnz;    // [S_total]
+    const double *lnk;           // log(k), k = 0 .. max n_max + 1
+    const double *slab4;         // packed slab as double4 (FP64 kernels)
+    const float *slab4f;         // packed slab as float4 (FP32 kernels)
+    const int16_t *stencil;      // column stencil tables
+    uint32_t key0, key1;
+    uint64_t th_disp, th_ins;
+    double max_disp;
+    int64_t sweep0;
+    int n_sweeps;
+    int sample_every;
+    int64_t rec_base;            // global record index of sample slot 0
+    double *samp_e;
+    int32_t *samp_n, *samp_s;
+    unsigned long long *hist;    // [S_total][hist_stride]
+    int hist_stride;
+    unsigned long long *stats;   // [S_total][kNStat]
+    uint32_t *trace_bits;        // [trace sweep][W][trace_words] or null
+    int32_t *trace_n;
+    int64_t trace_sweep0, trace_cap;
+    int trace_words;
+    int max_slab_len, max_stencil;  // LDS carve sizes of this launch
+    int gas_stride;                 // LDS entries per walker (max n_max over classes)
+};
+
+struct SwapArgs {
+    const ClassDev *cls;
+    int32_t *label;
+    int32_t *wos;                // [S_total] global walker holding global state
+    const int32_t *n;
+    const double *e;
+    const double *beta, *lnz;
+    uint32_t key0, key1;
+    int64_t q;                   // exchange step index
+    int scheme;
+    unsigned long long *att, *acc;   // [4][S_total]
+    int S_total;
+};
+
+struct EnergyArgs {
+    const ClassDev *cls;
+    const int *walker_class;
+    int n_walkers;
+    PotDev pot;
+    const int32_t *n;
+    const double *xyz;
+    int xyz_stride;
+    const double *slab4;         // unbinned packed slab (double4), per class at unb_off
+    const int *unb_off, *unb_len;
+    double *e_out;
+};
+
+// launchers (defined in the .hip files)
+hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int wpb, size_t smem, hipStream_t s);
+hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int wpb, size_t smem, hipStream_t s);
+hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
+hipError_t launch_energy_f64(const EnergyArgs &a, hipStream_t s);
+hipError_t launch_energy_f32(const EnergyArgs &a, hipStream_t s);
+
+}  // namespace regc

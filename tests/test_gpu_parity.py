@@ -1,0 +1,256 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+FP64 mode: identical accept/reject sequences and integer N trajectories, running
+energies within 1e-10 relative (different summation order only).  FP32 pair mode:
+per-configuration energies within 1e-5 relative of the FP64 oracle, long-run <N>
+within 3 standard errors.  Reweighting: free energies and reweighted averages
+against the naive FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_11118_amd import regc
+from paper_1908_11118_amd import workloads as W
+from tests.stats_util import batch_means, per_state_series
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    torch.cuda.set_device(0)
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _first_divergence(bits_a, bits_b, n_a, n_b):
+    d = np.argwhere(bits_a != bits_b)
+    if len(d):
+        s, w, word = d[0]
+        x = int(bits_a[s, w, word] ^ bits_b[s, w, word])
+        return f"sweep {s} walker {w} trial {32 * word + (x & -x).bit_length() - 1}"
+    d = np.argwhere(n_a != n_b)
+    if len(d):
+        return f"N differs at sweep {d[0][0]} walker {d[0][1]}"
+    return None
+
+
+def _fp64_trajectory(w, sweeps, **kw):
+    _say(f"[fp64 trajectory] {w.name} S={w.n_states} sweeps={sweeps} {kw}")
+    ref = oracle.Chain(w)
+    r = ref.run(sweeps, trace=True)
+    with regc.Regc(w, precision=regc.FP64, trace_capacity=sweeps, sample_capacity=0, **kw) as g:
+        g.run(sweeps)
+        bits, nps = g.trace(sweeps)
+        wk = g.walkers()
+        smp = g.samples()
+        st = g.stats()
+        hist = g.histograms()
+    where = _first_divergence(bits, r["bits"], nps, r["trace_n"])
+    assert where is None, f"trajectory diverges: {where}"
+    assert np.array_equal(wk["n"], ref.n)
+    assert np.array_equal(wk["label"], ref.label)
+    assert np.allclose(wk["e"], ref.e, rtol=1e-10, atol=1e-9)
+    for k in range(ref.S):
+        assert np.allclose(wk["xyz"][k, : ref.n[k]], ref.xyz[k, : ref.n[k]], rtol=0, atol=0)
+    assert np.array_equal(st["stats"], ref.stats)
+    assert np.array_equal(st["swap_att"], ref.swap_att)
+    assert np.array_equal(st["swap_acc"], ref.swap_acc)
+    assert np.array_equal(smp["n"], r["n"]) and np.array_equal(smp["state"], r["state"])
+    assert np.allclose(smp["e"], r["e"], rtol=1e-10, atol=1e-9)
+    if w.sample_every > 0:
+        ref_hist = np.zeros_like(hist)
+        np.add.at(ref_hist, (r["state"], r["n"]), 1)
+        assert np.array_equal(hist, ref_hist)
+    return ref, wk
+
+
+def test_fp64_trajectories_config1():
+    """64 replicas, 32-atom slab, N <= 40, 10^3 sweeps: bit-identical decisions."""
+    _fp64_trajectory(W.config1(), 1000)
+
+
+def test_fp64_trajectories_binned_slab_and_scheme1():
+    """6x6x3 slab (binned columns), odd grid sizes, diagonal swap scheme."""
+    w = W.config3_classes()[0].replace(t=W.linear_grid(0.6, 1.8, 4), mu=W.linear_grid(-6.0, -2.5, 4),
+                                       n_max=60, swap_scheme=1, sample_every=3)
+    _fp64_trajectory(w, 300)
+    w2 = w.replace(t=W.linear_grid(0.6, 1.8, 3), mu=W.linear_grid(-6.0, -2.5, 5), swap_scheme=0, seed=7)
+    _fp64_trajectory(w2, 200, slab_bins=-1)
+
+
+@pytest.mark.parametrize("wpb,spl", [(1, 1), (4, 3), (8, 0)])
+def test_fp64_invariant_to_launch_shape(wpb, spl):
+    w = W.small_lj(n_t=4, n_mu=4, n_max=20, n_sweeps=60)
+    _fp64_trajectory(w, 60, walkers_per_block=wpb, sweeps_per_launch=spl)
+
+
+def test_fp64_edge_cases():
+    # N capped at 1, one state, no exchange, K = 1 trial per sweep
+    _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=500).replace(swap_every=0), 500)
+    _fp64_trajectory(W.small_lj(n_t=2, n_mu=3, n_max=8).replace(trials_per_sweep=1), 300)
+    # no slab at all
+    _fp64_trajectory(W.small_lj(n_t=2, n_mu=2, n_max=15).replace(slab=np.zeros((0, 3))), 150)
+    # ideal gas mode
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300)
+
+
+def test_checkpoint_restore_continues_identically():
+    w = W.small_lj(n_t=2, n_mu=4, n_max=20)
+    _say("[checkpoint] small_lj 2x4")
+    with regc.Regc(w, sample_capacity=0) as a:
+        a.run(50)
+        blob = a.checkpoint()
+        a.run(70)
+        ref = a.walkers()
+        ref_st = a.stats()
+    with regc.Regc(w) as b:
+        b.restore(blob)
+        assert b.sweep == 50
+        b.run(70)
+        got = b.walkers()
+        st = b.stats()
+    for k in ("n", "label"):
+        assert np.array_equal(got[k], ref[k])
+    assert np.array_equal(got["e"], ref["e"])
+    assert np.array_equal(got["xyz"], ref["xyz"])
+    assert np.array_equal(st["stats"], ref_st["stats"])
+
+
+def test_capacity_and_state_errors():
+    w = W.small_lj(n_t=2, n_mu=2, n_max=10)
+    with regc.Regc(w, sample_capacity=4 * 5) as g:
+        g.run(5)
+        with pytest.raises(regc.RegcError) as ei:
+            g.run(1)
+        assert ei.value.code == regc.ECAPACITY
+        assert g.sweep == 5
+        g.clear_samples()
+        g.run(5)
+        assert g.sample_count() == 20
+
+
+# ---------------------------------------------------------------------------
+# FP32 pair mode
+# ---------------------------------------------------------------------------
+def test_fp32_configuration_energies_config2_scale():
+    """1024 replicas, 192-atom slab, N <= 200, the benchmark's launch shape: the
+    oracle re-evaluates sampled walkers' configurations in FP64."""
+    w = W.config2()
+    _say("[fp32 energies] config2 1024 walkers, 30 sweeps")
+    with regc.Regc(w, precision=regc.FP32PAIR, sample_capacity=0) as g:
+        g.run(30)
+        wk = g.walkers()
+        e_re = g.energies()
+    ch = oracle.Chain(w.replace(t=w.t[:1], mu=w.mu[:1]))
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([np.argsort(wk["n"])[-16:], rng.choice(len(wk["n"]), 24, replace=False)])
+    assert wk["n"].max() > 100
+    for k in idx:
+        ref = ch.energy(wk["xyz"][k, : wk["n"][k]])
+        tol = 1e-5 * max(1.0, abs(ref))
+        assert abs(e_re[k] - ref) <= tol, (k, e_re[k], ref)
+        assert abs(wk["e"][k] - ref) <= tol, (k, wk["e"][k], ref)
+
+
+def test_fp32_long_run_mean_n_within_3se():
+    w = W.small_lj(n_t=2, n_mu=3, n_max=24, t=(0.9, 1.4), mu=(-5.0, -3.0)).replace(sample_every=2)
+    sweeps, burn = 16000, 1000
+    _say(f"[fp32 statistics] small_lj 2x3, {sweeps} sweeps")
+    ref = oracle.Chain(w)
+    ref.run(burn)
+    r = ref.run(sweeps)
+    with regc.Regc(w, precision=regc.FP32PAIR, sample_capacity=(burn + sweeps) * 6) as g:
+        g.run(burn)
+        g.clear_samples()
+        g.run(sweeps)
+        s = g.samples()
+    n_ref, _ = per_state_series(r, ref.S)
+    n_gpu, _ = per_state_series(s, ref.S)
+    z = []
+    for k in range(ref.S):
+        m1, se1 = batch_means(n_ref[:, k])
+        m2, se2 = batch_means(n_gpu[:, k])
+        z.append((m2 - m1) / math.sqrt(se1 ** 2 + se2 ** 2 + 1e-12))
+    z = np.array(z)
+    assert np.all(np.abs(z) < 3.0), z
+
+
+# ---------------------------------------------------------------------------
+# Reweighting
+# ---------------------------------------------------------------------------
+def test_mbar_matches_oracle():
+    w = W.config1(400)
+    _say("[mbar] config1 400 sweeps")
+    with regc.Regc(w, precision=regc.FP64, sample_capacity=400 * 64) as g:
+        g.run(400)
+        s = g.samples()
+        mb = regc.Mbar(w.t, w.mu, w.n_max)
+        mb.load_run(g, 0, skip_records=40)
+    keep = slice(40 * 64, None)
+    e, n, st = s["e"][keep], s["n"][keep], s["state"][keep]
+    beta, lnz = oracle.state_arrays(w)
+    omega = np.bincount(st, minlength=len(beta))
+    f_ref, logd, ok, it, _ = oracle.mbar_solve(beta, lnz, omega, e, n, tol=1e-11, max_iter=20000)
+    f_gpu, conv, it_gpu, d = mb.solve(tol=1e-11, max_iter=20000)
+    assert ok and conv
+    assert np.max(np.abs(f_gpu - f_ref)) < 1e-7, np.max(np.abs(f_gpu - f_ref))
+    tt, tm = W.linear_grid(0.5, 2.0, 11), W.linear_grid(-8.0, -2.0, 13)
+    got = mb.targets(tt, tm)
+    TB = np.repeat(1.0 / tt, len(tm))
+    TZ = np.array([oracle.state_lnz(a, b) for a in tt for b in tm])
+    ref = oracle.mbar_targets(TB, TZ, e, n, logd, w.n_max)
+    assert np.allclose(got["mean_n"], ref["mean_n"], rtol=1e-7, atol=1e-7)
+    assert np.allclose(got["mean_e"], ref["mean_e"], rtol=1e-7, atol=1e-6)
+    assert np.allclose(got["mean_e2"], ref["mean_e2"], rtol=1e-7, atol=1e-5)
+    assert np.allclose(got["p_n"], ref["p_n"], atol=1e-8)
+    assert np.allclose(got["f"] - got["f"][0], ref["f"] - ref["f"][0], atol=1e-7)
+    # phase map: identical wherever the top two probabilities are distinguishable
+    srt = np.sort(ref["p_n"], axis=1)
+    clear = srt[:, -1] - srt[:, -2] > 1e-9
+    assert np.array_equal(got["phase"][clear], ref["phase"][clear])
+    mb.close()
+
+
+def test_mbar_ideal_gas_iid_samples():
+    """GPU reweighting of i.i.d. truncated-Poisson samples against the oracle on the
+    same samples, with an unsampled state and an empty N segment."""
+    rng = np.random.default_rng(4)
+    t, mu, V, n_max = np.array([1.0, 1.2, 1.5]), np.array([-4.6, -4.0, -3.4, -3.0]), 288.0, 45
+    es, ns, ss = [], [], []
+    for l, T in enumerate(t):
+        for m, u in enumerate(mu):
+            if (l, m) == (1, 2):
+                continue           # an unsampled state
+            zv = math.exp(u / T) * T ** 1.5 * V
+            k = np.arange(n_max + 1)
+            lp = k * math.log(zv) - np.array([math.lgamma(i + 1) for i in k])
+            p = np.exp(lp - lp.max())
+            p /= p.sum()
+            x = rng.choice(n_max + 1, 3000, p=p)
+            ns.append(x)
+            es.append(rng.normal(-0.3, 0.1, len(x)) * x)
+            ss.append(np.full(len(x), l * len(mu) + m))
+    e, n, st = np.concatenate(es), np.concatenate(ns).astype(np.int32), np.concatenate(ss).astype(np.int32)
+    beta = np.repeat(1 / t, len(mu))
+    lnz = np.array([oracle.state_lnz(T, u) for T in t for u in mu])
+    omega = np.bincount(st, minlength=len(beta))
+    f_ref, logd, ok, _, _ = oracle.mbar_solve(beta, lnz, omega, e, n, tol=1e-11)
+    mb = regc.Mbar(t, mu, n_max)
+    mb.set_samples(e, n, st)
+    f_gpu, conv, _, _ = mb.solve(tol=1e-11)
+    assert ok and conv and np.max(np.abs(f_gpu - f_ref)) < 1e-8
+    got = mb.targets(t, mu)
+    ref = oracle.mbar_targets(beta, lnz, e, n, logd, n_max)
+    assert np.allclose(got["mean_n"], ref["mean_n"], rtol=1e-9, atol=1e-9)
+    assert np.allclose(got["f"], ref["f"] - ref["f"][0] + got["f"][0], atol=1e-8)
+    mb.close()
