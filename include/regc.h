@@ -119,7 +119,11 @@ typedef struct {
  *  walkers_per_block  waves (one walker each) per workgroup, 1..8; 0 -> auto.
  *  sweeps_per_launch  upper bound of sweeps per kernel launch; 0 -> swap_every.
  *  slab_bins       -1 off, 1 on, 0 auto: slab atoms sorted into x-y columns no
- *                  narrower than rcut + max_disp; each trial scans the 3x3 stencil. */
+ *                  narrower than rcut + max_disp; each trial scans the 3x3 stencil.
+ *  split           wavefronts per walker: 1, 2, or 0 (auto: 1); with 2,
+ *                  walkers_per_block is 1.
+ *  cull            1: squared distances first, LJ terms only for pairs inside the
+ *                  cutoff (compacted in LDS); 0 or -1: every candidate in full. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -131,6 +135,8 @@ typedef struct {
     int walkers_per_block;
     int sweeps_per_launch;
     int slab_bins;
+    int split;
+    int cull;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;
@@ -209,8 +215,14 @@ int regc_clear_samples(regc_ctx *ctx);
  * total number of states (sum over classes); any pointer may be NULL. */
 int regc_get_stats(regc_ctx *ctx, int64_t *stats, int64_t *swap_att, int64_t *swap_acc);
 
-/* Histogram of recorded N per state: S_total x (n_max_class + 1) counts, classes
- * concatenated (class c uses its own n_max). */
+/* Work counters of the sweep kernel since create: candidates = pair terms
+ * evaluated (a displacement evaluates each candidate at the old and the new
+ * position, so it counts twice), within_cutoff = those with r < rcut.  Either
+ * pointer may be NULL. */
+int regc_get_pair_counts(regc_ctx *ctx, int64_t *candidates, int64_t *within_cutoff);
+
+/* Histogram of recorded N per state: S_total x (n_max_all + 1) counts, where
+ * n_max_all is the largest n_max over the classes. */
 int regc_get_histograms(regc_ctx *ctx, int64_t *n_hist);
 
 /* Accept-bit trace of the sweeps run since create/clear_trace:

@@ -48,7 +48,8 @@ struct regc_ctx {
     int W = 0, nmax_all = 0, kmax = 0, words = 1;
     PotDev potd{};
     hipStream_t stream = nullptr;
-    int wpb = 1, nblocks = 0, max_slab_len = 0, max_stencil = 0;
+    int wpb = 1, split = 1, nblocks = 0, max_slab_len = 0, max_stencil = 0, max_slab_scan = 0;
+    bool cull = false;
     size_t smem = 0;
 
     DevBuf<ClassDev> cls_d;
@@ -60,7 +61,7 @@ struct regc_ctx {
     DevBuf<double> samp_e;
     DevBuf<int32_t> samp_n, samp_s;
     int64_t rec_cap = 0, rec_base = 0, n_rec = 0;
-    DevBuf<unsigned long long> hist_d, stats_d, att_d, acc_d;
+    DevBuf<unsigned long long> hist_d, stats_d, att_d, acc_d, pairs_d;
     DevBuf<uint32_t> trace_bits_d;
     DevBuf<int32_t> trace_n_d;
     int64_t trace_cap = 0, trace_sweep0 = 0;
@@ -112,6 +113,8 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->walkers_per_block = 0;
     o->sweeps_per_launch = 0;
     o->slab_bins = 0;
+    o->split = 0;
+    o->cull = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -139,6 +142,7 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->swap_scheme == 0 || o->swap_scheme == 1, REGC_EUNSUPPORTED, "unknown swap scheme");
     REGC_CHECK(o->walkers_per_block >= 0 && o->walkers_per_block <= kMaxWalkersPerBlock, REGC_EINVAL,
                "walkers_per_block must be 0..%d", kMaxWalkersPerBlock);
+    REGC_CHECK(o->split >= 0 && o->split <= 2, REGC_EINVAL, "split must be 0, 1 or 2");
     return REGC_OK;
 }
 
@@ -274,27 +278,35 @@ static int ctx_alloc_and_init(regc_ctx *c)
         d.stencil_off = (int)stencil.size();
         stencil.insert(stencil.end(), h.stencil.begin(), h.stencil.end());
         max_slab_len = std::max(max_slab_len, len);
+        c->max_slab_scan = std::max(c->max_slab_scan, h.bins ? 9 * h.cap : len);
         max_stencil = std::max(max_stencil, (int)h.stencil.size());
     }
     c->max_slab_len = max_slab_len;
     c->max_stencil = max_stencil;
 
-    // launch shape: walkers per block, LDS
+    // launch shape: walkers per block, waves per walker, LDS
     int dev = 0;
     REGC_HIP(hipGetDevice(&dev));
-    int lds_max = 0;
+    int lds_max = 0, n_cu = 0;
     REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t real4 = o.precision == REGC_FP64 ? 32 : 16;
+    REGC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int real = o.precision == REGC_FP64 ? 8 : 4;
+    // one wave per walker unless asked: two waves per walker measured within noise
+    // of one at 1024 walkers on 256 CUs (the barrier costs what the latency hiding gains)
+    int split = o.split > 0 ? o.split : 1;
+    (void)n_cu;
+    const bool cull = o.cull > 0;
     auto smem_for = [&](int wpb) {
-        return (size_t)max_slab_len * real4 + (((size_t)max_stencil * 2 + 31) & ~(size_t)31) +
-               (size_t)wpb * nmax * real4;
+        return lds_layout(max_slab_len, max_stencil, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
     };
-    int wpb = o.walkers_per_block;
+    int wpb = split == 2 ? 1 : o.walkers_per_block;
     if (wpb == 0) wpb = W >= 1024 ? 4 : 1;
     while (wpb > 1 && smem_for(wpb) > (size_t)lds_max) --wpb;
     REGC_CHECK(smem_for(wpb) <= (size_t)lds_max, REGC_EUNSUPPORTED,
                "one walker needs %zu bytes of LDS, the device allows %d", smem_for(wpb), lds_max);
     c->wpb = wpb;
+    c->split = split;
+    c->cull = cull;
     c->smem = smem_for(wpb);
     std::vector<int> bcls, bw0, bnw;
     c->walker_class.assign(W, 0);
@@ -341,7 +353,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->stencil_d.alloc(stencil.size())) || (rc = c->samp_e.alloc((size_t)rec_cap * W)) ||
         (rc = c->samp_n.alloc((size_t)rec_cap * W)) || (rc = c->samp_s.alloc((size_t)rec_cap * W)) ||
         (rc = c->hist_d.alloc((size_t)W * (nmax + 1))) || (rc = c->stats_d.alloc((size_t)W * kNStat)) ||
-        (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) ||
+        (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) || (rc = c->pairs_d.alloc(2)) ||
         (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
         (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)))
         return rc;
@@ -369,6 +381,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
     REGC_HIP(hipMemset(c->stats_d.p, 0, sizeof(unsigned long long) * (size_t)W * kNStat));
     REGC_HIP(hipMemset(c->att_d.p, 0, sizeof(unsigned long long) * 4 * W));
     REGC_HIP(hipMemset(c->acc_d.p, 0, sizeof(unsigned long long) * 4 * W));
+    REGC_HIP(hipMemset(c->pairs_d.p, 0, sizeof(unsigned long long) * 2));
     REGC_HIP(hipDeviceSynchronize());
     return REGC_OK;
 }
@@ -484,6 +497,7 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
     a.hist = c->hist_d.p;
     a.hist_stride = c->nmax_all + 1;
     a.stats = c->stats_d.p;
+    a.pairs = c->pairs_d.p;
     a.trace_bits = c->trace_cap > 0 ? c->trace_bits_d.p : nullptr;
     a.trace_n = c->trace_cap > 0 ? c->trace_n_d.p : nullptr;
     a.trace_sweep0 = c->trace_sweep0;
@@ -492,12 +506,13 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
     a.max_slab_len = c->max_slab_len;
     a.max_stencil = c->max_stencil;
     a.gas_stride = c->nmax_all;
+    a.max_slab_scan = c->max_slab_scan;
     int rc;
     if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
     if (c->opts.precision == REGC_FP64)
-        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb, c->smem, c->stream));
+        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, c->stream));
     else
-        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb, c->smem, c->stream));
+        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, c->stream));
     if (c->timing && (rc = record_event(c, c->ev_sweep, false))) return rc;
     return REGC_OK;
 }
@@ -709,6 +724,17 @@ extern "C" int regc_get_stats(regc_ctx *c, int64_t *stats, int64_t *swap_att, in
     if (stats) REGC_HIP(hipMemcpy(stats, c->stats_d.p, sizeof(int64_t) * (size_t)c->W * kNStat, hipMemcpyDeviceToHost));
     if (swap_att) REGC_HIP(hipMemcpy(swap_att, c->att_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
     if (swap_acc) REGC_HIP(hipMemcpy(swap_acc, c->acc_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_get_pair_counts(regc_ctx *c, int64_t *candidates, int64_t *within_cutoff)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    unsigned long long h[2];
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy(h, c->pairs_d.p, sizeof h, hipMemcpyDeviceToHost));
+    if (candidates) *candidates = (int64_t)h[0];
+    if (within_cutoff) *within_cutoff = (int64_t)h[1];
     return REGC_OK;
 }
 

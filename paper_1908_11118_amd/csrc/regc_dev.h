@@ -69,12 +69,14 @@ struct SweepArgs {
     unsigned long long *hist;    // [S_total][hist_stride]
     int hist_stride;
     unsigned long long *stats;   // [S_total][kNStat]
+    unsigned long long *pairs;   // [0] candidate pairs evaluated, [1] of them inside the cutoff
     uint32_t *trace_bits;        // [trace sweep][W][trace_words] or null
     int32_t *trace_n;
     int64_t trace_sweep0, trace_cap;
     int trace_words;
     int max_slab_len, max_stencil;  // LDS carve sizes of this launch
     int gas_stride;                 // LDS entries per walker (max n_max over classes)
+    int max_slab_scan;              // most slab candidates one trial scans (max over classes)
 };
 
 struct SwapArgs {
@@ -104,9 +106,36 @@ struct EnergyArgs {
     double *e_out;
 };
 
+// LDS carve of the sweep kernel (byte offsets, 32-byte aligned), shared by the
+// kernel and the host launch code: class slab, stencil table, ln k table, the
+// split-walker exchange slots, the walkers' gas coordinates, the pair queues.
+struct LdsLayout {
+    size_t slab, stencil, lnk, xch, gas, queue, total;
+};
+
+__host__ __device__ inline size_t lds_round(size_t x) { return (x + 31) & ~(size_t)31; }
+
+__host__ __device__ inline LdsLayout lds_layout(int max_slab_len, int max_stencil, int gas_stride, int max_slab_scan,
+                                                int walkers, int queue_waves, int real_size)
+{
+    LdsLayout L;
+    const size_t r4 = 4 * (size_t)real_size;
+    size_t off = 0;
+    L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
+    L.stencil = off; off = lds_round(off + (size_t)max_stencil * 2);
+    L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
+    L.xch = off;     off = lds_round(off + (size_t)walkers * 8 * 8);
+    L.gas = off;     off = lds_round(off + (size_t)walkers * gas_stride * r4);
+    L.queue = off;   off = lds_round(off + (size_t)queue_waves * (2 * gas_stride + 2 * max_slab_scan) * real_size);
+    L.total = off;
+    return L;
+}
+
 // launchers (defined in the .hip files)
-hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int wpb, size_t smem, hipStream_t s);
-hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int wpb, size_t smem, hipStream_t s);
+hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
+                            hipStream_t s);
+hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
+                            hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs &a, hipStream_t s);
 hipError_t launch_energy_f32(const EnergyArgs &a, hipStream_t s);

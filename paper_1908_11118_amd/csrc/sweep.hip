@@ -1,13 +1,14 @@
 // sweep.hip -- the REGC sweep kernel: K grand-canonical / displacement trials per
-// sweep for every walker, one wavefront (64 lanes) per walker, its gas
-// coordinates and its class's frozen slab resident in LDS for the whole launch.
+// sweep for every walker, its gas coordinates and its class's frozen slab resident
+// in LDS for the whole launch; plus the full energy recomputation kernel.
 //
 // This file is compiled twice:
 //   -DREGC_FP64 with -ffp-contract=off : every operation in FP64 (trajectory-parity
-//                                        mode; the same decisions as a sequential
-//                                        FP64 reference up to summation order and exp);
-//   -DREGC_FP32                        : pair terms and their per-lane sums in FP32,
-//                                        running energy, acceptance test in FP64.
+//                                        mode: the same decisions as a sequential FP64
+//                                        evaluation up to summation order and the last
+//                                        bit of log);
+//   -DREGC_FP32                        : pair terms and their per-lane sums in FP32;
+//                                        running energy and acceptance test in FP64.
 //
 // Per trial (arXiv:1908.11118, Sec. II.A.1 and II.A.3):
 //   move type from word A0 (displacement / insertion / removal, thresholds set
@@ -16,28 +17,41 @@
 //   insertion at a uniform point of V, Eq. (3) with the exponent read as
 //   beta [mu - (E_{N+1} - E_N)]: ln A = ln z + ln V - ln(N+1) - beta dE;
 //   removal, Eq. (2): ln A = ln N - ln z - ln V - beta dE;
-//   accept when ln A >= 0 or U53 < exp(ln A).
-// dE is the sum of LJ pair terms of the moved particle over the other gas atoms
-// (lanes stride over them) and over the slab atoms (all of them, or the 3x3
-// stencil of x-y columns around the particle), reduced across the wave.
-// Storage rule: insertion appends, removal moves the last particle into the
-// freed slot.
+//   accept when U53 <= min(1, A), evaluated as dE <= (ln prefactor - ln U) / beta.
+// dE sums LJ pair terms of the moved particle over the other gas atoms and over
+// the slab atoms (all of them, or the 3x3 stencil of x-y columns around the
+// particle).  Storage rule: insertion appends, removal moves the last particle
+// into the freed slot.
+//
+// Launch variants (template parameters):
+//   SPLIT = 1: one wavefront per walker, several walkers per workgroup;
+//   SPLIT = 2: one walker per workgroup of two wavefronts; each takes half of the
+//              candidates, the two partial sums meet in LDS behind a barrier, both
+//              waves then take the same decision.  Two waves per SIMD hide latency
+//              when walkers are as few as SIMDs.
+//   CULL  = false: every candidate pair is evaluated in full;
+//   CULL  = true : a first pass computes squared distances only and queues the pairs
+//              inside the cutoff in LDS (compacted across the wave); the LJ terms are
+//              evaluated on the queue only.
 #include "regc_dev.h"
 #include "philox_dev.h"
 
 namespace regc {
 
+// Each compilation of this file gets its own namespace: the kernels are templates
+// with the same names in both precisions, and one symbol per precision must reach
+// the code-object registry.
 #if defined(REGC_FP64)
+namespace fp64 {
 typedef double Real;
 struct alignas(32) Real4 { double x, y, z, w; };
-#define SWEEP_KERNEL sweep_kernel_f64
 #define SWEEP_LAUNCH launch_sweep_f64
 #define ENERGY_KERNEL energy_kernel_f64
 #define ENERGY_LAUNCH launch_energy_f64
 #elif defined(REGC_FP32)
+namespace fp32 {
 typedef float Real;
 struct alignas(16) Real4 { float x, y, z, w; };
-#define SWEEP_KERNEL sweep_kernel_f32
 #define SWEEP_LAUNCH launch_sweep_f32
 #define ENERGY_KERNEL energy_kernel_f32
 #define ENERGY_LAUNCH launch_energy_f32
@@ -72,23 +86,63 @@ struct Pair {
     Real sig2, eps4, shift, rc2, hc2;
 };
 
-__device__ __forceinline__ Real lj(Real r2, const Pair &p)
+// truncated-shifted LJ 12-6 at squared distance r2 (r2 < rc2 is the caller's business)
+__device__ __forceinline__ Real lj_inside(Real r2, Real sig2, Real eps4, Real shift)
 {
 #if defined(REGC_FP64)
-    const double s2 = p.sig2 / r2;
+    const double s2 = sig2 / r2;
 #else
-    const float s2 = p.sig2 * __builtin_amdgcn_rcpf(r2);
+    const float s2 = sig2 * __builtin_amdgcn_rcpf(r2);
 #endif
     const Real s6 = s2 * s2 * s2;
-    const Real v = p.eps4 * (s6 * s6 - s6) - p.shift;
+    return eps4 * (s6 * s6 - s6) - shift;
+}
+
+__device__ __forceinline__ Real lj(Real r2, const Pair &p)
+{
+    const Real v = lj_inside(r2, p.sig2, p.eps4, p.shift);
     return r2 < p.rc2 ? v : Real(0);
 }
 
-__device__ __forceinline__ Real wave_sum(Real v)
+// Wave-wide sum with DPP (quad permutes, row mirrors, row broadcasts); the total
+// ends in lane 63 and is read back as a wave-uniform value.  The order of the
+// additions is fixed, so the result is deterministic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += dpp_f32<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f32<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_f32<0x140, 0xF>(v);   // row_mirror
+    v += dpp_f32<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_f32<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    v += dpp_f64<0x141, 0xF>(v);
+    v += dpp_f64<0x140, 0xF>(v);
+    v += dpp_f64<0x142, 0xA>(v);
+    v += dpp_f64<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -98,12 +152,28 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Keep a wave-uniform constant in a VGPR: the hot loop has more uniform values
+// than SGPRs, and VALU operands read from VGPRs cost no scalar-register spills.
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 __device__ __forceinline__ uint32_t bcast(uint32_t v, int lane)
 {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// Slab access: all atoms, or the 3x3 column stencil around (cx, cy).
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Slab access: all atoms, or the 3x3 column stencil around a column.
 struct SlabView {
     const Real4 *atoms;
     const int16_t *stencil;   // [ncol][9]
@@ -123,52 +193,144 @@ __device__ __forceinline__ int column_of(const SlabView &sv, Real x, Real y)
     return cy * sv.ncx + cx;
 }
 
-// Sum over slab candidates of lj(p) (and of lj(q) when TWO), lanes striding.
-template <bool TWO>
-__device__ __forceinline__ void slab_terms(const SlabView &sv, const Box &b, const Pair &pp, int lane,
-                                           Real px, Real py, Real pz, Real qx, Real qy, Real qz,
-                                           Real cxp, Real cyp, Real &acc_p, Real &acc_q, bool &core)
+// Appends the lanes' values whose predicate holds to an LDS queue (wave-wide
+// compaction): each lane's slot is the number of set predicate bits below it.
+__device__ __forceinline__ void push(Real *queue, int &count, bool pred, Real value)
 {
-    if (!sv.bins) {
-        for (int k = lane; k < sv.len; k += kWave) {
-            const Real4 a = sv.atoms[k];
-            const Real r2 = dist2(b, px, py, pz, a);
-            core |= r2 < pp.hc2;
-            acc_p += lj(r2, pp);
-            if (TWO) acc_q += lj(dist2(b, qx, qy, qz, a), pp);
+    const uint64_t mask = __ballot(pred);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    if (pred) queue[count + (int)below] = value;
+    count += __popcll(mask);
+}
+
+// One candidate atom g (mask m): pair terms of the new position p (NEW, added) and
+// of the old position q (OLD, subtracted).  CULL queues the in-cutoff squared
+// distances (old ones negated) instead of evaluating them.
+template <bool NEW, bool OLD, bool CULL>
+__device__ __forceinline__ void candidate(const Box &b, const Pair &pp, bool m, const Real4 &g, Real px, Real py,
+                                          Real pz, Real qx, Real qy, Real qz, Real &acc, bool &core,
+                                          uint32_t &useful, Real *queue, int &count)
+{
+    if (NEW) {
+        const Real r2 = dist2(b, px, py, pz, g);
+        core |= m && r2 < pp.hc2;
+        if (CULL) {
+            push(queue, count, m && r2 < pp.rc2, r2);
+        } else {
+            useful += m && r2 < pp.rc2;
+            acc += m ? lj(r2, pp) : Real(0);
         }
-    } else {
-        const int16_t *st = sv.stencil + column_of(sv, cxp, cyp) * 9;
-        const int total = 9 * sv.cap;
-        for (int k = lane; k < total; k += kWave) {
-            const int sp = (int)(((float)k + 0.5f) * sv.inv_cap);
-            const int slot = k - sp * sv.cap;
-            const Real4 a = sv.atoms[(int)st[sp] * sv.cap + slot];
-            const Real r2 = dist2(b, px, py, pz, a);
-            core |= r2 < pp.hc2;
-            acc_p += lj(r2, pp);
-            if (TWO) acc_q += lj(dist2(b, qx, qy, qz, a), pp);
+    }
+    if (OLD) {
+        const Real r2 = dist2(b, qx, qy, qz, g);
+        if (CULL) {
+            push(queue, count, m && r2 < pp.rc2, -r2);
+        } else {
+            useful += m && r2 < pp.rc2;
+            acc -= m ? lj(r2, pp) : Real(0);
         }
     }
 }
 
-__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) SWEEP_KERNEL(SweepArgs a)
+// This wave's part of the energy change of a trial: sum over the other gas atoms
+// (all j < n except `skip`) and over the slab candidates of phi(|p - r|) (NEW)
+// minus phi(|q - r|) (OLD).  The wave with index `part` of SPLIT takes every
+// SPLIT-th block of candidates; trip counts are wave-uniform.  Returns the
+// wave-uniform partial sum; `core_out` is this wave's hard-core flag.
+template <bool NEW, bool OLD, int SPLIT, bool CULL>
+__device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip, const SlabView &sv, const Box &b,
+                                              const Pair &gg, const Pair &gs, int lane, int part, Real px, Real py,
+                                              Real pz, Real qx, Real qy, Real qz, Real *qgas, Real *qslab,
+                                              bool &core_out, uint32_t &useful)
+{
+    constexpr int U = SPLIT == 1 ? 2 : 1;   // candidates per lane per step
+    constexpr int STEP = SPLIT * U * kWave;
+    Real acc = 0;
+    bool core = false;
+    int ng = 0, ns = 0;
+    for (int j0 = part * U * kWave; j0 < n; j0 += STEP) {
+        const int j = j0 + lane;
+        const bool v1 = j < n;
+        const Real4 ga = gas[v1 ? j : 0];
+        if (U == 2) {
+            const int j2 = j + kWave;
+            const bool v2 = j2 < n;
+            const Real4 gb = gas[v2 ? j2 : 0];
+            candidate<NEW, OLD, CULL>(b, gg, v1 && j != skip, ga, px, py, pz, qx, qy, qz, acc, core, useful, qgas, ng);
+            candidate<NEW, OLD, CULL>(b, gg, v2 && j2 != skip, gb, px, py, pz, qx, qy, qz, acc, core, useful, qgas,
+                                      ng);
+        } else {
+            candidate<NEW, OLD, CULL>(b, gg, v1 && j != skip, ga, px, py, pz, qx, qy, qz, acc, core, useful, qgas, ng);
+        }
+    }
+    const Real zmin = (NEW && OLD) ? (pz < qz ? pz : qz) : (NEW ? pz : qz);
+    if (zmin < sv.top_plus_rc) {
+        const bool bins = sv.bins != 0;
+        const int16_t *st = sv.stencil + (bins ? column_of(sv, OLD ? qx : px, OLD ? qy : py) * 9 : 0);
+        const int total = bins ? 9 * sv.cap : sv.len;
+        for (int k0 = part * U * kWave; k0 < total; k0 += STEP) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u * kWave + lane;
+                const bool v = k < total;
+                const int kk = v ? k : 0;
+                int idx = kk;
+                if (bins) {
+                    const int sp = (int)(((float)kk + 0.5f) * sv.inv_cap);
+                    idx = (int)st[sp] * sv.cap + (kk - sp * sv.cap);
+                }
+                const Real4 g = sv.atoms[idx];
+                candidate<NEW, OLD, CULL>(b, gs, v, g, px, py, pz, qx, qy, qz, acc, core, useful, qslab, ns);
+            }
+        }
+    }
+    core_out = __any(core);
+    if (CULL) {
+        useful += lane == 0 ? (uint32_t)(ng + ns) : 0u;
+        wave_sync();
+        // LJ terms of the queued pairs: gas pairs, then slab pairs, in one lane space
+        const int nq = ng + ns;
+        for (int k0 = 0; k0 < nq; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < nq) {
+                const bool is_gas = k < ng;
+                const Real v = is_gas ? qgas[k] : qslab[k - ng];
+                const Real r2 = v < Real(0) ? -v : v;
+                const Real phi = lj_inside(r2, is_gas ? gg.sig2 : gs.sig2, is_gas ? gg.eps4 : gs.eps4,
+                                           is_gas ? gg.shift : gs.shift);
+                acc += v < Real(0) ? -phi : phi;
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
+template <int SPLIT, bool CULL>
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(SweepArgs a)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
+    const int slot = wave / SPLIT;              // walker within the block
+    const int part = wave % SPLIT;              // this wave's share of the candidates
+    const int waves = blockDim.x / kWave;
     const int blk = blockIdx.x;
     const int cid = a.block_class[blk];
     const ClassDev &C = a.cls[cid];
     const int nw = a.block_nw[blk];
 
-    Real4 *slab = reinterpret_cast<Real4 *>(smem);
-    int16_t *stencil = reinterpret_cast<int16_t *>(smem + (size_t)a.max_slab_len * sizeof(Real4));
-    size_t st_bytes = ((size_t)a.max_stencil * sizeof(int16_t) + 31) & ~(size_t)31;
-    Real4 *gas = reinterpret_cast<Real4 *>(smem + (size_t)a.max_slab_len * sizeof(Real4) + st_bytes) +
-                 (size_t)wave * a.gas_stride;
+    const LdsLayout L = lds_layout(a.max_slab_len, a.max_stencil, a.gas_stride, a.max_slab_scan, waves / SPLIT,
+                                   CULL ? waves : 0, (int)sizeof(Real));
+    Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
+    int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
+    double *lnk = reinterpret_cast<double *>(smem + L.lnk);
+    double *xch = reinterpret_cast<double *>(smem + L.xch) + slot * 8;     // [parity][part][value, core]
+    Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)slot * a.gas_stride;
+    Real *qgas = reinterpret_cast<Real *>(smem + L.queue) + (size_t)wave * (2 * a.gas_stride + 2 * a.max_slab_scan);
+    Real *qslab = qgas + 2 * a.gas_stride;
 
-    // ---- class slab and stencil into LDS (shared by the block's walkers) ----
+    // ---- class slab, stencil and log table into LDS (shared by the block) ----
     const int slab_len = C.slab_len;
     for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
 #if defined(REGC_FP64)
@@ -182,10 +344,11 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) SWEEP_KERNEL(Swee
     }
     const int n_st = C.bins ? C.ncx * C.ncy * 9 : 0;
     for (int k = threadIdx.x; k < n_st; k += blockDim.x) stencil[k] = a.stencil[C.stencil_off + k];
+    for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
     __syncthreads();
-    if (wave >= nw) return;
+    if (slot >= nw) return;    // (SPLIT == 2 blocks always hold one walker)
 
-    const int w = a.block_w0[blk] + wave;
+    const int w = a.block_w0[blk] + slot;
     const int n_max = C.n_max;
     const int K = C.trials;
 
@@ -196,37 +359,43 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) SWEEP_KERNEL(Swee
     const int sg = C.state_off + label;
     const double beta = a.beta[sg];
     const double lnz = a.lnz[sg];
-    const double lnzv = lnz + C.lnv;
+    const double lnzv = in_vgpr(lnz + C.lnv);
     {
         const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
-        for (int k = lane; k < n; k += kWave) {
+        for (int k = part * kWave + lane; k < n; k += SPLIT * kWave) {
             Real4 v;
             v.x = (Real)src[3 * k]; v.y = (Real)src[3 * k + 1]; v.z = (Real)src[3 * k + 2]; v.w = 0;
             gas[k] = v;
         }
     }
-    wave_sync();
+    if (SPLIT == 1) wave_sync(); else __syncthreads();
 
     Box b;
-    b.lx = (Real)C.lx; b.ly = (Real)C.ly; b.hx = (Real)C.half_lx; b.hy = (Real)C.half_ly;
-    b.ix = (Real)C.inv_lx; b.iy = (Real)C.inv_ly;
+    b.lx = in_vgpr((Real)C.lx); b.ly = in_vgpr((Real)C.ly);
+    b.hx = in_vgpr((Real)C.half_lx); b.hy = in_vgpr((Real)C.half_ly);
+    b.ix = in_vgpr((Real)C.inv_lx); b.iy = in_vgpr((Real)C.inv_ly);
     Pair gg, gs;
-    gg.sig2 = (Real)a.pot.sig2_gg; gg.eps4 = (Real)a.pot.eps4_gg; gg.shift = (Real)a.pot.shift_gg;
-    gg.rc2 = (Real)a.pot.rc2; gg.hc2 = (Real)a.pot.hc2_gg;
-    gs.sig2 = (Real)a.pot.sig2_gs; gs.eps4 = (Real)a.pot.eps4_gs; gs.shift = (Real)a.pot.shift_gs;
-    gs.rc2 = (Real)a.pot.rc2; gs.hc2 = (Real)a.pot.hc2_gs;
+    gg.sig2 = in_vgpr((Real)a.pot.sig2_gg); gg.eps4 = in_vgpr((Real)a.pot.eps4_gg);
+    gg.shift = in_vgpr((Real)a.pot.shift_gg); gg.rc2 = in_vgpr((Real)a.pot.rc2); gg.hc2 = in_vgpr((Real)a.pot.hc2_gg);
+    gs.sig2 = in_vgpr((Real)a.pot.sig2_gs); gs.eps4 = in_vgpr((Real)a.pot.eps4_gs);
+    gs.shift = in_vgpr((Real)a.pot.shift_gs); gs.rc2 = gg.rc2; gs.hc2 = in_vgpr((Real)a.pot.hc2_gs);
     const bool ideal = a.pot.ideal != 0;
     SlabView sv;
     sv.atoms = slab; sv.stencil = stencil; sv.len = slab_len; sv.bins = C.bins;
-    sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap; sv.inv_cap = C.bins ? 1.0f / (float)C.cap : 0.f;
-    sv.inv_cw_x = (Real)C.inv_cw_x; sv.inv_cw_y = (Real)C.inv_cw_y;
-    sv.top_plus_rc = (Real)(C.slab_top + sqrt(a.pot.rc2));
-    const double lx = C.lx, ly = C.ly, zlo = C.zlo, zhi = C.zhi, H = C.zhi - C.zlo;
-    const double md = a.max_disp;
+    sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
+    sv.inv_cap = in_vgpr(C.bins ? 1.0f / (float)C.cap : 0.f);
+    sv.inv_cw_x = in_vgpr((Real)C.inv_cw_x); sv.inv_cw_y = in_vgpr((Real)C.inv_cw_y);
+    sv.top_plus_rc = in_vgpr((Real)(C.slab_top + sqrt(a.pot.rc2)));
+    const double lx = in_vgpr(C.lx), ly = in_vgpr(C.ly), zlo = in_vgpr(C.zlo), zhi = in_vgpr(C.zhi);
+    const double H = in_vgpr(C.zhi - C.zlo);
+    const double md = in_vgpr(a.max_disp);
+    const double tinv = in_vgpr(1.0 / beta);
+    const int slab_scan = C.bins ? 9 * C.cap : slab_len;
 
-    uint32_t st_cnt[kNStat];
-#pragma unroll
-    for (int k = 0; k < kNStat; ++k) st_cnt[k] = 0;
+    uint32_t stat = 0;     // lane k < kNStat holds counter k
+    uint32_t useful = 0;   // per lane: evaluated pairs inside the cutoff
+    uint64_t cand = 0;     // wave-uniform: candidate pairs of all parts
+    uint32_t xcount = 0;   // exchanges so far: consecutive exchanges use alternate slots
 
     for (int it = 0; it < a.n_sweeps; ++it) {
         const int64_t sweep = a.sweep0 + it;
@@ -237,149 +406,120 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) SWEEP_KERNEL(Swee
             const uint4 R = philox4x32_10(
                 make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)sweep, (uint32_t)w, (uint32_t)(lane & 1)),
                 a.key0, a.key1);
+            // FP64 uniforms of the batch, lane-parallel: on A lanes f0, f1 are the x, y
+            // uniforms (A2, A3); on B lanes f2 is the z uniform (B0) and f3 = ln U (B1, B2).
+            const double f0 = uniform_open(R.z), f1 = uniform_open(R.w), f2 = uniform_open(R.x);
+            const double f3 = log(uniform53(R.y, R.z));
             const int tn = K - t0 < 32 ? K - t0 : 32;
             uint32_t bits = 0;
             for (int tt = 0; tt < tn; ++tt) {
                 const uint32_t A0 = bcast(R.x, 2 * tt), A1 = bcast(R.y, 2 * tt);
-                const uint32_t A2 = bcast(R.z, 2 * tt), A3 = bcast(R.w, 2 * tt);
-                const uint32_t B0 = bcast(R.x, 2 * tt + 1), B1 = bcast(R.y, 2 * tt + 1);
-                const uint32_t B2 = bcast(R.z, 2 * tt + 1);
-                const double U = uniform53(B1, B2);
+                // move type: 0 displacement, 1 insertion, 2 removal
+                const int kind = (uint64_t)A0 < a.th_disp ? 0 : ((uint64_t)A0 < a.th_ins ? 1 : 2);
+                stat += lane == 2 * kind;
                 bool accepted = false;
-                if ((uint64_t)A0 < a.th_disp) {
-                    // ---------------- displacement ----------------
-                    st_cnt[0]++;
-                    if (n == 0) {
-                        st_cnt[7]++;
-                    } else {
-                        const int i = (int)(((uint64_t)A1 * (uint64_t)n) >> 32);
-                        const Real4 o = gas[i];
-                        double px = (double)o.x + md * (2.0 * uniform_open(A2) - 1.0);
-                        double py = (double)o.y + md * (2.0 * uniform_open(A3) - 1.0);
-                        const double pz = (double)o.z + md * (2.0 * uniform_open(B0) - 1.0);
+                if (kind == 1 ? n >= n_max : n == 0) {
+                    stat += lane == (kind == 1 ? 6 : 7);          // cap / empty
+                } else {
+                    const double lnU = bcast(f3, 2 * tt + 1);
+                    const double ux = bcast(f0, 2 * tt), uy = bcast(f1, 2 * tt), uz = bcast(f2, 2 * tt + 1);
+                    const int i = kind == 1 ? -1 : (int)(((uint64_t)A1 * (uint64_t)n) >> 32);
+                    const Real4 o = gas[kind == 1 ? 0 : i];
+                    double px = 0.0, py = 0.0, pz = 0.0, c;
+                    bool wall = false;
+                    if (kind == 0) {
+                        px = (double)o.x + md * (2.0 * ux - 1.0);
+                        py = (double)o.y + md * (2.0 * uy - 1.0);
+                        pz = (double)o.z + md * (2.0 * uz - 1.0);
                         if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
                         if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
-                        if (pz < zlo || pz > zhi) {
-                            st_cnt[8]++;
-                        } else {
-                            const Real qx = (Real)px, qy = (Real)py, qz = (Real)pz;
-                            double de = 0.0;
-                            bool core = false;
-                            if (!ideal) {
-                                Real en = 0, eo = 0;
-                                for (int j = lane; j < n; j += kWave) {
-                                    if (j == i) continue;
-                                    const Real4 g = gas[j];
-                                    const Real r2n = dist2(b, qx, qy, qz, g);
-                                    core |= r2n < gg.hc2;
-                                    en += lj(r2n, gg);
-                                    eo += lj(dist2(b, o.x, o.y, o.z, g), gg);
-                                }
-                                const Real zmin = qz < o.z ? qz : o.z;
-                                if (zmin < sv.top_plus_rc)
-                                    slab_terms<true>(sv, b, gs, lane, qx, qy, qz, o.x, o.y, o.z, o.x, o.y, en, eo,
-                                                     core);
-#if defined(REGC_FP64)
-                                const double sn = wave_sum(en), so = wave_sum(eo);
-                                de = sn - so;
-#else
-                                de = (double)wave_sum(en - eo);
-#endif
-                                core = __any(core);
-                            }
-                            if (core) {
-                                st_cnt[9]++;
-                            } else {
-                                accepted = metropolis(-beta * de, U);
-                                if (accepted) {
-                                    if (lane == 0) {
-                                        Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
-                                        gas[i] = v;
-                                    }
-                                    e += de;
-                                    st_cnt[1]++;
-                                }
-                            }
-                        }
-                    }
-                } else if ((uint64_t)A0 < a.th_ins) {
-                    // ---------------- insertion ----------------
-                    st_cnt[2]++;
-                    if (n >= n_max) {
-                        st_cnt[6]++;
+                        wall = pz < zlo || pz > zhi;
+                        c = 0.0;
+                    } else if (kind == 1) {
+                        px = lx * ux;
+                        py = ly * uy;
+                        pz = zlo + H * uz;
+                        c = lnzv - lnk[n + 1];                    // ln z V / (N+1)
                     } else {
-                        const Real qx = (Real)(lx * uniform_open(A2));
-                        const Real qy = (Real)(ly * uniform_open(A3));
-                        const Real qz = (Real)(zlo + H * uniform_open(B0));
+                        c = lnk[n] - lnzv;                        // ln N / (z V)
+                    }
+                    if (wall) {
+                        stat += lane == 8;
+                    } else {
+                        // accept iff ln U <= ln prefactor - beta dE (U <= min(1, A))
+                        const double thr = (c - lnU) * tinv;
+                        const Real qx = (Real)px, qy = (Real)py, qz = (Real)pz;
                         double de = 0.0;
                         bool core = false;
                         if (!ideal) {
-                            Real en = 0, dummy = 0;
-                            for (int j = lane; j < n; j += kWave) {
-                                const Real r2 = dist2(b, qx, qy, qz, gas[j]);
-                                core |= r2 < gg.hc2;
-                                en += lj(r2, gg);
-                            }
-                            if (qz < sv.top_plus_rc)
-                                slab_terms<false>(sv, b, gs, lane, qx, qy, qz, qx, qy, qz, qx, qy, en, dummy, core);
-                            de = (double)wave_sum(en);
-                            core = __any(core);
-                        }
-                        if (core) {
-                            st_cnt[9]++;
-                        } else {
-                            accepted = metropolis((lnzv - a.lnk[n + 1]) - beta * de, U);
-                            if (accepted) {
+                            Real pd;
+                            if (kind == 0)
+                                pd = partial_delta<true, true, SPLIT, CULL>(gas, n, i, sv, b, gg, gs, lane, part, qx,
+                                                                            qy, qz, o.x, o.y, o.z, qgas, qslab, core,
+                                                                            useful);
+                            else if (kind == 1)
+                                pd = partial_delta<true, false, SPLIT, CULL>(gas, n, -1, sv, b, gg, gs, lane, part,
+                                                                             qx, qy, qz, qx, qy, qz, qgas, qslab,
+                                                                             core, useful);
+                            else
+                                pd = partial_delta<false, true, SPLIT, CULL>(gas, n, i, sv, b, gg, gs, lane, part,
+                                                                             o.x, o.y, o.z, o.x, o.y, o.z, qgas,
+                                                                             qslab, core, useful);
+                            if (SPLIT == 1) {
+                                de = (double)pd;
+                            } else {
+                                // alternate slots: exchange k+2 reuses the slot of exchange k
+                                // only after both waves passed the barrier of exchange k+1
+                                double *mine = xch + ((xcount & 1) * 2 + part) * 2;
                                 if (lane == 0) {
+                                    mine[0] = (double)pd;
+                                    mine[1] = core ? 1.0 : 0.0;
+                                }
+                                __syncthreads();
+                                const double *x0 = xch + (xcount & 1) * 4;
+                                de = x0[0] + x0[2];
+                                core = (x0[1] + x0[3]) != 0.0;
+                                ++xcount;
+                            }
+                            const uint64_t mult = kind == 0 ? 2 : 1;
+                            const Real zmin = kind == 0 ? (qz < o.z ? qz : o.z) : (kind == 1 ? qz : o.z);
+                            cand += mult * (uint64_t)((kind == 1 ? n : n - 1) +
+                                                      (zmin < sv.top_plus_rc ? slab_scan : 0));
+                        }
+                        if (core && kind != 2) {
+                            stat += lane == 9;
+                        } else if (de <= thr) {
+                            accepted = true;
+                            stat += lane == 2 * kind + 1;
+                            e += de;
+                            if (kind == 0) {
+                                if (part == 0 && lane == 0) {
+                                    Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
+                                    gas[i] = v;
+                                }
+                            } else if (kind == 1) {
+                                if (part == 0 && lane == 0) {
                                     Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
                                     gas[n] = v;
                                 }
                                 n += 1;
-                                e += de;
-                                st_cnt[3]++;
+                            } else {
+                                if (part == 0 && lane == 0 && i != n - 1) gas[i] = gas[n - 1];
+                                n -= 1;
                             }
-                        }
-                    }
-                } else {
-                    // ---------------- removal ----------------
-                    st_cnt[4]++;
-                    if (n == 0) {
-                        st_cnt[7]++;
-                    } else {
-                        const int i = (int)(((uint64_t)A1 * (uint64_t)n) >> 32);
-                        const Real4 o = gas[i];
-                        double de = 0.0;
-                        if (!ideal) {
-                            Real eo = 0, dummy = 0;
-                            bool core = false;
-                            for (int j = lane; j < n; j += kWave) {
-                                if (j == i) continue;
-                                eo += lj(dist2(b, o.x, o.y, o.z, gas[j]), gg);
-                            }
-                            if (o.z < sv.top_plus_rc)
-                                slab_terms<false>(sv, b, gs, lane, o.x, o.y, o.z, o.x, o.y, o.z, o.x, o.y, eo, dummy,
-                                                  core);
-                            de = -(double)wave_sum(eo);
-                        }
-                        accepted = metropolis((a.lnk[n] - lnzv) - beta * de, U);
-                        if (accepted) {
-                            if (lane == 0 && i != n - 1) gas[i] = gas[n - 1];
-                            n -= 1;
-                            e += de;
-                            st_cnt[5]++;
                         }
                     }
                 }
                 if (accepted) {
                     bits |= 1u << tt;
-                    wave_sync();
+                    if (SPLIT == 1) wave_sync(); else __syncthreads();
                 }
             }
-            if (tracing && lane == 0)
+            if (tracing && part == 0 && lane == 0)
                 a.trace_bits[((size_t)(sweep - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
         }
         // ---- end of sweep: trace N, sample record ----
-        if (lane == 0) {
+        if (part == 0 && lane == 0) {
             if (tracing) a.trace_n[(size_t)(sweep - a.trace_sweep0) * a.n_walkers + w] = n;
             if (a.sample_every > 0 && (sweep + 1) % a.sample_every == 0) {
                 const int64_t rec = (sweep + 1) / a.sample_every - 1 - a.rec_base;
@@ -393,19 +533,29 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) SWEEP_KERNEL(Swee
     }
 
     // ---- write back ----
+    if (SPLIT == 2) __syncthreads();
     {
         double *dst = a.xyz + (size_t)w * a.xyz_stride * 3;
-        for (int k = lane; k < n; k += kWave) {
+        for (int k = part * kWave + lane; k < n; k += SPLIT * kWave) {
             const Real4 v = gas[k];
             dst[3 * k] = (double)v.x; dst[3 * k + 1] = (double)v.y; dst[3 * k + 2] = (double)v.z;
         }
     }
-    if (lane == 0) {
-        a.n[w] = n;
-        a.e[w] = e;
+    {
+        uint32_t u = useful;
 #pragma unroll
-        for (int k = 0; k < kNStat; ++k)
-            if (st_cnt[k]) atomicAdd(a.stats + (size_t)sg * kNStat + k, (unsigned long long)st_cnt[k]);
+        for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+        if (lane == 0 && a.pairs) {
+            if (part == 0) atomicAdd(a.pairs, (unsigned long long)cand);
+            atomicAdd(a.pairs + 1, (unsigned long long)u);
+        }
+    }
+    if (part == 0) {
+        if (lane < kNStat && stat) atomicAdd(a.stats + (size_t)sg * kNStat + lane, (unsigned long long)stat);
+        if (lane == 0) {
+            a.n[w] = n;
+            a.e[w] = e;
+        }
     }
 }
 
@@ -416,8 +566,8 @@ __global__ void __launch_bounds__(256) ENERGY_KERNEL(EnergyArgs a)
     const int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     if (w >= a.n_walkers) return;
-    const ClassDev &C = a.cls[a.walker_class[w]];
     const int cid = a.walker_class[w];
+    const ClassDev &C = a.cls[cid];
     Box b;
     b.lx = (Real)C.lx; b.ly = (Real)C.ly; b.hx = (Real)C.half_lx; b.hy = (Real)C.half_ly;
     b.ix = (Real)C.inv_lx; b.iy = (Real)C.inv_ly;
@@ -449,6 +599,14 @@ __global__ void __launch_bounds__(256) ENERGY_KERNEL(EnergyArgs a)
     if (lane == 0) a.e_out[w] = acc;
 }
 
+}  // namespace fp64 / fp32
+
+#if defined(REGC_FP64)
+using namespace fp64;
+#else
+using namespace fp32;
+#endif
+
 hipError_t ENERGY_LAUNCH(const EnergyArgs &a, hipStream_t s)
 {
     const int per = 4;
@@ -456,9 +614,17 @@ hipError_t ENERGY_LAUNCH(const EnergyArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int wpb, size_t smem, hipStream_t s)
+hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL(SWEEP_KERNEL, dim3(n_blocks), dim3(kWave * wpb), smem, s, a);
+    const dim3 grid(n_blocks), block(kWave * waves_per_block);
+    if (split == 2) {
+        if (cull) hipLaunchKernelGGL((sweep_kernel<2, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<2, false>), grid, block, smem, s, a);
+    } else {
+        if (cull) hipLaunchKernelGGL((sweep_kernel<1, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<1, false>), grid, block, smem, s, a);
+    }
     return hipGetLastError();
 }
 

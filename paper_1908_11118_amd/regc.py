@@ -26,7 +26,7 @@ STAT_NAMES = ["disp_att", "disp_acc", "ins_att", "ins_acc", "del_att", "del_acc"
 EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_layout", "regc_set_stream",
            "regc_run", "regc_sync", "regc_get_sweep", "regc_get_walkers", "regc_set_walkers", "regc_energies",
            "regc_sample_count", "regc_get_samples", "regc_samples_device", "regc_clear_samples",
-           "regc_get_stats", "regc_get_histograms", "regc_get_trace", "regc_timing_enable", "regc_timing_get",
+           "regc_get_stats", "regc_get_pair_counts", "regc_get_histograms", "regc_get_trace", "regc_timing_enable", "regc_timing_get",
            "regc_checkpoint", "regc_restore", "regc_destroy", "regc_mbar_create", "regc_mbar_set_stream",
            "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_solve", "regc_mbar_targets",
            "regc_mbar_timing", "regc_mbar_destroy", "regc_strerror", "regc_last_error"]
@@ -64,7 +64,7 @@ class Opts(C.Structure):
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("sample_capacity", C.c_int64),
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
-                ("slab_bins", C.c_int)]
+                ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int)]
 
 
 _lib = None
@@ -99,6 +99,7 @@ def lib():
         L.regc_clear_samples.argtypes = [vp]
         L.regc_get_stats.argtypes = [vp, _i64p, _i64p, _i64p]
         L.regc_get_histograms.argtypes = [vp, _i64p]
+        L.regc_get_pair_counts.argtypes = [vp, _i64p, _i64p]
         L.regc_get_trace.argtypes = [vp, _u32p, _i32p, C.c_int64, _i64p]
         L.regc_timing_enable.argtypes = [vp, C.c_int]
         L.regc_timing_get.argtypes = [vp, _dp, _i64p, _dp, _i64p]
@@ -154,7 +155,8 @@ class Regc:
     sharing potential and schedule) advanced on the GPU."""
 
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
-                 walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, stream=None):
+                 walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
+                 cull: int = 0, stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
         self.workloads = wl
@@ -176,6 +178,7 @@ class Regc:
         o.sample_every, o.swap_scheme = w0.sample_every, w0.swap_scheme
         o.sample_capacity, o.trace_capacity = sample_capacity, trace_capacity
         o.walkers_per_block, o.sweeps_per_launch, o.slab_bins = walkers_per_block, sweeps_per_launch, slab_bins
+        o.split, o.cull = split, cull
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:
@@ -271,6 +274,11 @@ class Regc:
         acc = np.zeros((4, self.W), np.int64)
         _check(lib().regc_get_stats(self.h, _p(st, _i64p), _p(att, _i64p), _p(acc, _i64p)))
         return {"stats": st, "swap_att": att, "swap_acc": acc}
+
+    def pair_counts(self):
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().regc_get_pair_counts(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def histograms(self):
         h = np.zeros((self.W, self.n_max_all + 1), np.int64)

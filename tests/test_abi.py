@@ -56,3 +56,14 @@ def test_default_opts_and_errors_without_gpu():
     pot.mode = 2                                                 # site lattice: oracle only
     assert L.regc_create(ctypes.byref(pot), ctypes.byref(sys_), ctypes.byref(g), ctypes.byref(o),
                          ctypes.byref(h)) == regc.EUNSUPPORTED
+
+
+def test_each_precision_has_its_own_kernel_symbols():
+    """The FP64 and FP32 builds of the sweep kernel must not share symbol names,
+    or one precision's launches run the other's code."""
+    if not os.path.exists(regc.LIB_PATH):
+        pytest.skip("libregc_hip.so not built")
+    blob = open(regc.LIB_PATH, "rb").read()
+    names = set(re.findall(rb"_ZN4regc4fp(?:32|64)12sweep_kernelILi[12]ELb[01]EEEvNS_9SweepArgsE", blob))
+    assert len(names) == 8, sorted(names)
+    assert not re.search(rb"_ZN4regc12sweep_kernel", blob)

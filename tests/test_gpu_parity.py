@@ -88,10 +88,23 @@ def test_fp64_trajectories_binned_slab_and_scheme1():
     _fp64_trajectory(w2, 200, slab_bins=-1)
 
 
-@pytest.mark.parametrize("wpb,spl", [(1, 1), (4, 3), (8, 0)])
-def test_fp64_invariant_to_launch_shape(wpb, spl):
+@pytest.mark.parametrize("wpb,spl,split,cull", [(1, 1, 1, 0), (4, 3, 1, 1), (8, 0, 1, 0), (1, 0, 2, 0), (1, 7, 2, 1)])
+def test_fp64_invariant_to_launch_shape(wpb, spl, split, cull):
+    """Walkers per block, sweeps per launch, waves per walker and the cull pass
+    change nothing but summation order: trajectories stay identical."""
     w = W.small_lj(n_t=4, n_mu=4, n_max=20, n_sweeps=60)
-    _fp64_trajectory(w, 60, walkers_per_block=wpb, sweeps_per_launch=spl)
+    _fp64_trajectory(w, 60, walkers_per_block=wpb, sweeps_per_launch=spl, split=split, cull=cull)
+    w2 = W.config3_classes()[0].replace(t=W.linear_grid(0.6, 1.8, 3), mu=W.linear_grid(-6.0, -2.5, 3), n_max=40)
+    _fp64_trajectory(w2, 40, walkers_per_block=wpb, sweeps_per_launch=spl, split=split, cull=cull)
+
+
+@pytest.mark.parametrize("split,cull", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_fp64_dense_walkers(split, cull):
+    """N well above 64 (a wave's width), binned 8x8x3 slab: both waves of a split
+    walker own gas candidates."""
+    w = W.config2(60).replace(t=np.array([0.9, 1.6]), mu=np.array([-3.0, -2.0]), n_max=160, sample_every=5)
+    _, wk = _fp64_trajectory(w, 60, split=split, cull=cull)
+    assert wk["n"].max() > 100
 
 
 def test_fp64_edge_cases():
