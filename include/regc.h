@@ -265,6 +265,10 @@ int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e, const int3
  * must be that class's grid.  EINVAL when nothing is left. */
 int regc_mbar_load_run(regc_mbar *mb, regc_ctx *ctx, int cls, int64_t skip_records);
 
+/* Fixed-point solver of regc_mbar_solve: method 0 plain iteration, 1 (default)
+ * Anderson acceleration with `memory` past iterates (1..32, default 8). */
+int regc_mbar_set_solver(regc_mbar *mb, int method, int memory);
+
 /* Solves the self-consistent equations (Eq. (9)) for the free energies f_s =
  * -ln c_s of the sampled states, gauge f = 0 at the first sampled state, until
  * max |delta f| < tol or max_iter iterations.  f_out[S] (unsampled states get

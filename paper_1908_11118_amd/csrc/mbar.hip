@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <vector>
 
 #include "host_util.h"
@@ -326,6 +327,7 @@ struct regc_mbar {
     bool have_samples = false, solved = false;
     double ms_iter = 0.0;
     int64_t n_iter = 0;
+    int method = 1, memory = 8;
 };
 
 static double lnz_of(double T, double mu, double lambda1)
@@ -496,6 +498,65 @@ static hipError_t mbar_iteration(regc_mbar *mb)
     return hipGetLastError();
 }
 
+// Least-squares coefficients gamma minimising || r - dR gamma ||_2 (dR: n x m,
+// column-major) by modified Gram-Schmidt QR; columns that are numerically
+// dependent on earlier ones get gamma = 0.
+static void lsq_mgs(int n, int m, const std::vector<double> &dR, const std::vector<double> &r,
+                    std::vector<double> &gamma)
+{
+    std::vector<double> Q(dR), R((size_t)m * m, 0.0), qtr(m, 0.0);
+    std::vector<bool> keep(m, true);
+    for (int j = 0; j < m; ++j) {
+        double *qj = &Q[(size_t)j * n];
+        double norm0 = 0.0;
+        for (int i = 0; i < n; ++i) norm0 += qj[i] * qj[i];
+        for (int k = 0; k < j; ++k) {
+            if (!keep[k]) continue;
+            const double *qk = &Q[(size_t)k * n];
+            double d = 0.0;
+            for (int i = 0; i < n; ++i) d += qk[i] * qj[i];
+            R[(size_t)k * m + j] = d;
+            for (int i = 0; i < n; ++i) qj[i] -= d * qk[i];
+        }
+        double nn = 0.0;
+        for (int i = 0; i < n; ++i) nn += qj[i] * qj[i];
+        if (nn <= 1e-24 * (norm0 + 1e-300)) {
+            keep[j] = false;
+            continue;
+        }
+        nn = std::sqrt(nn);
+        R[(size_t)j * m + j] = nn;
+        for (int i = 0; i < n; ++i) qj[i] /= nn;
+        double d = 0.0;
+        for (int i = 0; i < n; ++i) d += qj[i] * r[i];
+        qtr[j] = d;
+    }
+    gamma.assign(m, 0.0);
+    for (int j = m - 1; j >= 0; --j) {
+        if (!keep[j]) continue;
+        double v = qtr[j];
+        for (int k = j + 1; k < m; ++k)
+            if (keep[k]) v -= R[(size_t)j * m + k] * gamma[k];
+        gamma[j] = v / R[(size_t)j * m + j];
+    }
+}
+
+extern "C" int regc_mbar_set_solver(regc_mbar *mb, int method, int memory)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    REGC_CHECK(method == 0 || method == 1, REGC_EINVAL, "method must be 0 (plain) or 1 (Anderson)");
+    REGC_CHECK(memory >= 1 && memory <= 32, REGC_EINVAL, "memory must be 1..32");
+    mb->method = method;
+    mb->memory = memory;
+    return REGC_OK;
+}
+
+// Fixed point f = g(f) of the self-consistent map (one device iteration = g plus the
+// gauge).  Plain: f <- g(f).  Anderson acceleration (Walker & Ni, SIAM J. Numer.
+// Anal. 49 (2011) 1715, type II, memory m) on the sampled states' components:
+// x_{k+1} = g_k - dG gamma, gamma = argmin || r_k - dR gamma ||, r = g(x) - x; a step
+// that raises the residual tenfold restarts the history.  Converged when
+// max |g(x) - x| over sampled states < tol.
 extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters, double *delta)
 {
     REGC_CHECK(mb, REGC_EINVAL, "null handle");
@@ -507,21 +568,54 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     REGC_HIP(hipEventCreate(&e0));
     REGC_HIP(hipEventCreate(&e1));
     REGC_HIP(hipEventRecord(e0, s));
-    const int check = 10;
-    double d = INFINITY;
+    std::vector<int> idx;
+    for (int k = 0; k < mb->S; ++k)
+        if (mb->lnomega[k] != -INFINITY) idx.push_back(k);
+    const int n = (int)idx.size();
+    const int m = mb->memory;
+    std::vector<double> x(mb->S, 0.0), gx(mb->S), xs(n), gs(n), r(n);
+    std::deque<std::vector<double>> hist_r, hist_g;   // last residuals and map values (sampled part)
+    double d = INFINITY, d_prev = INFINITY;
     int it = 0;
     bool conv = false;
+    const int check = mb->method == 0 ? 10 : 1;
     for (it = 0; it < max_iter;) {
-        REGC_HIP(mbar_iteration(mb));
+        REGC_HIP(mbar_iteration(mb));   // f_d <- gauge(map(f_d)), delta_d <- max |new - old|
         ++it;
-        if (it % check == 0 || it == max_iter) {
-            REGC_HIP(hipMemcpyAsync(&d, mb->delta_d.p, sizeof(double), hipMemcpyDeviceToHost, s));
-            REGC_HIP(hipStreamSynchronize(s));
-            if (d < tol) { conv = true; break; }
+        if (it % check != 0 && it != max_iter) continue;
+        REGC_HIP(hipMemcpyAsync(&d, mb->delta_d.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (mb->method == 1) REGC_HIP(hipMemcpyAsync(gx.data(), mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost, s));
+        REGC_HIP(hipStreamSynchronize(s));
+        if (!(d == d)) break;                       // NaN: give up, report the last state
+        if (d < tol) { conv = true; break; }
+        if (mb->method == 0) continue;
+        for (int q = 0; q < n; ++q) {
+            gs[q] = gx[idx[q]];
+            r[q] = gx[idx[q]] - x[idx[q]];
         }
+        if (d > 10.0 * d_prev) { hist_r.clear(); hist_g.clear(); }
+        d_prev = d;
+        hist_r.push_back(r);
+        hist_g.push_back(gs);
+        if ((int)hist_r.size() > m + 1) { hist_r.pop_front(); hist_g.pop_front(); }
+        const int mk = (int)hist_r.size() - 1;
+        std::vector<double> xn(gx);
+        if (mk > 0) {
+            std::vector<double> dR((size_t)n * mk), gamma;
+            for (int j = 0; j < mk; ++j)
+                for (int q = 0; q < n; ++q) dR[(size_t)j * n + q] = hist_r[j + 1][q] - hist_r[j][q];
+            lsq_mgs(n, mk, dR, r, gamma);
+            for (int q = 0; q < n; ++q) {
+                double v = gs[q];
+                for (int j = 0; j < mk; ++j) v -= gamma[j] * (hist_g[j + 1][q] - hist_g[j][q]);
+                xn[idx[q]] = v;
+            }
+        }
+        x = xn;
+        REGC_HIP(hipMemcpyAsync(mb->f_d.p, x.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
     }
     REGC_HIP(hipEventRecord(e1, s));
-    // log D consistent with the final f
+    // f_d holds g of the last iterate; log D consistent with it
     hipLaunchKernelGGL(mbar_loga, dim3(mb->L), dim3(256), 0, s, mb->M, mb->nN, mb->lnomega_d.p, mb->f_d.p,
                        mb->lnz_d.p, mb->logA_d.p);
     REGC_HIP(hipGetLastError());

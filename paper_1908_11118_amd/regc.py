@@ -28,7 +28,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_sample_count", "regc_get_samples", "regc_samples_device", "regc_clear_samples",
            "regc_get_stats", "regc_get_pair_counts", "regc_get_histograms", "regc_get_trace", "regc_timing_enable", "regc_timing_get",
            "regc_checkpoint", "regc_restore", "regc_destroy", "regc_mbar_create", "regc_mbar_set_stream",
-           "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_solve", "regc_mbar_targets",
+           "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_set_solver", "regc_mbar_solve", "regc_mbar_targets",
            "regc_mbar_timing", "regc_mbar_destroy", "regc_strerror", "regc_last_error"]
 
 
@@ -111,6 +111,7 @@ def lib():
         L.regc_mbar_set_stream.argtypes = [vp, vp]
         L.regc_mbar_set_samples.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_int]
         L.regc_mbar_load_run.argtypes = [vp, vp, C.c_int, C.c_int64]
+        L.regc_mbar_set_solver.argtypes = [vp, C.c_int, C.c_int]
         L.regc_mbar_solve.argtypes = [vp, C.c_double, C.c_int, _dp, C.POINTER(C.c_int), _dp]
         L.regc_mbar_targets.argtypes = [vp, C.POINTER(Grid), _dp, _dp, _dp, _dp, _dp, _i32p]
         L.regc_mbar_timing.argtypes = [vp, _dp, _i64p]
@@ -353,6 +354,9 @@ class Mbar:
 
     def load_run(self, run: Regc, cls: int = 0, skip_records: int = 0):
         _check(lib().regc_mbar_load_run(self.h, run.h, cls, skip_records))
+
+    def set_solver(self, method: int = 1, memory: int = 8):
+        _check(lib().regc_mbar_set_solver(self.h, method, memory))
 
     def solve(self, tol: float = 1e-10, max_iter: int = 10000, allow_noconv: bool = False):
         f = np.zeros(len(self.t) * len(self.mu))

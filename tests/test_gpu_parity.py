@@ -201,13 +201,17 @@ def test_fp32_long_run_mean_n_within_3se():
 # ---------------------------------------------------------------------------
 # Reweighting
 # ---------------------------------------------------------------------------
-def test_mbar_matches_oracle():
+@pytest.mark.parametrize("method", [1, 0])
+def test_mbar_matches_oracle(method):
+    """GPU reweighting (factorised over temperatures, plain or Anderson-accelerated
+    fixed point) against the naive FP64 oracle on the same config-1 samples."""
     w = W.config1(400)
-    _say("[mbar] config1 400 sweeps")
+    _say(f"[mbar] config1 400 sweeps, solver {method}")
     with regc.Regc(w, precision=regc.FP64, sample_capacity=400 * 64) as g:
         g.run(400)
         s = g.samples()
         mb = regc.Mbar(w.t, w.mu, w.n_max)
+        mb.set_solver(method, 8)
         mb.load_run(g, 0, skip_records=40)
     keep = slice(40 * 64, None)
     e, n, st = s["e"][keep], s["n"][keep], s["state"][keep]
