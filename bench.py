@@ -45,6 +45,11 @@ def main():
     ap.add_argument("--mbar-records", type=int, default=1000, help="records for the reweighting leg (0: skip)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+                    help="c2: 1024 replicas at a 192-atom slab (the headline); c3: 4096 replicas in four "
+                         "slab classes batched in one launch")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
+    ap.add_argument("--graph", type=int, default=-1, help="graph_intervals (-1: 0 for c2, 10 for c3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
@@ -59,13 +64,24 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = W.config2()
+    wl = [W.config2()] if args.workload == "c2" else W.config3_classes()
+    w = wl[0]
+    n_walkers = sum(x.n_states for x in wl)
+    trials_per_sweep_all = sum(x.n_states * x.trials for x in wl)
     sweeps_per_step = w.swap_every
     prec = regc.FP32PAIR if args.precision == "fp32" else regc.FP64
     total_sweeps = args.burnin + (args.warmup + args.steps) * sweeps_per_step
-    cap = (total_sweeps // w.sample_every + 2) * w.n_states
-    g = regc.Regc(w, precision=prec, sample_capacity=cap, walkers_per_block=args.wpb)
-    print(f"[bench] burn-in {args.burnin} sweeps of {w.name}", file=sys.stderr, flush=True)
+    cap = (total_sweeps // w.sample_every + 2) * n_walkers
+    opts = {"walkers_per_block": args.wpb,
+            "graph_intervals": (0 if args.workload == "c2" else 10) if args.graph < 0 else args.graph}
+    tuned = None
+    if args.autotune:
+        from paper_1908_11118_amd import autotune
+        print("[bench] autotuning the launch shape", file=sys.stderr, flush=True)
+        tuned = autotune.autotune(wl, precision=prec, cache_path=None, verbose=True)
+        opts = dict(tuned["options"])
+    g = regc.Regc(wl if len(wl) > 1 else w, precision=prec, sample_capacity=cap, **opts)
+    print(f"[bench] burn-in {args.burnin} sweeps of {args.workload}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     done = 0
     while done < args.burnin:
@@ -91,7 +107,7 @@ def main():
     tm = g.timing()
     st1 = g.stats()["stats"]
     pc1 = g.pair_counts()
-    trials = args.steps * sweeps_per_step * w.n_states * w.trials
+    trials = args.steps * sweeps_per_step * trials_per_sweep_all
     d = st1 - st0
     assert int(d[:, [0, 2, 4]].sum()) == trials, "trial count mismatch"
     value = trials / elapsed
@@ -99,6 +115,7 @@ def main():
     useful = pc1[1] - pc0[1]
     ms_kernel = tm["ms_sweep"] / max(tm["n_sweep"], 1)
     flops_launch = FLOPS_PER_PAIR * cand / max(tm["n_sweep"], 1)
+    graph = opts.get("graph_intervals", 0) > 0
     achieved = flops_launch / (ms_kernel * 1e-3) / 1e12
     wk = g.walkers(xyz=True)
 
@@ -119,9 +136,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == regc.FP32PAIR else "f64",
         "data": "synthetic",
-        "config": {"workload": "REGC 1024 replicas (32 T x 32 mu), 8x8x3 = 192-atom fcc(100) LJ slab, "
-                               "gas box 12^3, N <= 200, K = 201 trials/sweep, exchange every 10 sweeps",
-                   "replicas": w.n_states, "n_max": w.n_max, "trials_per_sweep": w.trials,
+        "config": {"workload": ("REGC 1024 replicas (32 T x 32 mu), 8x8x3 = 192-atom fcc(100) LJ slab, "
+                                "gas box 12^3, N <= 200, K = 201 trials/sweep, exchange every 10 sweeps")
+                               if args.workload == "c2" else
+                               ("REGC 4096 replicas: four slab classes {6,8,10,12}^2 x 3 (108-432 atoms), "
+                                "boxes 9-18 x 12, each 32 T x 32 mu, N <= 500, K = 501, one launch per interval"),
+                   "replicas": n_walkers, "n_max": w.n_max, "trials_per_sweep": w.trials,
+                   "launch": opts,
                    "sweeps_per_step": sweeps_per_step, "burnin_sweeps": args.burnin,
                    "precision": "FP32 pair terms, FP64 energies/decisions/exchange" if prec == regc.FP32PAIR
                    else "FP64", "mean_N": float(wk["n"].mean()), "max_N": int(wk["n"].max())},
@@ -129,6 +150,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "sweep_kernel_f32" if prec == regc.FP32PAIR else "sweep_kernel_f64",
                      "kernel_ms_avg": ms_kernel, "launches": tm["n_sweep"],
+                     "timed_unit": "graph replay (sweeps + exchange)" if graph else "sweep-kernel launch",
                      "candidate_pairs_per_launch": cand / max(tm["n_sweep"], 1),
                      "flops_per_pair": FLOPS_PER_PAIR,
                      "useful_pair_fraction": useful / max(cand, 1)},
@@ -137,8 +159,10 @@ def main():
         "kernel_share": tm["ms_sweep"] / (elapsed * 1e3),
     }
 
+    if tuned is not None:
+        result["autotune"] = {"chosen": tuned["options"], "table": tuned["table"]}
     # ---- CPU baseline: the FP64 oracle on the host cores, same configurations ----
-    if args.cpu_sweeps > 0:
+    if args.cpu_sweeps > 0 and args.workload == "c2":
         import oracle
         oracle.build(force=False)
         threads = oracle.default_threads()
@@ -158,7 +182,7 @@ def main():
                                             f"{csec:.1f} s"}
 
     # ---- reweighting leg: 1024 states x mbar-records records ----
-    if args.mbar_records > 0:
+    if args.mbar_records > 0 and args.workload == "c2":
         g.close()
         wm = w.replace(sample_every=1)
         gm = regc.Regc(wm, precision=prec, sample_capacity=args.mbar_records * w.n_states,

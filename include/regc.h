@@ -123,7 +123,12 @@ typedef struct {
  *  split           wavefronts per walker: 1, 2, or 0 (auto: 1); with 2,
  *                  walkers_per_block is 1.
  *  cull            1: squared distances first, LJ terms only for pairs inside the
- *                  cutoff (compacted in LDS); 0 or -1: every candidate in full. */
+ *                  cutoff (compacted in LDS); 0 or -1: every candidate in full.
+ *  graph_intervals 0: launch kernels one by one; R > 0: capture R exchange intervals
+ *                  (sweep launches, exchange, sweep-clock advance) in a hipGraph once
+ *                  and replay it; the run is split into an eager prefix up to the next
+ *                  exchange boundary, whole replays, and an eager remainder.  In graph
+ *                  mode regc_timing_get's sweep figures cover whole replays. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -137,6 +142,7 @@ typedef struct {
     int slab_bins;
     int split;
     int cull;
+    int graph_intervals;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

@@ -63,7 +63,8 @@ class _Config(C.Structure):
                 ("n_t", C.c_int), ("n_mu", C.c_int), ("t", _dp), ("mu", _dp),
                 ("seed", C.c_uint64), ("p_disp", C.c_double), ("p_ins", C.c_double),
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
-                ("sample_every", C.c_int), ("swap_scheme", C.c_int)]
+                ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("walker_offset", C.c_int),
+                ("class_id", C.c_int)]
 
 
 class _Walkers(C.Structure):
@@ -145,7 +146,7 @@ def state_arrays(w):
 class Chain:
     """All walkers of one REGC simulation, advanced by the C oracle."""
 
-    def __init__(self, w, n_threads: int | None = None):
+    def __init__(self, w, n_threads: int | None = None, walker_offset: int = 0, class_id: int = 0):
         self.w = w
         self.S = len(w.t) * len(w.mu)
         self.n_max = int(w.n_max)
@@ -172,6 +173,7 @@ class Chain:
         c.p_disp, c.p_ins, c.max_disp = w.p_disp, w.p_ins, w.max_disp
         c.trials_per_sweep, c.swap_every = w.trials_per_sweep, w.swap_every
         c.sample_every, c.swap_scheme = w.sample_every, w.swap_scheme
+        c.walker_offset, c.class_id = walker_offset, class_id
         self.cfg = c
         S = self.S
         # initial state: empty walkers, walker w holds state w

@@ -109,6 +109,10 @@ typedef struct {
     double p_disp, p_ins, max_disp;
     int trials_per_sweep;
     int swap_every, sample_every, swap_scheme;
+    /* position of this simulation inside a batch of several: its walkers' Philox
+     * walker index is offset by walker_offset, its exchange stream is
+     * 0xFFFFFFFF - class_id (both 0 for a lone simulation) */
+    int walker_offset, class_id;
 } orc_config;
 
 /* derived per-state constants */
@@ -244,8 +248,9 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
                  orc_walkers *W, int w, int64_t sweep, int t)
 {
     uint32_t A[4], B[4];
-    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, (uint32_t)w, 0u, A);
-    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, (uint32_t)w, 1u, B);
+    const uint32_t wid = (uint32_t)(w + c->walker_offset);
+    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, wid, 0u, A);
+    philox_words(c->seed, (uint32_t)t, (uint32_t)sweep, wid, 1u, B);
 
     const int s = W->label[w];
     const double beta = sc[s].beta, lnz = sc[s].lnz;
@@ -380,7 +385,7 @@ static void swap_pair(const orc_config *c, const orc_statec *sc, orc_walkers *W,
     int S = c->n_t * c->n_mu;
     int lo = sa < sb ? sa : sb;
     uint32_t R[4];
-    philox_words(c->seed, (uint32_t)lo, (uint32_t)q, 0xFFFFFFFFu, 4u, R);
+    philox_words(c->seed, (uint32_t)lo, (uint32_t)q, 0xFFFFFFFFu - (uint32_t)c->class_id, 4u, R);
     int i = W->wos[sa], j = W->wos[sb];
     double x = (sc[sa].beta - sc[sb].beta) * (W->e[i] - W->e[j])
              + (double)(W->n[j] - W->n[i]) * (sc[sa].lnz - sc[sb].lnz);
@@ -397,7 +402,7 @@ static void swap_pair(const orc_config *c, const orc_statec *sc, orc_walkers *W,
 static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W, int64_t q)
 {
     uint32_t R[4];
-    philox_words(c->seed, 0u, (uint32_t)q, 0xFFFFFFFFu, 3u, R);
+    philox_words(c->seed, 0u, (uint32_t)q, 0xFFFFFFFFu - (uint32_t)c->class_id, 3u, R);
     int type = (int)(R[0] >> 30);
     int L = c->n_t, M = c->n_mu;
     if (c->swap_scheme == 0) {

@@ -71,8 +71,17 @@ struct regc_ctx {
     bool timing = false;
     std::vector<TimingPair> ev_sweep, ev_swap;
 
+    // graph replay of whole exchange intervals
+    DevBuf<int64_t> clock_d;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
     ~regc_ctx()
     {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (auto &p : ev_sweep) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (auto &p : ev_swap) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     }
@@ -115,6 +124,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->slab_bins = 0;
     o->split = 0;
     o->cull = 0;
+    o->graph_intervals = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -143,6 +153,7 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->walkers_per_block >= 0 && o->walkers_per_block <= kMaxWalkersPerBlock, REGC_EINVAL,
                "walkers_per_block must be 0..%d", kMaxWalkersPerBlock);
     REGC_CHECK(o->split >= 0 && o->split <= 2, REGC_EINVAL, "split must be 0, 1 or 2");
+    REGC_CHECK(o->graph_intervals >= 0 && o->graph_intervals <= 1000, REGC_EINVAL, "graph_intervals must be 0..1000");
     return REGC_OK;
 }
 
@@ -310,7 +321,16 @@ static int ctx_alloc_and_init(regc_ctx *c)
     c->smem = smem_for(wpb);
     std::vector<int> bcls, bw0, bnw;
     c->walker_class.assign(W, 0);
-    for (int k = 0; k < n_class; ++k) {
+    // blocks of the costliest classes first (largest n_max + slab candidates), so the
+    // long-running walkers start early and the launch ends with the short ones
+    std::vector<int> order(n_class);
+    for (int k = 0; k < n_class; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const ClassHost &ha = c->cls[a], &hb = c->cls[b];
+        return ha.sys.n_max + (ha.bins ? 9 * ha.cap : (int)(ha.packed.size() / 3)) >
+               hb.sys.n_max + (hb.bins ? 9 * hb.cap : (int)(hb.packed.size() / 3));
+    });
+    for (int k : order) {
         const ClassHost &h = c->cls[k];
         for (int w = 0; w < h.S; w += wpb) {
             bcls.push_back(k);
@@ -355,7 +375,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->hist_d.alloc((size_t)W * (nmax + 1))) || (rc = c->stats_d.alloc((size_t)W * kNStat)) ||
         (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) || (rc = c->pairs_d.alloc(2)) ||
         (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
-        (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)))
+        (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)) || (rc = c->clock_d.alloc(1)))
         return rc;
     if ((rc = upload(c->cls_d.p, cd.data(), sizeof(ClassDev) * n_class)) ||
         (rc = upload(c->block_class_d.p, bcls.data(), sizeof(int) * bcls.size())) ||
@@ -462,7 +482,7 @@ static int record_event(regc_ctx *c, std::vector<TimingPair> &v, bool start)
     return REGC_OK;
 }
 
-static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
+static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream, bool use_clock)
 {
     SweepArgs a{};
     a.cls = c->cls_d.p;
@@ -487,7 +507,8 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
     a.th_disp = (uint64_t)std::llround(c->opts.p_disp * 4294967296.0);
     a.th_ins = a.th_disp + (uint64_t)std::llround(c->opts.p_ins * 4294967296.0);
     a.max_disp = c->opts.max_disp;
-    a.sweep0 = sweep0;
+    a.sweep0 = sweep0;              // with the clock: offset from clock[0]
+    a.clock = use_clock ? c->clock_d.p : nullptr;
     a.n_sweeps = n;
     a.sample_every = c->opts.sample_every;
     a.rec_base = c->rec_base;
@@ -508,16 +529,17 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n)
     a.gas_stride = c->nmax_all;
     a.max_slab_scan = c->max_slab_scan;
     int rc;
-    if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
+    const bool ev = c->timing && !use_clock;
+    if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
     if (c->opts.precision == REGC_FP64)
-        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, c->stream));
+        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
     else
-        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, c->stream));
-    if (c->timing && (rc = record_event(c, c->ev_sweep, false))) return rc;
+        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
+    if (ev && (rc = record_event(c, c->ev_sweep, false))) return rc;
     return REGC_OK;
 }
 
-static int launch_exchange(regc_ctx *c, int64_t q)
+static int launch_exchange(regc_ctx *c, int64_t q, hipStream_t stream, bool use_clock)
 {
     SwapArgs a{};
     a.cls = c->cls_d.p;
@@ -534,10 +556,51 @@ static int launch_exchange(regc_ctx *c, int64_t q)
     a.att = c->att_d.p;
     a.acc = c->acc_d.p;
     a.S_total = c->W;
+    a.clock = use_clock ? c->clock_d.p : nullptr;
+    a.interval = c->opts.swap_every;
+    a.swap_every = c->opts.swap_every;
     int rc;
-    if (c->timing && (rc = record_event(c, c->ev_swap, true))) return rc;
-    REGC_HIP(launch_swap(a, (int)c->cls.size(), c->stream));
-    if (c->timing && (rc = record_event(c, c->ev_swap, false))) return rc;
+    const bool ev = c->timing && !use_clock;
+    if (ev && (rc = record_event(c, c->ev_swap, true))) return rc;
+    REGC_HIP(launch_swap(a, (int)c->cls.size(), stream));
+    if (ev && (rc = record_event(c, c->ev_swap, false))) return rc;
+    return REGC_OK;
+}
+
+// The captured graph bakes in the sample and trace bases: drop it when they move.
+static void invalidate_graph(regc_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+// Captures graph_intervals exchange intervals (sweep launches, exchange, clock
+// advance) once; replays start from the sweep index held in the device clock.
+static int build_graph(regc_ctx *c)
+{
+    if (c->gexec) return REGC_OK;
+    const regc_opts &o = c->opts;
+    const int spl = o.sweeps_per_launch > 0 ? std::min(o.sweeps_per_launch, o.swap_every) : o.swap_every;
+    REGC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    REGC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = REGC_OK;
+    for (int r = 0; r < o.graph_intervals && !rc; ++r) {
+        for (int off = 0; off < o.swap_every && !rc; off += spl)
+            rc = launch_sweeps(c, off, std::min(spl, o.swap_every - off), c->cap_stream, true);
+        if (!rc) rc = launch_exchange(c, 0, c->cap_stream, true);
+        if (!rc && launch_clock_advance(c->clock_d.p, o.swap_every, c->cap_stream) != hipSuccess) rc = REGC_EHIP;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    REGC_CHECK(e == hipSuccess, REGC_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    c->graph = g;
+    REGC_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
     return REGC_OK;
 }
 
@@ -556,20 +619,45 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
         REGC_CHECK(c->sweep + n_sweeps - c->trace_sweep0 <= c->trace_cap, REGC_ECAPACITY,
                    "trace capacity of %lld sweeps exceeded", (long long)c->trace_cap);
     int64_t left = n_sweeps;
-    while (left > 0) {
-        int64_t chunk = left;
-        if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
-        const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
-        chunk = std::min<int64_t>(chunk, spl);
-        int rc = launch_sweeps(c, c->sweep, (int)chunk);
-        if (rc) return rc;
-        c->sweep += chunk;
-        left -= chunk;
-        if (o.swap_every > 0 && c->sweep % o.swap_every == 0) {
-            rc = launch_exchange(c, c->sweep / o.swap_every - 1);
+    auto eager = [&](int64_t count) -> int {
+        int64_t rem = count;
+        while (rem > 0) {
+            int64_t chunk = rem;
+            if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
+            const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
+            chunk = std::min<int64_t>(chunk, spl);
+            int rc = launch_sweeps(c, c->sweep, (int)chunk, c->stream, false);
             if (rc) return rc;
+            c->sweep += chunk;
+            rem -= chunk;
+            if (o.swap_every > 0 && c->sweep % o.swap_every == 0) {
+                rc = launch_exchange(c, c->sweep / o.swap_every - 1, c->stream, false);
+                if (rc) return rc;
+            }
+        }
+        return REGC_OK;
+    };
+    int rc;
+    if (o.graph_intervals > 0 && o.swap_every > 0) {
+        const int64_t align = (o.swap_every - c->sweep % o.swap_every) % o.swap_every;
+        const int64_t pre = std::min(align, left);
+        if ((rc = eager(pre))) return rc;
+        left -= pre;
+        const int64_t per = (int64_t)o.graph_intervals * o.swap_every;
+        const int64_t reps = left / per;
+        if (reps > 0) {
+            if ((rc = build_graph(c))) return rc;
+            REGC_HIP(launch_clock_set(c->clock_d.p, c->sweep, c->stream));
+            for (int64_t r = 0; r < reps; ++r) {
+                if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
+                REGC_HIP(hipGraphLaunch(c->gexec, c->stream));
+                if (c->timing && (rc = record_event(c, c->ev_sweep, false))) return rc;
+                c->sweep += per;
+            }
+            left -= reps * per;
         }
     }
+    if ((rc = eager(left))) return rc;
     if (o.sample_every > 0) c->n_rec = c->sweep / o.sample_every - c->rec_base;
     return REGC_OK;
 }
@@ -714,6 +802,7 @@ extern "C" int regc_clear_samples(regc_ctx *c)
     c->n_rec = 0;
     REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * (size_t)c->W * (c->nmax_all + 1)));
     c->trace_sweep0 = c->sweep;
+    invalidate_graph(c);
     return REGC_OK;
 }
 
@@ -863,6 +952,7 @@ extern "C" int regc_restore(regc_ctx *c, const void *buf, size_t size)
     c->rec_base = c->opts.sample_every > 0 ? c->sweep / c->opts.sample_every : 0;
     c->n_rec = 0;
     c->trace_sweep0 = c->sweep;
+    invalidate_graph(c);
     REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * W * (c->nmax_all + 1)));
     return REGC_OK;
 }

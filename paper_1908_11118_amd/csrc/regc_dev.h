@@ -61,6 +61,7 @@ struct SweepArgs {
     uint64_t th_disp, th_ins;
     double max_disp;
     int64_t sweep0;
+    const int64_t *clock;        // if set, the first sweep index is read from clock[0] (graph replays)
     int n_sweeps;
     int sample_every;
     int64_t rec_base;            // global record index of sample slot 0
@@ -88,6 +89,8 @@ struct SwapArgs {
     const double *beta, *lnz;
     uint32_t key0, key1;
     int64_t q;                   // exchange step index
+    const int64_t *clock;        // if set: q = (clock[0] + interval) / swap_every - 1
+    int interval, swap_every;
     int scheme;
     unsigned long long *att, *acc;   // [4][S_total]
     int S_total;
@@ -137,6 +140,8 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_bloc
 hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
                             hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
+hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s);
+hipError_t launch_clock_set(int64_t *clock, int64_t value, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs &a, hipStream_t s);
 hipError_t launch_energy_f32(const EnergyArgs &a, hipStream_t s);
 

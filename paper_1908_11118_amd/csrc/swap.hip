@@ -56,14 +56,15 @@ __global__ void __launch_bounds__(256) swap_kernel(SwapArgs a)
     const ClassDev &C = a.cls[c];
     const int L = C.n_t, M = C.n_mu, off = C.state_off;
     const uint32_t stream = 0xFFFFFFFFu - (uint32_t)c;
-    const uint4 T = philox4x32_10(make_uint4(0u, (uint32_t)a.q, stream, 3u), a.key0, a.key1);
+    const int64_t q = a.clock ? (a.clock[0] + a.interval) / a.swap_every - 1 : a.q;
+    const uint4 T = philox4x32_10(make_uint4(0u, (uint32_t)q, stream, 3u), a.key0, a.key1);
     const int type = (int)(T.x >> 30);
     const int P = pair_count(a.scheme, type, L, M);
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         int sa, sb;
         pair_of(a.scheme, type, p, L, M, sa, sb);
         const int lo = sa < sb ? sa : sb;
-        const uint4 R = philox4x32_10(make_uint4((uint32_t)lo, (uint32_t)a.q, stream, 4u), a.key0, a.key1);
+        const uint4 R = philox4x32_10(make_uint4((uint32_t)lo, (uint32_t)q, stream, 4u), a.key0, a.key1);
         const int ga = off + sa, gb = off + sb;
         const int i = a.wos[ga], j = a.wos[gb];
         const double x = (a.beta[ga] - a.beta[gb]) * (a.e[i] - a.e[j]) +
@@ -77,6 +78,29 @@ __global__ void __launch_bounds__(256) swap_kernel(SwapArgs a)
             a.acc[(size_t)type * a.S_total + off + lo] += 1ull;
         }
     }
+}
+
+// Advances the device-side sweep clock after one replayed exchange interval.
+__global__ void clock_advance(int64_t *clock, int n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += n;
+}
+
+hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(clock_advance, dim3(1), dim3(64), 0, s, clock, n);
+    return hipGetLastError();
+}
+
+__global__ void clock_set(int64_t *clock, int64_t value)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = value;
+}
+
+hipError_t launch_clock_set(int64_t *clock, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(clock_set, dim3(1), dim3(64), 0, s, clock, value);
+    return hipGetLastError();
 }
 
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s)

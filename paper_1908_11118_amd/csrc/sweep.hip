@@ -397,8 +397,9 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     uint64_t cand = 0;     // wave-uniform: candidate pairs of all parts
     uint32_t xcount = 0;   // exchanges so far: consecutive exchanges use alternate slots
 
+    const int64_t sweep_first = a.clock ? a.clock[0] + a.sweep0 : a.sweep0;
     for (int it = 0; it < a.n_sweeps; ++it) {
-        const int64_t sweep = a.sweep0 + it;
+        const int64_t sweep = sweep_first + it;
         const bool tracing = a.trace_bits != nullptr && (sweep - a.trace_sweep0) < a.trace_cap &&
                              sweep >= a.trace_sweep0;
         for (int t0 = 0; t0 < K; t0 += 32) {

@@ -64,7 +64,8 @@ class Opts(C.Structure):
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("sample_capacity", C.c_int64),
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
-                ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int)]
+                ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
+                ("graph_intervals", C.c_int)]
 
 
 _lib = None
@@ -157,7 +158,7 @@ class Regc:
 
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
                  walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
-                 cull: int = 0, stream=None):
+                 cull: int = 0, graph_intervals: int = 0, stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
         self.workloads = wl
@@ -179,7 +180,7 @@ class Regc:
         o.sample_every, o.swap_scheme = w0.sample_every, w0.swap_scheme
         o.sample_capacity, o.trace_capacity = sample_capacity, trace_capacity
         o.walkers_per_block, o.sweeps_per_launch, o.slab_bins = walkers_per_block, sweeps_per_launch, slab_bins
-        o.split, o.cull = split, cull
+        o.split, o.cull, o.graph_intervals = split, cull, graph_intervals
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:

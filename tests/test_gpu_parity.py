@@ -117,6 +117,48 @@ def test_fp64_edge_cases():
     _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300)
 
 
+def _batch_classes():
+    """Three classes; a batch shares one schedule (that of its first class)."""
+    c3 = W.config3_classes()
+    out = [c3[1].replace(t=W.linear_grid(0.6, 1.8, 3), mu=W.linear_grid(-5.0, -2.5, 4), n_max=70),
+           W.small_lj(n_t=2, n_mu=3, n_max=30),
+           c3[0].replace(t=W.linear_grid(0.7, 1.5, 4), mu=W.linear_grid(-6.0, -3.0, 2), n_max=50)]
+    return [w.replace(sample_every=3, swap_every=10) for w in out]
+
+
+@pytest.mark.parametrize("graph", [0, 2])
+def test_fp64_uneven_batch(graph):
+    """Three classes of different slab, box, n_max and grid in the same launches:
+    each class's trajectories equal a lone oracle simulation with the batch's
+    Philox stream offsets; with graph replay of whole exchange intervals too."""
+    classes = _batch_classes()
+    sweeps = 63
+    _say(f"[batch] {len(classes)} classes, graph={graph}")
+    with regc.Regc(classes, precision=regc.FP64, trace_capacity=sweeps, graph_intervals=graph,
+                   sample_capacity=0) as g:
+        g.run(25)
+        g.run(sweeps - 25)
+        bits, nps = g.trace(sweeps)
+        wk = g.walkers()
+        st = g.stats()
+        smp = g.samples()
+        offs, cnts = g.offsets, g.counts
+    W_all = sum(cnts)
+    for c, w in enumerate(classes):
+        ref = oracle.Chain(w, walker_offset=offs[c], class_id=c)
+        r = ref.run(sweeps, trace=True)
+        sl = slice(offs[c], offs[c] + cnts[c])
+        words = r["bits"].shape[2]
+        where = _first_divergence(bits[:, sl, :words], r["bits"], nps[:, sl], r["trace_n"])
+        assert where is None, f"class {c}: {where}"
+        assert np.array_equal(wk["n"][sl], ref.n) and np.array_equal(wk["label"][sl], ref.label)
+        assert np.allclose(wk["e"][sl], ref.e, rtol=1e-10, atol=1e-9)
+        assert np.array_equal(st["stats"][sl], ref.stats)
+        assert np.array_equal(st["swap_acc"][:, sl], ref.swap_acc)
+        rec_n = smp["n"].reshape(-1, W_all)[:, sl].ravel()
+        assert np.array_equal(rec_n, r["n"])
+
+
 def test_checkpoint_restore_continues_identically():
     w = W.small_lj(n_t=2, n_mu=4, n_max=20)
     _say("[checkpoint] small_lj 2x4")
