@@ -181,3 +181,43 @@ def random_configuration(rng: np.random.Generator, w: Workload, n: int, min_dist
     if len(pts) < n:
         raise RuntimeError("could not place the requested number of particles")
     return np.array(pts, dtype=np.float64).reshape(-1, 3)
+
+
+# ---------------------------------------------------------------------------
+# learned insertion proposal: network shape and seeded initial weights
+MLP_GRID = 16
+MLP_NV = MLP_GRID ** 3
+MLP_HIDDEN = 128
+MLP_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+MLP_SHAPES = {"W1": (MLP_NV, MLP_HIDDEN), "b1": (MLP_HIDDEN,), "W2": (MLP_HIDDEN, MLP_HIDDEN),
+              "b2": (MLP_HIDDEN,), "W3": (MLP_HIDDEN, MLP_HIDDEN), "b3": (MLP_HIDDEN,),
+              "W4": (MLP_NV, MLP_HIDDEN), "b4": (MLP_NV,)}
+
+
+def mlp_init(seed: int = 0, occupancy_scale: float = 20.0, out_scale: float = 0.1) -> dict:
+    """Seeded float32 initial weights.  W1 is stored voxel-major ([4096][128]: the
+    column of each input voxel is contiguous), W2/W3 as [out][in], W4 as [4096][128]
+    (one row per output voxel).  Normal entries with std 1/sqrt(occupancy_scale)
+    (W1), sqrt(2/128) (W2, W3) and out_scale/sqrt(128) (W4); zero biases."""
+    rng = np.random.default_rng(seed)
+    p = {"W1": rng.normal(0.0, 1.0 / math.sqrt(occupancy_scale), MLP_SHAPES["W1"]),
+         "W2": rng.normal(0.0, math.sqrt(2.0 / MLP_HIDDEN), MLP_SHAPES["W2"]),
+         "W3": rng.normal(0.0, math.sqrt(2.0 / MLP_HIDDEN), MLP_SHAPES["W3"]),
+         "W4": rng.normal(0.0, out_scale / math.sqrt(MLP_HIDDEN), MLP_SHAPES["W4"])}
+    for b in ("b1", "b2", "b3", "b4"):
+        p[b] = np.zeros(MLP_SHAPES[b])
+    return {k: np.asarray(v, dtype=np.float32) for k, v in p.items()}
+
+
+def mlp_pack(p: dict) -> np.ndarray:
+    """Parameters concatenated in MLP_ORDER as one float32 vector."""
+    return np.concatenate([np.asarray(p[k], np.float32).ravel() for k in MLP_ORDER])
+
+
+def mlp_unpack(flat) -> dict:
+    out, o = {}, 0
+    for k in MLP_ORDER:
+        size = int(np.prod(MLP_SHAPES[k]))
+        out[k] = np.asarray(flat[o:o + size], np.float32).reshape(MLP_SHAPES[k])
+        o += size
+    return out

@@ -1,0 +1,106 @@
+"""Pins of the learned-proposal oracle: bfloat16 rounding against torch's
+conversion, GELU against its closed form, FP64 gradients against central finite
+differences, the first Adam step, and the alpha = 0 limit of the proposal density.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_1908_11118_amd import workloads as W
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(0, 10, 5000), rng.uniform(-1e-3, 1e-3, 1000),
+                        [0.0, -0.0, 1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 65504.0, 3.4e38]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(M.bf16_round(x), ref)
+
+
+def test_gelu_closed_form():
+    assert M.gelu(np.array([0.0]))[0] == 0.0
+    for x in (-3.0, -0.5, 0.3, 1.0, 2.7):
+        ref = 0.5 * x * (1 + math.erf(x / math.sqrt(2)))
+        assert abs(M.gelu(np.array([x]))[0] - ref) < 1e-15
+        h = 1e-6
+        fd = (M.gelu(np.array([x + h]))[0] - M.gelu(np.array([x - h]))[0]) / (2 * h)
+        assert abs(M.gelu_grad(np.array([x]))[0] - fd) < 1e-8
+    assert abs(M.gelu(np.array([8.0]))[0] - 8.0) < 1e-12
+    assert abs(M.gelu(np.array([-8.0]))[0]) < 1e-12
+
+
+def _batch(rng, B=6, nmax=12):
+    n = rng.integers(2, nmax + 1, B)
+    vox = rng.integers(0, M.NV, (B, nmax))
+    vox[0, 1] = vox[0, 0]                   # a doubly occupied voxel
+    excl = np.array([rng.integers(0, k) for k in n])
+    target = np.array([vox[b, excl[b]] for b in range(B)])
+    return vox, n, excl, target
+
+
+def test_fp64_gradients_match_finite_differences():
+    rng = np.random.default_rng(1)
+    params = {k: v.astype(np.float64) for k, v in W.mlp_init(3, out_scale=1.0).items()}
+    for k in ("b1", "b2", "b3", "b4"):
+        params[k] = rng.normal(0, 0.1, params[k].shape)
+    vox, n, excl, target = _batch(rng)
+    loss, g = M.loss_and_grads(params, vox, n, excl, target, "fp64")
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        flat = params[name].reshape(-1)
+        if name == "W1":
+            idx = [vox[0, 0] * M.H + 5, vox[1, 0] * M.H + 77]        # rows that carry gradient
+        elif name in ("W4", "b4"):
+            idx = [target[0] * (M.H if name == "W4" else 1), int(rng.integers(0, flat.size))]
+        else:
+            idx = list(rng.integers(0, flat.size, 3))
+        for i in idx:
+            h = 1e-6 * max(1.0, abs(flat[i]))
+            old = flat[i]
+            flat[i] = old + h
+            lp, _ = M.loss_and_grads(params, vox, n, excl, target, "fp64")
+            flat[i] = old - h
+            lm, _ = M.loss_and_grads(params, vox, n, excl, target, "fp64")
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, i, fd, an)
+
+
+def test_bf16_path_close_to_fp64():
+    rng = np.random.default_rng(2)
+    params = W.mlp_init(4, out_scale=1.0)
+    vox, n, excl, target = _batch(rng, B=16)
+    l64, g64 = M.loss_and_grads({k: v.astype(np.float64) for k, v in params.items()}, vox, n, excl, target, "fp64")
+    l16, g16 = M.loss_and_grads(params, vox, n, excl, target, "bf16")
+    assert abs(l64 - l16) < 2e-2 * max(1.0, abs(l64))
+    for k in g64:
+        scale = np.abs(g64[k]).max()
+        assert np.abs(g64[k] - g16[k]).max() <= 5e-2 * scale + 1e-12, k
+
+
+def test_adam_first_step_is_signed_lr():
+    p = {"a": np.array([0.5, -1.0, 2.0, 0.0])}
+    g = {"a": np.array([0.3, -2e-3, 7.0, 0.0])}
+    st = {}
+    out = M.adam(dict(p), g, st, lr=1e-3, eps=1e-8)["a"]
+    step = 1e-3 * g["a"] / (np.abs(g["a"]) + 1e-8)
+    assert np.allclose(out, p["a"] - step, atol=1e-15)
+
+
+def test_proposal_density_limits_and_voxels():
+    params = W.mlp_init(5)
+    rng = np.random.default_rng(6)
+    vox, n, excl, target = _batch(rng)
+    V = 288.0
+    lq0, _ = M.log_q(params, vox, n, excl, target, 0.0, V)
+    assert np.allclose(lq0, -math.log(V))
+    lq1, lp = M.log_q(params, vox, n, excl, target, 1.0, V)
+    assert np.allclose(np.exp(lp).sum(1), 1.0)
+    assert np.allclose(lq1, lp[np.arange(len(n)), target] - math.log(V / M.NV))
+    # voxel indexing: corners and clamping
+    v = M.voxel_of([[0.0, 0.0, 0.0], [5.999, 0.0, 0.0], [0.0, 5.999, 0.0], [0.0, 0.0, 8.0], [6.0, 6.0, 8.0]],
+                   6.0, 6.0, 0.0, 8.0)
+    assert list(v) == [0, 15, 15 * 16, 15 * 256, 4095]
