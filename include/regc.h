@@ -295,6 +295,44 @@ int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter);
 
 void regc_mbar_destroy(regc_mbar *mb);
 
+/* ---- learned insertion proposal (not in the paper; keeps its statistics) ---- */
+/* A multilayer perceptron maps the 16^3 occupancy grid of the gas region (voxel
+ * (iz*16 + iy)*16 + ix, cells of lx/16 x ly/16 x (z_hi - z_lo)/16, indices clamped)
+ * to a 4096-bin categorical over insertion voxels: occupancy -> 128 -> 128 -> 128
+ * -> 4096 with GELU (erf form) after the hidden layers.  bfloat16 weights and
+ * activations on MFMA, FP32 accumulation, FP32 master weights and Adam state.
+ * Parameter vector (FP32, regc_mlp_param_count entries): W1 [4096][128]
+ * (voxel-major), b1 [128], W2 [128][128] ([out][in]), b2, W3, b3, W4 [4096][128],
+ * b4 [4096].  A training example is a configuration given as the voxel of each
+ * particle (vox [nmax] per example, n particles), one particle left out (excl, or
+ * -1 for none) and, for training, the left-out particle's voxel as target. */
+typedef struct regc_mlp regc_mlp;
+
+int regc_mlp_param_count(int64_t *count);
+/* params may be NULL (all zero). */
+int regc_mlp_create(const float *params, regc_mlp **out);
+int regc_mlp_set_stream(regc_mlp *mlp, void *stream);
+/* Replaces the parameters and resets the Adam state. */
+int regc_mlp_set_params(regc_mlp *mlp, const float *params);
+int regc_mlp_get_params(regc_mlp *mlp, float *params);
+/* Logits [B][4096] of B examples (B a positive multiple of 64); host arrays
+ * vox [B][nmax] (uint16 voxel indices), n [B], excl [B]. */
+int regc_mlp_forward(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, const int32_t *n, const int32_t *excl,
+                     float *logits);
+/* Mean cross-entropy of target [B] and its gradient (FP32, parameter layout;
+ * grads may be NULL); no update. */
+int regc_mlp_loss_grads(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, const int32_t *n,
+                        const int32_t *excl, const int32_t *target, double *loss, float *grads);
+/* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on batches drawn from a
+ * device data set of n_examples configurations (vox_dev [n_examples][nmax],
+ * n_dev [n_examples], every n >= 1): example and left-out particle from Philox
+ * keyed by seed.  mean_loss (may be NULL) receives the last batch's loss. */
+int regc_mlp_train(regc_mlp *mlp, int64_t n_examples, int nmax, const uint16_t *vox_dev, const int32_t *n_dev,
+                   int64_t steps, int batch, double lr, uint64_t seed, double *mean_loss);
+/* Accumulated training time in ms and steps. */
+int regc_mlp_timing(regc_mlp *mlp, double *ms, int64_t *steps);
+void regc_mlp_destroy(regc_mlp *mlp);
+
 /* ---- errors ---------------------------------------------------------------- */
 const char *regc_strerror(int code);
 const char *regc_last_error(void);

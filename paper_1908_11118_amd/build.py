@@ -28,6 +28,7 @@ UNITS = [
     ("sweep.hip", "sweep_f32.o", ["-DREGC_FP32"]),
     ("swap.hip", "swap.o", ["-ffp-contract=off"]),
     ("mbar.hip", "mbar.o", []),
+    ("mlp.hip", "mlp.o", []),
     ("api.cpp", "api.o", ["-x", "hip"]),
 ]
 

@@ -29,7 +29,10 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_get_stats", "regc_get_pair_counts", "regc_get_histograms", "regc_get_trace", "regc_timing_enable", "regc_timing_get",
            "regc_checkpoint", "regc_restore", "regc_destroy", "regc_mbar_create", "regc_mbar_set_stream",
            "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_set_solver", "regc_mbar_solve", "regc_mbar_targets",
-           "regc_mbar_timing", "regc_mbar_destroy", "regc_strerror", "regc_last_error"]
+           "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
+           "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
+           "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
+           "regc_strerror", "regc_last_error"]
 
 
 class RegcError(RuntimeError):
@@ -118,6 +121,20 @@ def lib():
         L.regc_mbar_timing.argtypes = [vp, _dp, _i64p]
         L.regc_mbar_destroy.argtypes = [vp]
         L.regc_mbar_destroy.restype = None
+        _u16p = C.POINTER(C.c_uint16)
+        L.regc_mlp_param_count.argtypes = [_i64p]
+        L.regc_mlp_create.argtypes = [C.POINTER(C.c_float), C.POINTER(vp)]
+        L.regc_mlp_set_stream.argtypes = [vp, vp]
+        L.regc_mlp_set_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.regc_mlp_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.regc_mlp_forward.argtypes = [vp, C.c_int, C.c_int, _u16p, _i32p, _i32p, C.POINTER(C.c_float)]
+        L.regc_mlp_loss_grads.argtypes = [vp, C.c_int, C.c_int, _u16p, _i32p, _i32p, _i32p, _dp,
+                                          C.POINTER(C.c_float)]
+        L.regc_mlp_train.argtypes = [vp, C.c_int64, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_double,
+                                     C.c_uint64, _dp]
+        L.regc_mlp_timing.argtypes = [vp, _dp, _i64p]
+        L.regc_mlp_destroy.argtypes = [vp]
+        L.regc_mlp_destroy.restype = None
         L.regc_strerror.argtypes = [C.c_int]
         L.regc_strerror.restype = C.c_char_p
         L.regc_last_error.restype = C.c_char_p
@@ -383,3 +400,80 @@ class Mbar:
         n = C.c_int64()
         _check(lib().regc_mbar_timing(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+_fp = C.POINTER(C.c_float)
+_u16p = C.POINTER(C.c_uint16)
+
+
+class Mlp:
+    """The learned insertion proposal network on the GPU (training and evaluation)."""
+
+    def __init__(self, params=None, stream=None):
+        cnt = C.c_int64()
+        _check(lib().regc_mlp_param_count(C.byref(cnt)))
+        self.n_params = cnt.value
+        flat = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if flat is not None and flat.size != self.n_params:
+            raise ValueError("parameter vector has the wrong length")
+        h = C.c_void_p()
+        _check(lib().regc_mlp_create(_p(flat, _fp), C.byref(h)))
+        self.h = h
+        s = stream if stream is not None else _torch_stream()
+        if s is not None:
+            _check(lib().regc_mlp_set_stream(h, s))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().regc_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        _check(lib().regc_mlp_get_params(self.h, _p(out, _fp)))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().regc_mlp_set_params(self.h, _p(flat, _fp)))
+
+    @staticmethod
+    def _batch(vox, n, excl):
+        vox = np.ascontiguousarray(vox, dtype=np.uint16)
+        return vox, np.ascontiguousarray(n, dtype=np.int32), np.ascontiguousarray(excl, dtype=np.int32)
+
+    def forward(self, vox, n, excl):
+        vox, n, excl = self._batch(vox, n, excl)
+        B, nmax = vox.shape
+        out = np.zeros((B, 4096), np.float32)
+        _check(lib().regc_mlp_forward(self.h, B, nmax, _p(vox, _u16p), _p(n, _i32p), _p(excl, _i32p), _p(out, _fp)))
+        return out
+
+    def loss_grads(self, vox, n, excl, target):
+        vox, n, excl = self._batch(vox, n, excl)
+        tgt = np.ascontiguousarray(target, dtype=np.int32)
+        B, nmax = vox.shape
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        _check(lib().regc_mlp_loss_grads(self.h, B, nmax, _p(vox, _u16p), _p(n, _i32p), _p(excl, _i32p),
+                                         _p(tgt, _i32p), C.byref(loss), _p(g, _fp)))
+        return loss.value, g
+
+    def train(self, n_examples: int, nmax: int, vox_dev_ptr: int, n_dev_ptr: int, steps: int, batch: int = 256,
+              lr: float = 1e-3, seed: int = 1):
+        loss = C.c_double()
+        _check(lib().regc_mlp_train(self.h, n_examples, nmax, C.c_void_p(vox_dev_ptr), C.c_void_p(n_dev_ptr), steps,
+                                    batch, lr, seed, C.byref(loss)))
+        return loss.value
+
+    def timing(self):
+        ms = C.c_double()
+        st = C.c_int64()
+        _check(lib().regc_mlp_timing(self.h, C.byref(ms), C.byref(st)))
+        return ms.value, st.value
