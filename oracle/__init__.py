@@ -64,12 +64,13 @@ class _Config(C.Structure):
                 ("seed", C.c_uint64), ("p_disp", C.c_double), ("p_ins", C.c_double),
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("walker_offset", C.c_int),
-                ("class_id", C.c_int)]
+                ("class_id", C.c_int), ("net", C.POINTER(C.c_float)), ("alpha", C.c_double)]
 
 
 class _Walkers(C.Structure):
     _fields_ = [("n", _i32p), ("e", _dp), ("label", _i32p), ("wos", _i32p), ("xyz", _dp),
-                ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p)]
+                ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p),
+                ("margin", C.POINTER(C.c_float))]
 
 
 def _declare(L):
@@ -87,6 +88,13 @@ def _declare(L):
     L.orc_swap_lnratio.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_int, C.c_double, C.c_int]
     L.orc_swap_lnratio.restype = C.c_double
+    L.orc_voxel_of.argtypes = [C.POINTER(_Config), _dp]
+    L.orc_voxel_of.restype = C.c_int
+    L.orc_net_logits.argtypes = [C.POINTER(_Config), _dp, C.c_int, C.c_int, C.POINTER(C.c_float)]
+    L.orc_net_logits.restype = C.c_double
+    L.orc_gumbel_argmax.argtypes = [C.POINTER(_Config), C.POINTER(C.c_float), C.c_uint32, C.c_uint32,
+                                    C.c_uint32, _dp]
+    L.orc_gumbel_argmax.restype = C.c_int
     L.orc_mbar_solve.argtypes = [C.c_int, _dp, _dp, _i64p, C.c_int64, _dp, _i32p, C.c_double,
                                  C.c_int, _dp, _dp, C.POINTER(C.c_int), _dp, C.c_int]
     L.orc_mbar_solve.restype = C.c_int
@@ -144,9 +152,14 @@ def state_arrays(w):
 
 
 class Chain:
-    """All walkers of one REGC simulation, advanced by the C oracle."""
+    """All walkers of one REGC simulation, advanced by the C oracle.
 
-    def __init__(self, w, n_threads: int | None = None, walker_offset: int = 0, class_id: int = 0):
+    net / alpha: the learned insertion proposal (FP32 parameter vector of the
+    network, mixture weight of its branch); alpha = 0 or net = None is the plain
+    method."""
+
+    def __init__(self, w, n_threads: int | None = None, walker_offset: int = 0, class_id: int = 0,
+                 net=None, alpha: float = 0.0):
         self.w = w
         self.S = len(w.t) * len(w.mu)
         self.n_max = int(w.n_max)
@@ -174,6 +187,11 @@ class Chain:
         c.trials_per_sweep, c.swap_every = w.trials_per_sweep, w.swap_every
         c.sample_every, c.swap_scheme = w.sample_every, w.swap_scheme
         c.walker_offset, c.class_id = walker_offset, class_id
+        self._net = None
+        if net is not None:
+            self._net = np.ascontiguousarray(net, dtype=np.float32).ravel()
+            c.net = self._net.ctypes.data_as(C.POINTER(C.c_float))
+        c.alpha = float(alpha)
         self.cfg = c
         S = self.S
         # initial state: empty walkers, walker w holds state w
@@ -215,9 +233,11 @@ class Chain:
         x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         return lib().orc_total_energy(C.byref(self.cfg), x.shape[0], _p(x, _dp))
 
-    def run(self, n_sweeps: int, trace: bool = False):
+    def run(self, n_sweeps: int, trace: bool = False, margins: bool = False):
         """Advance n_sweeps sweeps.  Returns dict with samples (e, n, state) and,
-        when trace is set, accept bits [n_sweeps, S, words] and N [n_sweeps, S]."""
+        when trace is set, accept bits [n_sweeps, S, words] and N [n_sweeps, S];
+        with margins, the learned proposal's per-trial decision margins
+        [n_sweeps, S, K] (+inf where the network took no part)."""
         S = self.S
         every = self.w.sample_every
         s0 = int(self.sweep[0])
@@ -232,6 +252,9 @@ class Chain:
         tb = np.zeros((n_sweeps, S, words), dtype=np.uint32) if trace else None
         tn = np.zeros((n_sweeps, S), dtype=np.int32) if trace else None
         W = self._walkers()
+        mg = np.zeros((n_sweeps, S, self.K), dtype=np.float32) if margins else None
+        if margins:
+            W.margin = mg.ctypes.data_as(C.POINTER(C.c_float))
         rc = lib().orc_run(C.byref(self.cfg), C.byref(W), _p(self.sweep, _i64p), n_sweeps,
                            _p(se, _dp), _p(sn, _i32p), _p(ss, _i32p), n_samp, _p(cnt, _i64p),
                            _p(tb, _u32p), _p(tn, _i32p), self.n_threads)
@@ -241,7 +264,31 @@ class Chain:
         out = {"e": se[:k], "n": sn[:k], "state": ss[:k]}
         if trace:
             out["bits"], out["trace_n"] = tb, tn
+        if margins:
+            out["margin"] = mg
         return out
+
+    def voxel_of(self, p) -> int:
+        q = np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+        return lib().orc_voxel_of(C.byref(self.cfg), _p(q, _dp))
+
+    def net_logits(self, xyz, skip: int = -1):
+        """Network logits [4096] (FP32) for the occupancy of xyz without particle
+        `skip`, and the FP64 log-normaliser."""
+        if self._net is None:
+            raise ValueError("no network attached")
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(4096, dtype=np.float32)
+        lse = lib().orc_net_logits(C.byref(self.cfg), _p(x, _dp), x.shape[0], int(skip),
+                                   out.ctypes.data_as(C.POINTER(C.c_float)))
+        return out, lse
+
+    def gumbel_argmax(self, logits, t: int, sweep: int, walker: int):
+        lg = np.ascontiguousarray(logits, dtype=np.float32)
+        gap = np.zeros(1)
+        v = lib().orc_gumbel_argmax(C.byref(self.cfg), lg.ctypes.data_as(C.POINTER(C.c_float)), t, sweep,
+                                    walker, _p(gap, _dp))
+        return v, float(gap[0])
 
     def swap_step(self, q: int):
         W = self._walkers()

@@ -29,6 +29,16 @@
  *   - LJ 12-6 pair potential: Appendix, truncated and shifted at rc.
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written
  * here from its published definition.
+ *
+ * Extension, not in the paper: a learned insertion proposal.  A network maps the
+ * 16^3 occupancy grid of a configuration to a categorical over the 4096 voxels of
+ * the gas region; an insertion point is either a voxel drawn from it plus a
+ * uniform offset (probability alpha) or a uniform point of V, so its density is
+ * q(r|X) = alpha P(v(r)|occ(X)) / V_vox + (1 - alpha) / V, and the acceptance
+ * ratios of Eqs. (2)-(3) take the Metropolis-Hastings form
+ *   insertion  ln A = ln z - ln(N+1) - ln q(r|X) - beta dE,
+ *   removal    ln A = ln N + ln q(r_i|X without i) - ln z - beta dE,
+ * which keeps Eq. (1) the stationary distribution for any network.
  */
 #include <math.h>
 #include <stdint.h>
@@ -113,6 +123,10 @@ typedef struct {
      * walker index is offset by walker_offset, its exchange stream is
      * 0xFFFFFFFF - class_id (both 0 for a lone simulation) */
     int walker_offset, class_id;
+    /* learned insertion proposal: network parameters (FP32, layout below) or NULL,
+     * and the mixture weight alpha of the network branch (0: plain method) */
+    const float *net;
+    double alpha;
 } orc_config;
 
 /* derived per-state constants */
@@ -214,6 +228,167 @@ double orc_total_energy(const orc_config *c, int n, const double *xyz)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Learned insertion proposal network                                        */
+/* ------------------------------------------------------------------------- */
+/* Parameter vector (FP32): W1 [4096][128] (row v: the weights of input voxel v),
+ * b1 [128], W2 [128][128] ([out][in]), b2 [128], W3 [128][128], b3 [128],
+ * W4 [4096][128] (row v: output voxel v), b4 [4096].
+ * Arithmetic of the sampler's network: weights and hidden activations rounded
+ * to bfloat16 (nearest, ties to even), products and sums in FP32, GELU in its
+ * erf form; the log-normaliser and everything after it in FP64. */
+#define NET_G 16
+#define NET_NV (NET_G * NET_G * NET_G)
+#define NET_H 128
+#define NET_NPARAM ((size_t)NET_NV * NET_H + NET_H + 2 * ((size_t)NET_H * NET_H + NET_H) + (size_t)NET_NV * NET_H + NET_NV)
+
+typedef struct {
+    float *W1, *W2, *W3, *W4;        /* bfloat16-rounded copies */
+    const float *b1, *b2, *b3, *b4;
+} orc_net;
+
+static float bf16_round(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return x;          /* NaN */
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&x, &u, 4);
+    return x;
+}
+
+static float gelu(float x) { return 0.5f * x * (1.0f + (float)erf((double)x / sqrt(2.0))); }
+
+static void net_prepare(const float *P, orc_net *net)
+{
+    const float *W1 = P, *b1 = W1 + (size_t)NET_NV * NET_H, *W2 = b1 + NET_H, *b2 = W2 + NET_H * NET_H,
+                *W3 = b2 + NET_H, *b3 = W3 + NET_H * NET_H, *W4 = b3 + NET_H, *b4 = W4 + (size_t)NET_NV * NET_H;
+    net->W1 = (float *)malloc(sizeof(float) * (size_t)NET_NV * NET_H);
+    net->W2 = (float *)malloc(sizeof(float) * NET_H * NET_H);
+    net->W3 = (float *)malloc(sizeof(float) * NET_H * NET_H);
+    net->W4 = (float *)malloc(sizeof(float) * (size_t)NET_NV * NET_H);
+    for (size_t k = 0; k < (size_t)NET_NV * NET_H; ++k) {
+        net->W1[k] = bf16_round(W1[k]);
+        net->W4[k] = bf16_round(W4[k]);
+    }
+    for (int k = 0; k < NET_H * NET_H; ++k) {
+        net->W2[k] = bf16_round(W2[k]);
+        net->W3[k] = bf16_round(W3[k]);
+    }
+    net->b1 = b1; net->b2 = b2; net->b3 = b3; net->b4 = b4;
+}
+
+static void net_release(orc_net *net)
+{
+    free(net->W1); free(net->W2); free(net->W3); free(net->W4);
+}
+
+/* Voxel (iz*16 + iy)*16 + ix of a point of the gas region, each axis cut in 16
+ * equal cells, indices clamped to the grid. */
+static int voxel_of(const orc_config *c, const double *p)
+{
+    long ix = (long)floor(p[0] * (NET_G / c->lx));
+    long iy = (long)floor(p[1] * (NET_G / c->ly));
+    long iz = (long)floor((p[2] - c->zlo) * (NET_G / (c->zhi - c->zlo)));
+    ix = ix < 0 ? 0 : (ix > NET_G - 1 ? NET_G - 1 : ix);
+    iy = iy < 0 ? 0 : (iy > NET_G - 1 ? NET_G - 1 : iy);
+    iz = iz < 0 ? 0 : (iz > NET_G - 1 ? NET_G - 1 : iz);
+    return (int)((iz * NET_G + iy) * NET_G + ix);
+}
+
+/* hidden layer: out[o] = bf16(gelu(sum_k W[o][k] in[k] + b[o])) */
+static void net_layer(const float *W, const float *b, const float *in, float *out)
+{
+    for (int o = 0; o < NET_H; ++o) {
+        float s = 0.0f;
+        for (int k = 0; k < NET_H; ++k) s += W[o * NET_H + k] * in[k];
+        out[o] = bf16_round(gelu(s + b[o]));
+    }
+}
+
+/* Logits of the network for the occupancy of xyz[0..n) without particle `skip`
+ * (-1: none); returns the log-normaliser ln sum_v exp(logit_v).  The first layer
+ * is the sum over occupied voxels, in ascending voxel order, of count * W1 row. */
+static double net_logits(const orc_config *c, const orc_net *net, const double *xyz, int n, int skip,
+                         float *logit)
+{
+    int occ[NET_NV];
+    memset(occ, 0, sizeof occ);
+    for (int j = 0; j < n; ++j)
+        if (j != skip) occ[voxel_of(c, xyz + 3 * j)]++;
+    float a[NET_H], h1[NET_H], h2[NET_H], h3[NET_H];
+    for (int k = 0; k < NET_H; ++k) a[k] = net->b1[k];
+    for (int v = 0; v < NET_NV; ++v) {
+        if (!occ[v]) continue;
+        const float cnt = (float)occ[v];
+        for (int k = 0; k < NET_H; ++k) a[k] += cnt * net->W1[(size_t)v * NET_H + k];
+    }
+    for (int k = 0; k < NET_H; ++k) h1[k] = bf16_round(gelu(a[k]));
+    net_layer(net->W2, net->b2, h1, h2);
+    net_layer(net->W3, net->b3, h2, h3);
+    double mx = -INFINITY;
+    for (int v = 0; v < NET_NV; ++v) {
+        float s = 0.0f;
+        for (int k = 0; k < NET_H; ++k) s += net->W4[(size_t)v * NET_H + k] * h3[k];
+        logit[v] = s + net->b4[v];
+        if ((double)logit[v] > mx) mx = (double)logit[v];
+    }
+    double sum = 0.0;
+    for (int v = 0; v < NET_NV; ++v) sum += exp((double)logit[v] - mx);
+    return mx + log(sum);
+}
+
+/* Gumbel-max draw from softmax(logit): the voxel maximising logit_v - ln(-ln u_v),
+ * u_v = open uniform of word v%4 of the Philox block (t, sweep, walker, 16 + v/4);
+ * ties go to the lowest v.  *gap = best key minus the runner-up. */
+static int gumbel_argmax(const orc_config *c, const float *logit, uint32_t t, uint32_t sweep, uint32_t wid,
+                         double *gap)
+{
+    double best = -INFINITY, second = -INFINITY;
+    int arg = 0;
+    for (int b = 0; b < NET_NV / 4; ++b) {
+        uint32_t R[4];
+        philox_words(c->seed, t, sweep, wid, 16u + (uint32_t)b, R);
+        for (int q = 0; q < 4; ++q) {
+            const int v = 4 * b + q;
+            const double key = (double)logit[v] - log(-log(u32_open(R[q])));
+            if (key > best) {
+                second = best;
+                best = key;
+                arg = v;
+            } else if (key > second) {
+                second = key;
+            }
+        }
+    }
+    *gap = best - second;
+    return arg;
+}
+
+/* ln q(r|X) - ln(1/V) = ln(1 + alpha (P_v V / V_vox - 1)), with V / V_vox = 4096 */
+static double ln_q_ratio(double alpha, double lnp)
+{
+    return log1p(alpha * (exp(lnp) * (double)NET_NV - 1.0));
+}
+
+/* exported for the tests */
+int orc_voxel_of(const orc_config *c, const double *p) { return voxel_of(c, p); }
+
+double orc_net_logits(const orc_config *c, const double *xyz, int n, int skip, float *logit)
+{
+    orc_net net;
+    net_prepare(c->net, &net);
+    double lse = net_logits(c, &net, xyz, n, skip, logit);
+    net_release(&net);
+    return lse;
+}
+
+int orc_gumbel_argmax(const orc_config *c, const float *logit, uint32_t t, uint32_t sweep, uint32_t wid,
+                      double *gap)
+{
+    return gumbel_argmax(c, logit, t, sweep, wid, gap);
+}
+
+/* ------------------------------------------------------------------------- */
 /* One trial move of one walker                                              */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -226,6 +401,10 @@ typedef struct {
     int64_t *stats;    /* [S][ORC_NSTAT] by state */
     int64_t *swap_att; /* [4][S] by swap type and lower state of the pair */
     int64_t *swap_acc;
+    /* [n_sweeps][S][K] or NULL: per trial, the distance of the learned proposal's
+     * decisions from their thresholds (|ln A - ln U|, and the Gumbel-max gap of a
+     * network-drawn voxel); +inf for trials the network took no part in */
+    float *margin;
 } orc_walkers;
 
 /* Metropolis decision on x = ln(acceptance ratio): accept when x >= 0, else
@@ -245,7 +424,7 @@ static int site_occupied(const int32_t *site, int n, int k)
 
 /* Returns 1 if the trial was accepted.  `lnk` holds log(k) for k = 0..n_max+1. */
 static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, double lnv,
-                 orc_walkers *W, int w, int64_t sweep, int t)
+                 const orc_net *net, orc_walkers *W, int w, int64_t sweep, int t, float *margin)
 {
     uint32_t A[4], B[4];
     const uint32_t wid = (uint32_t)(w + c->walker_offset);
@@ -319,10 +498,33 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
         if (n >= c->n_max) { st[ST_CAP_REJ]++; return 0; }
         double p[3];
         int core = 0, k = -1;
+        double lnq = 0.0;
         if (c->mode == 2) {
             k = (int)(((uint64_t)A[2] * (uint64_t)c->n_sites) >> 32);
             if (site_occupied(site, n, k)) return 0;
             memcpy(p, c->sites + 3 * k, sizeof p);
+        } else if (net) {
+            /* learned proposal: network voxel with probability alpha, else uniform */
+            float logit[NET_NV];
+            const double lse = net_logits(c, net, xyz, n, -1, logit);
+            int v;
+            if (u32_open(B[3]) < c->alpha) {
+                double gap;
+                v = gumbel_argmax(c, logit, (uint32_t)t, (uint32_t)sweep, wid, &gap);
+                if (margin) *margin = (float)gap;
+                const int ix = v % NET_G, iy = (v / NET_G) % NET_G, iz = v / (NET_G * NET_G);
+                p[0] = ((double)ix + u32_open(A[2])) * (c->lx / NET_G);
+                p[1] = ((double)iy + u32_open(A[3])) * (c->ly / NET_G);
+                p[2] = c->zlo + ((double)iz + u32_open(B[0])) * ((c->zhi - c->zlo) / NET_G);
+                /* a point rounded onto a neighbouring voxel is not a draw of v */
+                if (voxel_of(c, p) != v) { st[ST_WALL_REJ]++; return 0; }
+            } else {
+                p[0] = c->lx * u32_open(A[2]);
+                p[1] = c->ly * u32_open(A[3]);
+                p[2] = c->zlo + (c->zhi - c->zlo) * u32_open(B[0]);
+                v = voxel_of(c, p);
+            }
+            lnq = ln_q_ratio(c->alpha, (double)logit[v] - lse);
         } else {
             p[0] = c->lx * u32_open(A[2]);
             p[1] = c->ly * u32_open(A[3]);
@@ -333,8 +535,13 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
             de = particle_energy(c, p, xyz, n, -1, &core);
             if (core && c->mode == 0) { st[ST_CORE_REJ]++; return 0; }
         }
-        /* ln A = ln z + ln V - ln(N+1) - beta dE  (V -> number of sites in mode 2) */
-        double x = ((lnz + lnv) - lnk[n + 1]) - beta * de;
+        /* ln A = ln z + ln V - ln(N+1) - beta dE  (V -> number of sites in mode 2);
+         * learned proposal: ln V -> -ln q = ln V - lnq */
+        double x = (((lnz + lnv) - lnk[n + 1]) - lnq) - beta * de;
+        if (net && margin) {
+            const float mg = (float)fabs(x - log(U));
+            if (mg < *margin) *margin = mg;
+        }
         if (metropolis(x, U)) {
             memcpy(xyz + 3 * n, p, sizeof p);
             if (site) site[n] = k;
@@ -352,8 +559,21 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
         double de = 0.0;
         int core = 0;
         if (c->mode != 1) de = -particle_energy(c, xyz + 3 * i, xyz, n, i, &core);
-        /* ln A = ln N - ln z - ln V - beta dE,  dE = E_{N-1} - E_N */
-        double x = (lnk[n] - (lnz + lnv)) - beta * de;
+        /* learned proposal: the reverse insertion's density at r_i, on the occupancy
+         * of the configuration without i */
+        double lnq = 0.0;
+        if (net) {
+            float logit[NET_NV];
+            const double lse = net_logits(c, net, xyz, n, i, logit);
+            lnq = ln_q_ratio(c->alpha, (double)logit[voxel_of(c, xyz + 3 * i)] - lse);
+        }
+        /* ln A = ln N - ln z - ln V - beta dE,  dE = E_{N-1} - E_N;
+         * learned proposal: -ln V -> ln q = -ln V + lnq */
+        double x = ((lnk[n] - (lnz + lnv)) + lnq) - beta * de;
+        if (net && margin) {
+            const float mg = (float)fabs(x - log(U));
+            if (mg < *margin) *margin = mg;
+        }
         if (metropolis(x, U)) {
             /* the removed slot is refilled by the last particle */
             if (i != n - 1) {
@@ -452,6 +672,17 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
     double lnv = (c->mode == 2) ? log((double)c->n_sites)
                                 : log(c->lx * c->ly * (c->zhi - c->zlo));
     int rc = 0;
+    /* the network takes part only with alpha > 0 (alpha = 0 is the plain method) */
+    orc_net netr, *net = NULL;
+    if (c->net && c->alpha > 0.0) {
+        if (c->mode == 2 || c->alpha > 1.0) {
+            free(sc);
+            free(lnk);
+            return -6;
+        }
+        net_prepare(c->net, &netr);
+        net = &netr;
+    }
     for (int64_t it = 0; it < n_sweeps; ++it) {
         const int64_t s = *sweep;
         if (c->sample_every > 0 && (s + 1) % c->sample_every == 0 && *samp_count + S > samp_cap) {
@@ -461,9 +692,11 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
 #pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
         for (int w = 0; w < S; ++w) {
             uint32_t *bits = trace_bits ? trace_bits + ((int64_t)it * S + w) * words : NULL;
+            float *mrow = W->margin ? W->margin + ((int64_t)it * S + w) * K : NULL;
             if (bits) memset(bits, 0, sizeof(uint32_t) * words);
             for (int t = 0; t < K; ++t) {
-                int acc = trial(c, sc, lnk, lnv, W, w, s, t);
+                if (mrow) mrow[t] = INFINITY;
+                int acc = trial(c, sc, lnk, lnv, net, W, w, s, t, mrow ? mrow + t : NULL);
                 if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
             }
             if (trace_n) trace_n[(int64_t)it * S + w] = W->n[w];
@@ -480,6 +713,7 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
             swap_step(c, sc, W, (s + 1) / c->swap_every - 1);
         *sweep = s + 1;
     }
+    if (net) net_release(net);
     free(sc);
     free(lnk);
     return rc;
