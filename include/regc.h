@@ -333,6 +333,31 @@ int regc_mlp_train(regc_mlp *mlp, int64_t n_examples, int nmax, const uint16_t *
 int regc_mlp_timing(regc_mlp *mlp, double *ms, int64_t *steps);
 void regc_mlp_destroy(regc_mlp *mlp);
 
+/* Sampling with the learned proposal.  An insertion draws, with probability alpha
+ * ((B3 + 1/2) / 2^32 < alpha, B3 the last word of the trial's second Philox
+ * block), a voxel v from the network's categorical for the current occupancy by
+ * Gumbel-max -- argmax_v logit_v - ln(-ln u_v), u_v the open uniform of word v%4
+ * of Philox block (trial, sweep, walker, 16 + v/4) -- and a uniform point inside
+ * it (the trial's uniforms A2, A3, B0); otherwise a uniform point of V as in the
+ * plain method.  The proposal density
+ *   q(r|X) = alpha P(v(r)|occ(X)) / V_vox + (1 - alpha) / V
+ * replaces 1/V in the insertion acceptance (Eq. (3) divided by V q) and in the
+ * removal acceptance (Eq. (2) multiplied by V q(r_i | X without i), the network
+ * evaluated on the occupancy left after the removal), the Metropolis-Hastings form
+ * that keeps Eq. (1) the stationary law for any network.  Displacements are
+ * unchanged.  The call copies the network's current parameters (bfloat16) into the
+ * context: call it again after training to refresh.  mlp = NULL or alpha = 0
+ * restores the plain method.  Single-class contexts only (EUNSUPPORTED for a
+ * batch); alpha outside [0, 1] is EINVAL.  With a proposal set, every walker runs
+ * in a workgroup of its own (256 threads); the walkers_per_block, split, cull and
+ * slab-binning options then have no effect. */
+int regc_set_proposal(regc_ctx *ctx, regc_mlp *mlp, double alpha);
+
+/* Counters of the learned proposal accumulated by the context: [0] network
+ * passes, [1] insertions served by the cached pass of the unchanged occupancy,
+ * [2] insertions drawn from the network, [3] of them accepted. */
+int regc_get_proposal_stats(regc_ctx *ctx, int64_t counts[4]);
+
 /* ---- errors ---------------------------------------------------------------- */
 const char *regc_strerror(int code);
 const char *regc_last_error(void);

@@ -1,8 +1,8 @@
 """Builds libregc_hip.so in-tree with hipcc for gfx950.
 
 Every translation unit is compiled with -Xclang -target-feature -Xclang -packed-fp32-ops
-(no packed FP32 instructions).  The sweep kernel is compiled twice: FP64 with
--ffp-contract=off (parity mode) and FP32.  The exchange kernel is compiled without
+(no packed FP32 instructions).  The sweep kernels (plain and learned proposal) are
+compiled twice: FP64 with -ffp-contract=off (parity mode) and FP32.  The exchange kernel is compiled without
 FP contraction so its FP64 acceptance matches a plain sequential evaluation.
 """
 from __future__ import annotations
@@ -26,6 +26,8 @@ COMMON = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Xclang", "-t
 UNITS = [
     ("sweep.hip", "sweep_f64.o", ["-DREGC_FP64", "-ffp-contract=off"]),
     ("sweep.hip", "sweep_f32.o", ["-DREGC_FP32"]),
+    ("learned.hip", "learned_f64.o", ["-DREGC_FP64", "-ffp-contract=off"]),
+    ("learned.hip", "learned_f32.o", ["-DREGC_FP32"]),
     ("swap.hip", "swap.o", ["-ffp-contract=off"]),
     ("mbar.hip", "mbar.o", []),
     ("mlp.hip", "mlp.o", []),

@@ -71,6 +71,13 @@ struct regc_ctx {
     bool timing = false;
     std::vector<TimingPair> ev_sweep, ev_swap;
 
+    // learned insertion proposal (alpha > 0: the learned kernel runs the sweeps)
+    double alpha = 0.0;
+    DevBuf<uint16_t> net_w;                 // w1 | w2p | w3p | w4p (bfloat16)
+    DevBuf<float> net_b;                    // b1 | b2 | b3 | b4
+    DevBuf<unsigned long long> net_ev_d;    // proposal counters [4]
+    size_t learn_smem = 0;
+
     // graph replay of whole exchange intervals
     DevBuf<int64_t> clock_d;
     hipStream_t cap_stream = nullptr;
@@ -531,10 +538,29 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     int rc;
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
-    if (c->opts.precision == REGC_FP64)
+    if (c->alpha > 0.0) {
+        LearnArgs l{};
+        const uint16_t *w = c->net_w.p;
+        const float *bb = c->net_b.p;
+        l.net.w1 = w;
+        l.net.w2 = w + (size_t)kNetNV * kNetH;
+        l.net.w3 = l.net.w2 + (size_t)kNetH * kNetH;
+        l.net.w4 = l.net.w3 + (size_t)kNetH * kNetH;
+        l.net.b1 = bb;
+        l.net.b2 = bb + kNetH;
+        l.net.b3 = bb + 2 * kNetH;
+        l.net.b4 = bb + 3 * kNetH;
+        l.alpha = c->alpha;
+        l.evals = c->net_ev_d.p;
+        if (c->opts.precision == REGC_FP64)
+            REGC_HIP(launch_learned_f64(a, l, c->learn_smem, stream));
+        else
+            REGC_HIP(launch_learned_f32(a, l, c->learn_smem, stream));
+    } else if (c->opts.precision == REGC_FP64) {
         REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
-    else
+    } else {
         REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
+    }
     if (ev && (rc = record_event(c, c->ev_sweep, false))) return rc;
     return REGC_OK;
 }
@@ -659,6 +685,55 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
     }
     if ((rc = eager(left))) return rc;
     if (o.sample_every > 0) c->n_rec = c->sweep / o.sample_every - c->rec_base;
+    return REGC_OK;
+}
+
+extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_CHECK(alpha >= 0.0 && alpha <= 1.0, REGC_EINVAL, "mixture weight %g outside [0, 1]", alpha);
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    invalidate_graph(c);
+    if (!mlp || alpha == 0.0) {
+        c->alpha = 0.0;
+        return REGC_OK;
+    }
+    REGC_CHECK(c->cls.size() == 1, REGC_EUNSUPPORTED, "the learned proposal needs a single-class context");
+    int dev = 0, lds_max = 0;
+    REGC_HIP(hipGetDevice(&dev));
+    REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int real = c->opts.precision == REGC_FP64 ? 8 : 4;
+    const size_t smem = learn_lds(c->max_slab_len, c->max_stencil, c->nmax_all, real).total;
+    REGC_CHECK(smem <= (size_t)lds_max, REGC_EUNSUPPORTED, "a walker needs %zu bytes of LDS, the device allows %d",
+               smem, lds_max);
+    int rc;
+    const size_t nw = 2 * (size_t)kNetNV * kNetH + 2 * (size_t)kNetH * kNetH, nb = 3 * kNetH + kNetNV;
+    if (!c->net_w.p && (rc = c->net_w.alloc(nw))) return rc;
+    if (!c->net_b.p && (rc = c->net_b.alloc(nb))) return rc;
+    if (!c->net_ev_d.p) {
+        if ((rc = c->net_ev_d.alloc(4))) return rc;
+        REGC_HIP(hipMemset(c->net_ev_d.p, 0, 4 * sizeof(unsigned long long)));
+    }
+    uint16_t *w = c->net_w.p;
+    float *b = c->net_b.p;
+    if ((rc = mlp_export_sampler(mlp, c->opts.precision == REGC_FP64, w, w + (size_t)kNetNV * kNetH,
+                                 w + (size_t)kNetNV * kNetH + kNetH * kNetH,
+                                 w + (size_t)kNetNV * kNetH + 2 * kNetH * kNetH, b, b + kNetH, b + 2 * kNetH,
+                                 b + 3 * kNetH, c->stream)))
+        return rc;
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    c->learn_smem = smem;
+    c->alpha = alpha;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_proposal_stats(regc_ctx *c, int64_t counts[4])
+{
+    REGC_CHECK(c && counts, REGC_EINVAL, "null argument");
+    unsigned long long h[4] = {0, 0, 0, 0};
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (c->net_ev_d.p) REGC_HIP(hipMemcpy(h, c->net_ev_d.p, sizeof h, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 4; ++k) counts[k] = (int64_t)h[k];
     return REGC_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "host_util.h"
+#include "mlp_dev.h"
 #include "philox_dev.h"
 #include "regc_dev.h"
 
@@ -32,28 +33,6 @@ constexpr int NV = 4096, H = 128;
 constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + (size_t)NV * H, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + (size_t)H * H,
                  OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + (size_t)H * H, OFF_W4 = OFF_B3 + H,
                  OFF_B4 = OFF_W4 + (size_t)NV * H, NPARAM = OFF_B4 + NV;
-
-typedef uint16_t bf16;
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ bf16 f2bf(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);   // NaN stays NaN
-    return (bf16)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
-__device__ __forceinline__ float bf2f(bf16 b) { return __uint_as_float((uint32_t)b << 16); }
-
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-
-__device__ __forceinline__ float gelu_grad(float x)
-{
-    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-    const float pdf = expf(-0.5f * x * x) * 0.39894228040143268f;
-    return cdf + x * pdf;
-}
 
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2 };
 
@@ -240,6 +219,26 @@ __global__ void make_batch(int B, int nmax, int64_t n_examples, const uint16_t *
         excl[b] = i;
         target[b] = i >= 0 ? set_vox[pick * nmax + i] : 0;
     }
+}
+
+// MFMA B-operand tiles of a [n_out][128] weight matrix (the layout of NetDev):
+// P[((tile*4 + kp)*64 + lane)*8 + j] = W[16 tile + lane%16][32 kp + 16 (j/4) + 4 (lane/16) + j%4]
+__global__ void pack_b_tiles(int n_out, const bf16 *W, bf16 *P)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n_out * H) return;
+    const int j = (int)(idx % 8), lane = (int)((idx / 8) % 64), kp = (int)((idx / 512) % 4);
+    const int tile = (int)(idx / 2048);
+    P[idx] = W[(size_t)(16 * tile + lane % 16) * H + 32 * kp + 16 * (j / 4) + 4 * (lane / 16) + j % 4];
+}
+
+// k-major copy of a [n_out][128] weight matrix: T[k][o] = W[o][k]
+__global__ void transpose_kmajor(int n_out, const bf16 *W, bf16 *T)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n_out * H) return;
+    const int k = (int)(idx / n_out), o = (int)(idx % n_out);
+    T[idx] = W[(size_t)o * H + k];
 }
 
 }  // namespace mlpk
@@ -516,6 +515,32 @@ extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const u
     if (mean_loss) *mean_loss = loss_acc;
     return REGC_OK;
 }
+
+namespace regc {
+int mlp_export_sampler(regc_mlp *h, bool kmajor, uint16_t *w1, uint16_t *w2, uint16_t *w3, uint16_t *w4, float *b1,
+                       float *b2, float *b3, float *b4, hipStream_t s)
+{
+    REGC_CHECK(h, REGC_EINVAL, "null network");
+    REGC_HIP(hipStreamSynchronize(h->stream));
+    REGC_HIP(hipMemcpyAsync(w1, h->p16.p + OFF_W1, sizeof(bf16) * (size_t)NV * H, hipMemcpyDeviceToDevice, s));
+    const bf16 *src[3] = {h->p16.p + OFF_W2, h->p16.p + OFF_W3, h->p16.p + OFF_W4};
+    uint16_t *dst[3] = {w2, w3, w4};
+    const int n_out[3] = {H, H, NV};
+    for (int q = 0; q < 3; ++q) {
+        const unsigned blocks = (unsigned)((size_t)n_out[q] * H / 256);
+        if (kmajor)
+            hipLaunchKernelGGL(transpose_kmajor, dim3(blocks), dim3(256), 0, s, n_out[q], src[q], dst[q]);
+        else
+            hipLaunchKernelGGL(pack_b_tiles, dim3(blocks), dim3(256), 0, s, n_out[q], src[q], dst[q]);
+        REGC_HIP(hipGetLastError());
+    }
+    REGC_HIP(hipMemcpyAsync(b1, h->p.p + OFF_B1, sizeof(float) * H, hipMemcpyDeviceToDevice, s));
+    REGC_HIP(hipMemcpyAsync(b2, h->p.p + OFF_B2, sizeof(float) * H, hipMemcpyDeviceToDevice, s));
+    REGC_HIP(hipMemcpyAsync(b3, h->p.p + OFF_B3, sizeof(float) * H, hipMemcpyDeviceToDevice, s));
+    REGC_HIP(hipMemcpyAsync(b4, h->p.p + OFF_B4, sizeof(float) * NV, hipMemcpyDeviceToDevice, s));
+    return REGC_OK;
+}
+}  // namespace regc
 
 extern "C" int regc_mlp_timing(regc_mlp *h, double *ms, int64_t *steps)
 {

@@ -32,7 +32,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
-           "regc_strerror", "regc_last_error"]
+           "regc_set_proposal", "regc_get_proposal_stats", "regc_strerror", "regc_last_error"]
 
 
 class RegcError(RuntimeError):
@@ -135,6 +135,8 @@ def lib():
         L.regc_mlp_timing.argtypes = [vp, _dp, _i64p]
         L.regc_mlp_destroy.argtypes = [vp]
         L.regc_mlp_destroy.restype = None
+        L.regc_set_proposal.argtypes = [vp, vp, C.c_double]
+        L.regc_get_proposal_stats.argtypes = [vp, _i64p]
         L.regc_strerror.argtypes = [C.c_int]
         L.regc_strerror.restype = C.c_char_p
         L.regc_last_error.restype = C.c_char_p
@@ -331,6 +333,17 @@ class Regc:
     def restore(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().regc_restore(self.h, buf, len(blob)))
+
+    def set_proposal(self, mlp, alpha: float):
+        """Learned insertion proposal from the network's current parameters with
+        mixture weight alpha (mlp None or alpha 0: the plain method)."""
+        _check(lib().regc_set_proposal(self.h, mlp.h if mlp is not None else None, float(alpha)))
+
+    def proposal_stats(self):
+        """{'passes', 'cached', 'drawn', 'drawn_accepted'} of the learned proposal."""
+        out = np.zeros(4, np.int64)
+        _check(lib().regc_get_proposal_stats(self.h, _p(out, _i64p)))
+        return dict(zip(("passes", "cached", "drawn", "drawn_accepted"), (int(x) for x in out)))
 
 
 class Mbar:
