@@ -15,7 +15,9 @@ production particle counts.  Metric: GC trial moves per second over all replicas
 Also reported: the sweep kernel against the FP32 vector roofline (candidate pair
 terms x 25 flops / kernel time from HIP events on the context stream), the CPU
 oracle's trial rate on the host cores on a bounded sample of the same workload,
-and the reweighting of 1024 states x ~10^6 samples.
+and the reweighting of 1024 states x ~10^6 samples.  A last leg measures the
+wall time to a target accuracy of <N>(T, mu) with and without the learned insertion
+proposal on the 64-replica system (--learned-seconds 0 skips it).
 """
 from __future__ import annotations
 
@@ -50,6 +52,10 @@ def main():
                          "slab classes batched in one launch")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with the autotuner first")
     ap.add_argument("--graph", type=int, default=-1, help="graph_intervals (-1: 0 for c2, 10 for c3)")
+    ap.add_argument("--learned-seconds", type=float, default=120.0,
+                    help="GPU-time cap of the learned-proposal run of the time-to-accuracy leg (0: skip the leg)")
+    ap.add_argument("--learned-tau", type=float, default=0.5, help="standard-error target (particles) of that leg")
+    ap.add_argument("--learned-alpha", type=float, default=0.9, help="mixture weight of the network branch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
@@ -124,7 +130,7 @@ def main():
     sw = g.stats()
     swap_rate = float(sw["swap_acc"].sum() / max(sw["swap_att"].sum(), 1))
     result = {
-        "metric": "GC trial moves/s (all replicas, 1 GPU)",
+        "metric": "GC trial moves/s (all replicas, 1 GPU); wall-s to <N>(T,mu) at 3 SE, learned vs plain",
         "value": value,
         "unit": "trial moves/s",
         "n_gpus": 1,
@@ -206,7 +212,73 @@ def main():
                           "target_grid": "64 x 64", "phases_found": int(len(set(tr["phase"].tolist())))}
         mb.close()
         gm.close()
+    if args.learned_seconds > 0:
+        result["learned"] = learned_leg(args)
     print(json.dumps(result))
+
+
+def learned_leg(args):
+    """Time to accuracy of <N>(T, mu) with and without the learned insertion
+    proposal on the 64-replica system (4x4x2 slab, box 6x6x8, N <= 40): training
+    data from plain runs (seeds 1, 2), training on the GPU, a long FP64 reference
+    run (seed 4), then both forms from the same equilibrated state (seed 3)."""
+    import numpy as np
+    import torch
+
+    from paper_1908_11118_amd import proposal as P
+    from paper_1908_11118_amd import regc
+    from paper_1908_11118_amd import workloads as W
+
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    w = W.config1()
+    out = {"workload": "64 replicas (8 T x 8 mu), 4x4x2 = 32-atom slab, box 6x6x8, N <= 40, K = 41",
+           "alpha": args.learned_alpha, "tau": args.learned_tau, "frac_within_3se": 0.98, "max_chi2": 1.3,
+           "precision": "FP32 pair terms; network bf16 on MFMA"}
+    t = time.perf_counter()
+    vox, n = P.capture_dataset(w, seeds=(1, 2), burnin=2000, sweeps=10000)
+    torch.cuda.synchronize()
+    out["training_examples"] = int(vox.shape[0])
+    out["capture_s"] = time.perf_counter() - t
+    say(f"[learned] captured {vox.shape[0]} configurations in {out['capture_s']:.1f} s")
+    t = time.perf_counter()
+    net = P.train(vox, n, steps=20000, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    out["train_s"] = time.perf_counter() - t
+    out["train_steps"] = 20000
+    # cross-entropy on 4096 random training examples (in-sample), against the uniform proposal's ln 4096
+    rng = np.random.default_rng(5)
+    vh = vox[:200000].cpu().numpy().view(np.uint16)
+    nh = n[:200000].cpu().numpy()
+    sel = rng.choice(np.nonzero(nh > 0)[0], 4096, replace=False)
+    excl = rng.integers(0, nh[sel]).astype(np.int32)
+    target = vh[sel, excl].astype(np.int32)
+    loss, _ = net.loss_grads(vh[sel], nh[sel], excl, target)
+    out["loss_after"] = loss
+    out["loss_uniform"] = float(np.log(4096.0))
+    del vox, n
+    say(f"[learned] trained in {out['train_s']:.1f} s, loss {loss:.3f} (uniform {np.log(4096.0):.3f})")
+    t = time.perf_counter()
+    ref_m, ref_se = P.reference(w, sweeps=100000)
+    out["reference"] = {"sweeps": 100000, "precision": "FP64", "seconds": time.perf_counter() - t,
+                        "max_se": float(ref_se.max())}
+    blob = P.equilibrated_state(w)
+    plain = P.time_to_accuracy(w, blob, ref_m, ref_se, tau=args.learned_tau, max_seconds=args.learned_seconds,
+                               log=say)
+    say(f"[learned] plain: reached={plain['reached']} t={plain['t_acc_s']:.2f} s sweeps={plain['sweeps']}")
+    learned = P.time_to_accuracy(w, blob, ref_m, ref_se, net=net, alpha=args.learned_alpha, tau=args.learned_tau,
+                                 max_seconds=args.learned_seconds, log=say)
+    say(f"[learned] learned: reached={learned['reached']} t={learned['t_acc_s']:.2f} s sweeps={learned['sweeps']}")
+    net.close()
+    keep = ("reached", "t_acc_s", "sweeps", "max_se", "frac_within", "chi2", "ins_acc", "ms_per_sweep")
+    out["plain"] = {k: plain[k] for k in keep}
+    out["learned"] = {k: learned[k] for k in keep}
+    out["learned"]["proposal"] = learned.get("proposal")
+    out["efficiency_ratio_learned_over_plain"] = P.efficiency_ratio(plain, learned)
+    if plain["reached"] and learned["reached"]:
+        out["speedup_t_acc"] = plain["t_acc_s"] / learned["t_acc_s"]
+    elif plain["reached"]:
+        out["speedup_t_acc"] = f"< {plain['t_acc_s'] / learned['t_acc_s']:.4f} (learned not reached in the cap)"
+    return out
 
 
 if __name__ == "__main__":

@@ -325,8 +325,10 @@ int regc_mlp_loss_grads(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, con
                         const int32_t *excl, const int32_t *target, double *loss, float *grads);
 /* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on batches drawn from a
  * device data set of n_examples configurations (vox_dev [n_examples][nmax],
- * n_dev [n_examples], every n >= 1): example and left-out particle from Philox
- * keyed by seed.  mean_loss (may be NULL) receives the last batch's loss. */
+ * n_dev [n_examples]): example and left-out particle from Philox keyed by seed;
+ * an empty configuration is passed over for the next non-empty one (at most 256
+ * further; a batch slot left empty adds nothing to the loss or its gradient).
+ * mean_loss (may be NULL) receives the last batch's loss (mean over the batch). */
 int regc_mlp_train(regc_mlp *mlp, int64_t n_examples, int nmax, const uint16_t *vox_dev, const int32_t *n_dev,
                    int64_t steps, int batch, double lr, uint64_t seed, double *mean_loss);
 /* Accumulated training time in ms and steps. */
@@ -352,6 +354,13 @@ void regc_mlp_destroy(regc_mlp *mlp);
  * in a workgroup of its own (256 threads); the walkers_per_block, split, cull and
  * slab-binning options then have no effect. */
 int regc_set_proposal(regc_ctx *ctx, regc_mlp *mlp, double alpha);
+
+/* Training data for the proposal network: writes, asynchronously on the
+ * context's stream, the voxel of every particle of every walker into the device
+ * array vox_dev [W][n_max] (uint16, rows padded with 0 beyond N; n_max the
+ * largest over classes) and N into n_dev [W].  Both are device pointers the
+ * caller owns (e.g. slices of a data set appended to after each sweep). */
+int regc_capture_voxels(regc_ctx *ctx, uint16_t *vox_dev, int32_t *n_dev);
 
 /* Counters of the learned proposal accumulated by the context: [0] network
  * passes, [1] insertions served by the cached pass of the unchanged occupancy,

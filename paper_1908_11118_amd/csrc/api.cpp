@@ -727,6 +727,14 @@ extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
     return REGC_OK;
 }
 
+extern "C" int regc_capture_voxels(regc_ctx *c, uint16_t *vox_dev, int32_t *n_dev)
+{
+    REGC_CHECK(c && vox_dev && n_dev, REGC_EINVAL, "null argument");
+    REGC_HIP(launch_capture_voxels(c->W, c->nmax_all, c->cls_d.p, c->walker_class_d.p, c->n_d.p, c->xyz_d.p,
+                                   c->nmax_all, vox_dev, n_dev, c->stream));
+    return REGC_OK;
+}
+
 extern "C" int regc_get_proposal_stats(regc_ctx *c, int64_t counts[4])
 {
     REGC_CHECK(c && counts, REGC_EINVAL, "null argument");

@@ -211,6 +211,7 @@ __device__ __forceinline__ void hidden_seq(const uint16_t *wt, const float *bias
 }
 
 struct NetLds {
+    const float *b1, *b2, *b3, *b4;   // biases (LDS copies)
     const uint32_t *occ;
     uint32_t *list;
     float *part;
@@ -263,12 +264,21 @@ __device__ double net_forward(const NetDev &net, const NetLds &S, int ex, int ti
     __syncthreads();
 
     // layer 1: b1 + sum over the list of count x W1 row
+    // (entries are taken 8 at a time, their weight rows loaded before they are summed)
     if (kExact) {
         if (tid < kNetH) {
-            float s = net.b1[tid];
-            for (int j = 0; j < m; ++j) {
-                const uint32_t e = S.list[j];
-                s += (float)(e >> 16) * bf2f(net.w1[(size_t)(e & 0xFFFFu) * kNetH + tid]);
+            float s = S.b1[tid];
+            for (int j0 = 0; j0 < m; j0 += 8) {
+                uint32_t e[8];
+                bf16 wv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    e[u] = j0 + u < m ? S.list[j0 + u] : 0u;
+                    wv[u] = net.w1[(size_t)(e[u] & 0xFFFFu) * kNetH + tid];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + u < m) s += (float)(e[u] >> 16) * bf2f(wv[u]);
             }
             S.h1[tid] = f2bf(act(s));
         }
@@ -276,51 +286,67 @@ __device__ double net_forward(const NetDev &net, const NetLds &S, int ex, int ti
         // wave w takes entries w, w+4, ...; the four partial sums meet in LDS
         float a0 = 0.f, a1 = 0.f;
         const uint32_t *w1 = reinterpret_cast<const uint32_t *>(net.w1);
-        for (int j = wave; j < m; j += kLearnWaves) {
-            const uint32_t e = S.list[j];
-            const float k = (float)(e >> 16);
-            const uint32_t wv = w1[(size_t)(e & 0xFFFFu) * (kNetH / 2) + lane];
-            a0 += k * lo_bf(wv);
-            a1 += k * hi_bf(wv);
+        for (int j0 = wave; j0 < m; j0 += 8 * kLearnWaves) {
+            uint32_t e[8], wv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * kLearnWaves;
+                e[u] = j < m ? S.list[j] : 0u;
+                wv[u] = w1[(size_t)(e[u] & 0xFFFFu) * (kNetH / 2) + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float k = (float)(e[u] >> 16);     // 0 for the padding entries
+                a0 += k * lo_bf(wv[u]);
+                a1 += k * hi_bf(wv[u]);
+            }
         }
         S.part[wave * kNetH + 2 * lane] = a0;
         S.part[wave * kNetH + 2 * lane + 1] = a1;
         __syncthreads();
         if (tid < kNetH) {
-            float s = net.b1[tid];
+            float s = S.b1[tid];
 #pragma unroll
             for (int k = 0; k < kLearnWaves; ++k) s += S.part[k * kNetH + tid];
             S.h1[tid] = f2bf(act(s));
         }
     }
     __syncthreads();
-    if (kExact) hidden_seq(net.w2, net.b2, S.h1, S.h2, tid);
-    else hidden_mfma(net.w2, net.b2, S.h1, S.h2, wave, lane);
+    if (kExact) hidden_seq(net.w2, S.b2, S.h1, S.h2, tid);
+    else hidden_mfma(net.w2, S.b2, S.h1, S.h2, wave, lane);
     __syncthreads();
-    if (kExact) hidden_seq(net.w3, net.b3, S.h2, S.h3, tid);
-    else hidden_mfma(net.w3, net.b3, S.h2, S.h3, wave, lane);
+    if (kExact) hidden_seq(net.w3, S.b3, S.h2, S.h3, tid);
+    else hidden_mfma(net.w3, S.b3, S.h2, S.h3, wave, lane);
     __syncthreads();
 
     if (kExact) {
-        // output layer, thread t: voxels 16t .. 16t+15, sequential sums in ascending k
+        // output layer, thread t: voxels 16t .. 16t+15, sequential sums in ascending k;
+        // the weights of 8 consecutive k are loaded before they are used
         float acc[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-        const uint4 *w4 = reinterpret_cast<const uint4 *>(net.w4);
-#pragma unroll 2
-        for (int k = 0; k < kNetH; ++k) {
-            const float hk = bf2f(S.h3[k]);
-            const uint4 q0 = w4[(size_t)k * (kNetNV / 8) + 2 * tid];
-            const uint4 q1 = w4[(size_t)k * (kNetNV / 8) + 2 * tid + 1];
-            const uint32_t wv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const uint4 *w4 = reinterpret_cast<const uint4 *>(net.w4) + 2 * tid;
+        for (int k0 = 0; k0 < kNetH; k0 += 8) {
+            uint4 q[8][2];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                acc[2 * j] += lo_bf(wv[j]) * hk;
-                acc[2 * j + 1] += hi_bf(wv[j]) * hk;
+            for (int u = 0; u < 8; ++u) {
+                q[u][0] = w4[(size_t)(k0 + u) * (kNetNV / 8)];
+                q[u][1] = w4[(size_t)(k0 + u) * (kNetNV / 8) + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float hk = bf2f(S.h3[k0 + u]);
+                const uint32_t wv[8] = {q[u][0].x, q[u][0].y, q[u][0].z, q[u][0].w,
+                                        q[u][1].x, q[u][1].y, q[u][1].z, q[u][1].w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    acc[2 * j] += lo_bf(wv[j]) * hk;
+                    acc[2 * j + 1] += hi_bf(wv[j]) * hk;
+                }
             }
         }
 #pragma unroll
-        for (int j = 0; j < 16; ++j) S.logit[16 * tid + j] = acc[j] + net.b4[16 * tid + j];
+        for (int j = 0; j < 16; ++j) S.logit[16 * tid + j] = acc[j] + S.b4[16 * tid + j];
         __syncthreads();
         double mx = -INFINITY;
 #pragma unroll
@@ -335,31 +361,41 @@ __device__ double net_forward(const NetDev &net, const NetLds &S, int ex, int ti
         sum = block_sum(sum, S.redd);
         return mx + log(sum);
     } else {
-        // output layer on MFMA: wave w takes tiles 64w .. 64w+63 (16 voxels each)
+        // output layer on MFMA: wave w takes tiles 64w .. 64w+63 (16 voxels each), in
+        // stages of 4 tiles; the next stage's weights are in flight while a stage computes
         bf16x4 a[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) a[kk] = afrag(S.h3, kk, lane);
-        const uint4 *wp = reinterpret_cast<const uint4 *>(net.w4);
-        for (int t = 0; t < 64; t += 2) {
-            const int t0 = 64 * wave + t;
-            uint4 bq[2][4];
+        constexpr int TS = 4;
+        const uint4 *wp = reinterpret_cast<const uint4 *>(net.w4) + (size_t)(64 * wave) * 4 * kWave + lane;
+        auto load = [&](uint4 (&b)[TS][4], int t) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < TS; ++u)
 #pragma unroll
-                for (int kp = 0; kp < 4; ++kp) bq[u][kp] = wp[((size_t)(t0 + u) * 4 + kp) * kWave + lane];
+                for (int kp = 0; kp < 4; ++kp) b[u][kp] = wp[((size_t)(t + u) * 4 + kp) * kWave];
+        };
+        auto compute = [&](const uint4 (&b)[TS][4], int t) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < TS; ++u) {
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kp = 0; kp < 4; ++kp) {
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2 * kp], lo4(bq[u][kp]), acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2 * kp + 1], hi4(bq[u][kp]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2 * kp], lo4(b[u][kp]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2 * kp + 1], hi4(b[u][kp]), acc, 0, 0, 0);
                 }
                 if (lane < 16) {
-                    const int v = 16 * (t0 + u) + lane;
-                    S.logit[v] = acc[0] + net.b4[v];
+                    const int v = 16 * (64 * wave + t + u) + lane;
+                    S.logit[v] = acc[0] + S.b4[v];
                 }
             }
+        };
+        uint4 bA[TS][4], bB[TS][4];
+        load(bA, 0);
+        for (int t = 0; t < 64; t += 2 * TS) {
+            load(bB, t + TS);
+            compute(bA, t);
+            if (t + 2 * TS < 64) load(bA, t + 2 * TS);
+            compute(bB, t + TS);
         }
         __syncthreads();
         float mx = -INFINITY;
@@ -445,6 +481,16 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     S.h2 = S.h1 + kNetH;
     S.h3 = S.h2 + kNetH;
     S.logit = reinterpret_cast<float *>(smem + L.logit);
+    {
+        float *bias = reinterpret_cast<float *>(smem + L.bias);
+        for (int k = tid; k < kNetNV; k += kLT) bias[k] = l.net.b4[k];
+        for (int k = tid; k < 3 * kNetH; k += kLT)
+            bias[kNetNV + k] = k < kNetH ? l.net.b1[k] : (k < 2 * kNetH ? l.net.b2[k - kNetH] : l.net.b3[k - 2 * kNetH]);
+        S.b4 = bias;
+        S.b1 = bias + kNetNV;
+        S.b2 = S.b1 + kNetH;
+        S.b3 = S.b2 + kNetH;
+    }
     S.redd = reinterpret_cast<double *>(smem + L.red);
     S.redf = reinterpret_cast<float *>(S.redd + kLearnWaves);
     S.redi = reinterpret_cast<int *>(S.redf + kLearnWaves);

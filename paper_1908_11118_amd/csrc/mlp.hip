@@ -138,9 +138,9 @@ __global__ void __launch_bounds__(256) softmax_xent(int B, const float *logits, 
     for (int v = threadIdx.x; v < NV; v += blockDim.x) s += expf(row[v] - mx);
     s = block_reduce(s, sh, false);
     const float lse = mx + logf(s);
-    const int t = target[b];
-    if (threadIdx.x == 0) loss[b] = lse - row[t];
-    const float inv_b = 1.0f / (float)B;
+    const int t = target[b];          // < 0: no example in this slot (zero loss and gradient)
+    if (threadIdx.x == 0) loss[b] = t >= 0 ? lse - row[t] : 0.0f;
+    const float inv_b = t >= 0 ? 1.0f / (float)B : 0.0f;
     for (int v = threadIdx.x; v < NV; v += blockDim.x) {
         const float g = (expf(row[v] - lse) - (v == t ? 1.0f : 0.0f)) * inv_b;
         d32[(size_t)b * NV + v] = g;
@@ -201,23 +201,29 @@ __global__ void to_bf16(size_t count, const float *x, bf16 *y)
 }
 
 // Training batch from a device data set of configurations (voxel lists): example
-// e = floor(U * n_examples) and left-out particle i = floor(U' * N_e) from
-// Philox counter (slot, step, 0xFFFFFFFF, 5) with the given key.
+// e = (53-bit word) mod n_examples and left-out particle i = floor(U' * N_e) from
+// Philox counter (slot, step, 0xFFFFFFFF, 5) with the given key.  Empty
+// configurations are passed over for the next ones (at most 256); a slot left
+// without particles gets target -1 (no loss, no gradient).
 __global__ void make_batch(int B, int nmax, int64_t n_examples, const uint16_t *set_vox, const int32_t *set_n,
                            int64_t step, uint32_t k0, uint32_t k1, uint16_t *vox, int32_t *n, int32_t *excl,
                            int32_t *target)
 {
     const int b = blockIdx.x;
     const uint4 r = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)step, 0xFFFFFFFFu, 5u), k0, k1);
-    const uint64_t pick = (uint64_t)(((((uint64_t)r.x << 32) | r.y) >> 11) % (uint64_t)n_examples);
-    const int nb = set_n[pick];
+    uint64_t pick = (uint64_t)(((((uint64_t)r.x << 32) | r.y) >> 11) % (uint64_t)n_examples);
+    int nb = set_n[pick];
+    for (int tries = 0; nb == 0 && tries < 256; ++tries) {
+        pick = pick + 1 == (uint64_t)n_examples ? 0 : pick + 1;
+        nb = set_n[pick];
+    }
     for (int j = threadIdx.x; j < nmax; j += blockDim.x)
         vox[(size_t)b * nmax + j] = j < nb ? set_vox[pick * nmax + j] : 0;
     if (threadIdx.x == 0) {
         const int i = nb > 0 ? (int)(((uint64_t)r.z * (uint64_t)nb) >> 32) : -1;
         n[b] = nb;
         excl[b] = i;
-        target[b] = i >= 0 ? set_vox[pick * nmax + i] : 0;
+        target[b] = i >= 0 ? (int32_t)set_vox[pick * nmax + i] : -1;
     }
 }
 
@@ -230,6 +236,30 @@ __global__ void pack_b_tiles(int n_out, const bf16 *W, bf16 *P)
     const int j = (int)(idx % 8), lane = (int)((idx / 8) % 64), kp = (int)((idx / 512) % 4);
     const int tile = (int)(idx / 2048);
     P[idx] = W[(size_t)(16 * tile + lane % 16) * H + 32 * kp + 16 * (j / 4) + 4 * (lane / 16) + j % 4];
+}
+
+// Voxel lists of walkers: vox[w][j] = voxel of particle j of walker w (the grid of
+// the learned proposal over the class's gas region), n_out[w] = N.
+__global__ void capture_voxels(int n_walkers, int stride, const ClassDev *cls, const int *walker_class,
+                               const int32_t *n, const double *xyz, int xyz_stride, uint16_t *vox, int32_t *n_out)
+{
+    const int w = blockIdx.x;
+    const ClassDev &C = cls[walker_class[w]];
+    const int nw = n[w];
+    const double gx = (double)kNetGrid / C.lx, gy = (double)kNetGrid / C.ly, gz = (double)kNetGrid / (C.zhi - C.zlo);
+    for (int j = threadIdx.x; j < stride; j += blockDim.x) {
+        int v = 0;
+        if (j < nw) {
+            const double *p = xyz + ((size_t)w * xyz_stride + j) * 3;
+            int ix = (int)floor(p[0] * gx), iy = (int)floor(p[1] * gy), iz = (int)floor((p[2] - C.zlo) * gz);
+            ix = ix < 0 ? 0 : (ix > kNetGrid - 1 ? kNetGrid - 1 : ix);
+            iy = iy < 0 ? 0 : (iy > kNetGrid - 1 ? kNetGrid - 1 : iy);
+            iz = iz < 0 ? 0 : (iz > kNetGrid - 1 ? kNetGrid - 1 : iz);
+            v = (iz * kNetGrid + iy) * kNetGrid + ix;
+        }
+        vox[(size_t)w * stride + j] = (uint16_t)v;
+    }
+    if (threadIdx.x == 0) n_out[w] = nw;
 }
 
 // k-major copy of a [n_out][128] weight matrix: T[k][o] = W[o][k]
@@ -517,6 +547,15 @@ extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const u
 }
 
 namespace regc {
+hipError_t launch_capture_voxels(int n_walkers, int stride, const ClassDev *cls, const int *walker_class,
+                                 const int32_t *n, const double *xyz, int xyz_stride, uint16_t *vox, int32_t *n_out,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(capture_voxels, dim3(n_walkers), dim3(64), 0, s, n_walkers, stride, cls, walker_class, n, xyz,
+                       xyz_stride, vox, n_out);
+    return hipGetLastError();
+}
+
 int mlp_export_sampler(regc_mlp *h, bool kmajor, uint16_t *w1, uint16_t *w2, uint16_t *w3, uint16_t *w4, float *b1,
                        float *b2, float *b3, float *b4, hipStream_t s)
 {

@@ -163,7 +163,7 @@ struct LearnArgs {
 // LDS carve of the learned-proposal kernel (one walker per workgroup of kLearnWaves waves).
 constexpr int kLearnWaves = 4;
 struct LearnLds {
-    size_t slab, stencil, lnk, xch, gas, vox, occ, list, part, hid, logit, red, total;
+    size_t slab, stencil, lnk, xch, gas, vox, occ, list, part, hid, logit, bias, red, total;
 };
 
 __host__ __device__ inline LearnLds learn_lds(int max_slab_len, int max_stencil, int gas_stride, int real_size)
@@ -182,6 +182,7 @@ __host__ __device__ inline LearnLds learn_lds(int max_slab_len, int max_stencil,
     L.part = off;    off = lds_round(off + (size_t)kLearnWaves * kNetH * 4);
     L.hid = off;     off = lds_round(off + (size_t)3 * kNetH * 2);
     L.logit = off;   off = lds_round(off + (size_t)kNetNV * 4);
+    L.bias = off;    off = lds_round(off + (size_t)(kNetNV + 3 * kNetH) * 4);   // b4 | b1 | b2 | b3
     L.red = off;     off = lds_round(off + (size_t)kLearnWaves * 16 + 32);
     L.total = off;
     return L;
@@ -208,6 +209,9 @@ namespace regc {
 // kmajor, else MFMA tiles) into caller-owned device buffers: w1 [4096*128],
 // w2/w3 [128*128], w4 [4096*128] bfloat16 and the four bias vectors, on stream s.
 // Returns a REGC_* code.
+hipError_t launch_capture_voxels(int n_walkers, int stride, const ClassDev *cls, const int *walker_class,
+                                 const int32_t *n, const double *xyz, int xyz_stride, uint16_t *vox, int32_t *n_out,
+                                 hipStream_t s);
 int mlp_export_sampler(regc_mlp *h, bool kmajor, uint16_t *w1, uint16_t *w2, uint16_t *w3, uint16_t *w4, float *b1,
                        float *b2, float *b3, float *b4, hipStream_t s);
 }  // namespace regc

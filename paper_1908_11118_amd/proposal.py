@@ -1,0 +1,194 @@
+"""The learned insertion proposal end to end: training data captured from plain
+REGC runs on the GPU, training of the proposal network on the GPU, and the
+comparison of wall time to a target accuracy of <N>(T, mu) with and without it.
+
+Training data (a reading: the network's inputs are the occupancy only): the
+sweep-end configurations of every walker of plain runs, as voxel lists on the
+device.  Training example: one configuration, one of its particles left out;
+input the occupancy of the others, target the left-out particle's voxel;
+cross-entropy loss, Adam.
+
+Time to accuracy (a reading of "wall-s to <N>(T, mu) at 3 SE"): both forms start
+from the same equilibrated state; after every chunk of sweeps the per-state mean
+N and its batch-means standard error are computed from all samples so far; the
+form has reached the target at the first chunk where (a) every state's standard
+error is at most tau particles, (b) at least `frac` of the states lie within
+3 sqrt(SE^2 + SE_ref^2) of the long reference run and (c) the mean squared
+z-score is at most 1.3.  Only the GPU sampling time (launches to synchronisation)
+is counted.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import regc
+from . import workloads as W
+
+
+def capture_dataset(workload, seeds=(1, 2), burnin: int = 2000, sweeps: int = 10000, every: int = 1,
+                    precision: int = regc.FP32PAIR):
+    """Device data set of sweep-end configurations of plain runs: returns torch
+    tensors vox [n_examples][n_max] (int16 storage of uint16 voxel indices) and
+    n [n_examples] (int32), n_examples = len(seeds) * (sweeps // every) * S."""
+    import torch
+    w0 = workload.replace(sample_every=0)
+    S, nmax = w0.n_states, w0.n_max
+    per = sweeps // every
+    vox = torch.zeros((len(seeds) * per * S, nmax), dtype=torch.int16, device="cuda")
+    n = torch.zeros((len(seeds) * per * S,), dtype=torch.int32, device="cuda")
+    off = 0
+    for seed in seeds:
+        with regc.Regc(w0.replace(seed=seed), precision=precision, sample_capacity=0) as g:
+            g.run(burnin)
+            for _ in range(per):
+                g.run(every)
+                g.capture_voxels(vox[off].data_ptr(), n[off].data_ptr())
+                off += S
+            g.sync()
+    return vox, n
+
+
+def train(vox, n, steps: int = 10000, batch: int = 256, lr: float = 1e-3, seed: int = 100, init_seed: int = 0,
+          report_every: int = 500, log=None) -> "regc.Mlp":
+    """Trains a fresh network on the device data set; returns it (regc.Mlp)."""
+    net = regc.Mlp(W.mlp_pack(W.mlp_init(init_seed)))
+    nmax = int(vox.shape[1])
+    done = 0
+    while done < steps:
+        k = min(report_every, steps - done)
+        loss = net.train(int(vox.shape[0]), nmax, vox.data_ptr(), n.data_ptr(), steps=k, batch=batch, lr=lr,
+                         seed=seed + done)
+        done += k
+        if log:
+            log(f"[train] step {done} loss {loss:.4f}")
+    return net
+
+
+def _per_state(state, nvals, S):
+    out = [[] for _ in range(S)]
+    order = np.argsort(state, kind="stable")
+    st = state[order]
+    nv = nvals[order]
+    bounds = np.searchsorted(st, np.arange(S + 1))
+    for s in range(S):
+        out[s] = nv[bounds[s]:bounds[s + 1]]
+    return out
+
+
+def mean_se(series, n_batches: int = 20):
+    """Mean and batch-means standard error of each state's series."""
+    m = np.zeros(len(series))
+    se = np.full(len(series), np.inf)
+    for s, x in enumerate(series):
+        x = np.asarray(x, dtype=np.float64)
+        if len(x) == 0:
+            m[s] = np.nan
+            continue
+        m[s] = x.mean()
+        b = len(x) // n_batches
+        if b >= 1:
+            bm = x[: b * n_batches].reshape(n_batches, b).mean(axis=1)
+            se[s] = bm.std(ddof=1) / math.sqrt(n_batches)
+    return m, se
+
+
+def reference(workload, sweeps: int = 100000, burnin: int = 2000, seed: int = 4, precision: int = regc.FP64,
+              chunk: int = 5000):
+    """Long plain run: per-state mean N and its standard error (records every sweep)."""
+    w = workload.replace(seed=seed, sample_every=1)
+    S = w.n_states
+    parts_s, parts_n = [], []
+    with regc.Regc(w, precision=precision, sample_capacity=chunk * S) as g:
+        g.run(burnin)
+        g.clear_samples()
+        done = 0
+        while done < sweeps:
+            k = min(chunk, sweeps - done)
+            g.run(k)
+            smp = g.samples()
+            parts_s.append(smp["state"])
+            parts_n.append(smp["n"])
+            g.clear_samples()
+            done += k
+    return mean_se(_per_state(np.concatenate(parts_s), np.concatenate(parts_n), S))
+
+
+def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["regc.Mlp"] = None,
+                     alpha: float = 0.0, precision: int = regc.FP32PAIR, chunk: int = 250,
+                     max_sweeps: int = 200000, max_seconds: float = 1e9, tau: float = 0.1, frac: float = 0.98,
+                     max_chi2: float = 1.3, seed: int = 3, log=None) -> Dict:
+    """Runs from the checkpoint `blob` (written by equilibrated_state with the same
+    seed) until the accuracy target is met or max_sweeps / max_seconds of GPU time
+    are spent; returns {"t_acc_s", "sweeps", "reached", "max_se", "frac_within",
+    "chi2", "ins_acc", ...}."""
+    w = workload.replace(seed=seed, sample_every=1)
+    S = w.n_states
+    parts_s, parts_n = [], []
+    t_gpu = 0.0
+    res = {"reached": False}
+    with regc.Regc(w, precision=precision, sample_capacity=chunk * S) as g:
+        g.restore(blob)
+        g.clear_samples()
+        if net is not None and alpha > 0:
+            g.set_proposal(net, alpha)
+        st0 = g.stats()["stats"].copy()
+        done = 0
+        while done < max_sweeps:
+            g.sync()
+            t0 = time.perf_counter()
+            g.run(chunk)
+            g.sync()
+            t_gpu += time.perf_counter() - t0
+            done += chunk
+            smp = g.samples()
+            g.clear_samples()
+            parts_s.append(smp["state"])
+            parts_n.append(smp["n"])
+            m, se = mean_se(_per_state(np.concatenate(parts_s), np.concatenate(parts_n), S))
+            z = (m - ref_mean) / np.sqrt(se ** 2 + ref_se ** 2)
+            within = float(np.mean(np.abs(z) <= 3.0))
+            chi2 = float(np.mean(z ** 2))
+            res = {"reached": bool(np.all(se <= tau) and within >= frac and chi2 <= max_chi2),
+                   "t_acc_s": t_gpu, "sweeps": done, "max_se": float(np.max(se)), "frac_within": within,
+                   "chi2": chi2}
+            if log and (done // chunk) % 40 == 0:
+                log(f"[t_acc] alpha={alpha} sweeps={done} t={t_gpu:.2f}s max_se={res['max_se']:.3f} "
+                    f"within={within:.3f} chi2={chi2:.2f}")
+            if res["reached"] or t_gpu >= max_seconds:
+                break
+        res["se_by_state"] = se.tolist()
+        res["mean_by_state"] = m.tolist()
+        st = g.stats()["stats"] - st0
+        res["ins_acc"] = float(st[:, 3].sum() / max(1, st[:, 2].sum()))
+        res["ins_acc_by_state"] = (st[:, 3] / np.maximum(st[:, 2], 1)).tolist()
+        res["ms_per_sweep"] = 1e3 * t_gpu / max(done, 1)
+        if net is not None and alpha > 0:
+            res["proposal"] = g.proposal_stats()
+    res["alpha"] = alpha
+    return res
+
+
+def equilibrated_state(workload, seed: int = 3, burnin: int = 2000, precision: int = regc.FP32PAIR) -> bytes:
+    """Checkpoint of a plain run after burn-in: the common starting point."""
+    with regc.Regc(workload.replace(seed=seed, sample_every=0), precision=precision, sample_capacity=0) as g:
+        g.run(burnin)
+        return g.checkpoint()
+
+
+def efficiency_ratio(plain: Dict, learned: Dict, min_se: float = 1e-3) -> Dict:
+    """Per-state statistical efficiency 1 / (SE^2 t) of the learned form over the
+    plain form, from the end of two time_to_accuracy runs (states whose standard
+    error is below min_se in either run -- frozen at 0 or at the cap -- are left
+    out).  Returns the median, minimum and maximum ratio and the state count."""
+    sp = np.asarray(plain["se_by_state"])
+    sl = np.asarray(learned["se_by_state"])
+    ok = (sp > min_se) & (sl > min_se) & np.isfinite(sp) & np.isfinite(sl)
+    if not ok.any():
+        return {"states": 0}
+    r = (sp[ok] ** 2 * plain["t_acc_s"]) / (sl[ok] ** 2 * learned["t_acc_s"])
+    return {"states": int(ok.sum()), "median": float(np.median(r)), "min": float(r.min()), "max": float(r.max()),
+            "geomean": float(np.exp(np.mean(np.log(r))))}

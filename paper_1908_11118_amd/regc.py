@@ -32,7 +32,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
-           "regc_set_proposal", "regc_get_proposal_stats", "regc_strerror", "regc_last_error"]
+           "regc_set_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_strerror", "regc_last_error"]
 
 
 class RegcError(RuntimeError):
@@ -137,6 +137,7 @@ def lib():
         L.regc_mlp_destroy.restype = None
         L.regc_set_proposal.argtypes = [vp, vp, C.c_double]
         L.regc_get_proposal_stats.argtypes = [vp, _i64p]
+        L.regc_capture_voxels.argtypes = [vp, vp, vp]
         L.regc_strerror.argtypes = [C.c_int]
         L.regc_strerror.restype = C.c_char_p
         L.regc_last_error.restype = C.c_char_p
@@ -338,6 +339,11 @@ class Regc:
         """Learned insertion proposal from the network's current parameters with
         mixture weight alpha (mlp None or alpha 0: the plain method)."""
         _check(lib().regc_set_proposal(self.h, mlp.h if mlp is not None else None, float(alpha)))
+
+    def capture_voxels(self, vox_dev_ptr: int, n_dev_ptr: int):
+        """Voxel lists [W][n_max] (uint16) and N [W] of the walkers into device memory
+        (asynchronous on the context's stream)."""
+        _check(lib().regc_capture_voxels(self.h, C.c_void_p(vox_dev_ptr), C.c_void_p(n_dev_ptr)))
 
     def proposal_stats(self):
         """{'passes', 'cached', 'drawn', 'drawn_accepted'} of the learned proposal."""
