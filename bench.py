@@ -37,6 +37,28 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_f32_1024rep_192slab_traffic.md")
+KERNEL_SOURCES = ["sweep.hip", "sweep_dev.h", "regc_dev.h", "philox_dev.h"]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("bytes_per_launch: ", "source_sha256: ")))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1908_11118_amd", "csrc", f), "rb").read())
+    if fields.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,7 +175,10 @@ def main():
                    "precision": "FP32 pair terms, FP64 energies/decisions/exchange" if prec == regc.FP32PAIR
                    else "FP64", "mean_N": float(wk["n"].mean()), "max_N": int(wk["n"].max())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic() if (args.workload == "c2" and prec == regc.FP32PAIR and not graph)
+                     else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "kernel": "sweep_kernel_f32" if prec == regc.FP32PAIR else "sweep_kernel_f64",
                      "kernel_ms_avg": ms_kernel, "launches": tm["n_sweep"],
                      "timed_unit": "graph replay (sweeps + exchange)" if graph else "sweep-kernel launch",
