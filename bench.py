@@ -78,6 +78,9 @@ def main():
                     help="GPU-time cap of the learned-proposal run of the time-to-accuracy leg (0: skip the leg)")
     ap.add_argument("--learned-tau", type=float, default=0.5, help="standard-error target (particles) of that leg")
     ap.add_argument("--learned-alpha", type=float, default=0.9, help="mixture weight of the network branch")
+    ap.add_argument("--learned-capture", type=int, default=10000, help="plain sweeps per seed captured for training")
+    ap.add_argument("--learned-train-steps", type=int, default=20000, help="Adam steps of the proposal network")
+    ap.add_argument("--learned-reference", type=int, default=100000, help="sweeps of the FP64 reference run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
@@ -260,20 +263,20 @@ def learned_leg(args):
            "alpha": args.learned_alpha, "tau": args.learned_tau, "frac_within_3se": 0.98, "max_chi2": 1.3,
            "precision": "FP32 pair terms; network bf16 on MFMA"}
     t = time.perf_counter()
-    vox, n = P.capture_dataset(w, seeds=(1, 2), burnin=2000, sweeps=10000)
+    vox, n = P.capture_dataset(w, seeds=(1, 2), burnin=2000, sweeps=args.learned_capture)
     torch.cuda.synchronize()
     out["training_examples"] = int(vox.shape[0])
     out["capture_s"] = time.perf_counter() - t
     say(f"[learned] captured {vox.shape[0]} configurations in {out['capture_s']:.1f} s")
     t = time.perf_counter()
-    net = P.train(vox, n, steps=20000, batch=256, lr=1e-3)
+    net = P.train(vox, n, steps=args.learned_train_steps, batch=256, lr=1e-3)
     torch.cuda.synchronize()
     out["train_s"] = time.perf_counter() - t
-    out["train_steps"] = 20000
+    out["train_steps"] = args.learned_train_steps
     # cross-entropy on 4096 random training examples (in-sample), against the uniform proposal's ln 4096
     rng = np.random.default_rng(5)
-    vh = vox[:200000].cpu().numpy().view(np.uint16)
-    nh = n[:200000].cpu().numpy()
+    vh = vox[:min(200000, int(vox.shape[0]))].cpu().numpy().view(np.uint16)
+    nh = n[:min(200000, int(n.shape[0]))].cpu().numpy()
     sel = rng.choice(np.nonzero(nh > 0)[0], 4096, replace=False)
     excl = rng.integers(0, nh[sel]).astype(np.int32)
     target = vh[sel, excl].astype(np.int32)
@@ -283,8 +286,8 @@ def learned_leg(args):
     del vox, n
     say(f"[learned] trained in {out['train_s']:.1f} s, loss {loss:.3f} (uniform {np.log(4096.0):.3f})")
     t = time.perf_counter()
-    ref_m, ref_se = P.reference(w, sweeps=100000)
-    out["reference"] = {"sweeps": 100000, "precision": "FP64", "seconds": time.perf_counter() - t,
+    ref_m, ref_se = P.reference(w, sweeps=args.learned_reference)
+    out["reference"] = {"sweeps": args.learned_reference, "precision": "FP64", "seconds": time.perf_counter() - t,
                         "max_se": float(ref_se.max())}
     blob = P.equilibrated_state(w)
     plain = P.time_to_accuracy(w, blob, ref_m, ref_se, tau=args.learned_tau, max_seconds=args.learned_seconds,

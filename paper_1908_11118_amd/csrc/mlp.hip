@@ -30,6 +30,7 @@ namespace regc {
 namespace mlpk {
 
 constexpr int NV = 4096, H = 128;
+constexpr int kSplitK = 16;   // K = 4096 products split 16 ways
 constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + (size_t)NV * H, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + (size_t)H * H,
                  OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + (size_t)H * H, OFF_W4 = OFF_B3 + H,
                  OFF_B4 = OFF_W4 + (size_t)NV * H, NPARAM = OFF_B4 + NV;
@@ -54,7 +55,10 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const bf16
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    // split K: block z takes k in [z K / Z, (z+1) K / Z) and writes the z-th of Z partial results
+    const int kspan = K / (int)gridDim.z, kbeg = (int)blockIdx.z * kspan;
+    C += (size_t)blockIdx.z * M * ldc;
+    for (int k0 = kbeg; k0 < kbeg + kspan; k0 += 16) {
         bf16x4 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -92,6 +96,16 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const bf16
                 C[(size_t)m * ldc + n] = v;
                 if (EPI == EPI_BIAS_GELU) act[(size_t)m * ldact + n] = f2bf(gelu(v));
             }
+}
+
+// out = sum over z of the Z partial results part[z] (count values each), z in order
+__global__ void sum_partials(int Z, size_t count, const float *part, float *out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = part[i];
+    for (int z = 1; z < Z; ++z) s += part[(size_t)z * count + i];
+    out[i] = s;
 }
 
 // Layer 1: a1[b] = b1 + sum of W1 columns of the occupied voxels (particles j != excl[b]).
@@ -157,14 +171,20 @@ __global__ void gelu_backward(int count, const float *dh, const float *a, float 
     da16[i] = f2bf(v);
 }
 
-// out[n] = sum_m X[m][n], one thread per column, rows in order (deterministic)
-__global__ void colsum(int M, int N, const float *X, float *out)
+// out[n] = sum_m X[m][n]: a block of 256 threads takes 64 columns; thread (g, c)
+// sums rows g, g+4, ... of column c in order, the four partial sums are added in
+// the order g = 0..3 (deterministic).
+__global__ void __launch_bounds__(256) colsum(int M, int N, const float *X, float *out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
+    __shared__ float part[4][64];
+    const int c = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int col = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[(size_t)m * N + c];
-    out[c] = s;
+    if (col < N)
+        for (int m = g; m < M; m += 4) s += X[(size_t)m * N + col];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && col < N) out[col] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
 }
 
 // dW1[voxel][k] += da1[b][k] for every occupied voxel of example b
@@ -282,7 +302,7 @@ struct regc_mlp {
     hipStream_t stream = nullptr;
     DevBuf<float> p, g, m, v;
     DevBuf<bf16> p16;
-    DevBuf<float> a1, a2, a3, logits, d32, dh, da, loss;
+    DevBuf<float> a1, a2, a3, logits, d32, dh, da, loss, ksplit;
     DevBuf<bf16> h1, h2, h3, d16, da16;
     DevBuf<uint16_t> bvox;
     DevBuf<int32_t> bn, bex, btgt;
@@ -302,7 +322,7 @@ static int mlp_workspace(regc_mlp *h, int B, int nmax)
         (rc = h->h1.alloc((size_t)Bm * H)) || (rc = h->h2.alloc((size_t)Bm * H)) || (rc = h->h3.alloc((size_t)Bm * H)) ||
         (rc = h->d16.alloc((size_t)Bm * NV)) || (rc = h->da16.alloc((size_t)Bm * H)) ||
         (rc = h->bvox.alloc((size_t)Bm * nm)) || (rc = h->bn.alloc(Bm)) || (rc = h->bex.alloc(Bm)) ||
-        (rc = h->btgt.alloc(Bm)))
+        (rc = h->btgt.alloc(Bm)) || (rc = h->ksplit.alloc((size_t)kSplitK * Bm * H)))
         return rc;
     h->max_batch = Bm;
     h->nmax = nm;
@@ -315,6 +335,19 @@ static hipError_t gemm(hipStream_t s, int M, int N, int K, const bf16 *A, int ld
 {
     hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI>), dim3(N / 64, M / 64), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
                        ldc, bias, act, ldact);
+    return hipGetLastError();
+}
+
+// C [M][N] (ldc = N) of a long reduction (K a multiple of 16 * kSplitK): kSplitK
+// partial products into the workspace, then their sum in a fixed order
+template <bool TA, bool TB>
+static hipError_t gemm_splitk(hipStream_t s, int M, int N, int K, const bf16 *A, int lda, const bf16 *B, int ldb,
+                              float *C, float *work)
+{
+    hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI_STORE>), dim3(N / 64, M / 64, kSplitK), dim3(256), 0, s, M, N, K, A, lda,
+                       B, ldb, work, N, nullptr, nullptr, 0);
+    const size_t count = (size_t)M * N;
+    hipLaunchKernelGGL(sum_partials, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, kSplitK, count, work, C);
     return hipGetLastError();
 }
 
@@ -344,27 +377,27 @@ static int mlp_backward_dev(regc_mlp *h, int B, int nmax)
     REGC_HIP(hipGetLastError());
     // output layer: dW4 = d^T h3, db4 = colsum d, dh3 = d W4
     REGC_HIP((gemm<true, false, EPI_STORE>(s, NV, H, B, h->d16.p, NV, h->h3.p, H, g + OFF_W4, H)));
-    hipLaunchKernelGGL(colsum, dim3((NV + 255) / 256), dim3(256), 0, s, B, NV, h->d32.p, g + OFF_B4);
+    hipLaunchKernelGGL(colsum, dim3(NV / 64), dim3(256), 0, s, B, NV, h->d32.p, g + OFF_B4);
     REGC_HIP(hipGetLastError());
-    REGC_HIP((gemm<false, false, EPI_STORE>(s, B, H, NV, h->d16.p, NV, W4, H, h->dh.p, H)));
+    REGC_HIP((gemm_splitk<false, false>(s, B, H, NV, h->d16.p, NV, W4, H, h->dh.p, h->ksplit.p)));
     // hidden layers 3 and 2
     const int cnt = B * H, gb = (cnt + 255) / 256;
     hipLaunchKernelGGL(gelu_backward, dim3(gb), dim3(256), 0, s, cnt, h->dh.p, h->a3.p, h->da.p, h->da16.p);
     REGC_HIP(hipGetLastError());
     REGC_HIP((gemm<true, false, EPI_STORE>(s, H, H, B, h->da16.p, H, h->h2.p, H, g + OFF_W3, H)));
-    hipLaunchKernelGGL(colsum, dim3(1), dim3(H), 0, s, B, H, h->da.p, g + OFF_B3);
+    hipLaunchKernelGGL(colsum, dim3(H / 64), dim3(256), 0, s, B, H, h->da.p, g + OFF_B3);
     REGC_HIP(hipGetLastError());
     REGC_HIP((gemm<false, false, EPI_STORE>(s, B, H, H, h->da16.p, H, W3, H, h->dh.p, H)));
     hipLaunchKernelGGL(gelu_backward, dim3(gb), dim3(256), 0, s, cnt, h->dh.p, h->a2.p, h->da.p, h->da16.p);
     REGC_HIP(hipGetLastError());
     REGC_HIP((gemm<true, false, EPI_STORE>(s, H, H, B, h->da16.p, H, h->h1.p, H, g + OFF_W2, H)));
-    hipLaunchKernelGGL(colsum, dim3(1), dim3(H), 0, s, B, H, h->da.p, g + OFF_B2);
+    hipLaunchKernelGGL(colsum, dim3(H / 64), dim3(256), 0, s, B, H, h->da.p, g + OFF_B2);
     REGC_HIP(hipGetLastError());
     REGC_HIP((gemm<false, false, EPI_STORE>(s, B, H, H, h->da16.p, H, W2, H, h->dh.p, H)));
     // layer 1: gather's gradient is a scatter into the occupied voxels' columns
     hipLaunchKernelGGL(gelu_backward, dim3(gb), dim3(256), 0, s, cnt, h->dh.p, h->a1.p, h->da.p, h->da16.p);
     REGC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(colsum, dim3(1), dim3(H), 0, s, B, H, h->da.p, g + OFF_B1);
+    hipLaunchKernelGGL(colsum, dim3(H / 64), dim3(256), 0, s, B, H, h->da.p, g + OFF_B1);
     REGC_HIP(hipGetLastError());
     REGC_HIP(hipMemsetAsync(g + OFF_W1, 0, sizeof(float) * (size_t)NV * H, s));
     hipLaunchKernelGGL(l1_backward, dim3(B), dim3(H), 0, s, nmax, h->bvox.p, h->bn.p, h->bex.p, h->da.p, g + OFF_W1);
