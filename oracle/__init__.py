@@ -64,7 +64,8 @@ class _Config(C.Structure):
                 ("seed", C.c_uint64), ("p_disp", C.c_double), ("p_ins", C.c_double),
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("walker_offset", C.c_int),
-                ("class_id", C.c_int), ("net", C.POINTER(C.c_float)), ("alpha", C.c_double)]
+                ("class_id", C.c_int), ("net", C.POINTER(C.c_float)), ("alpha", C.c_double),
+                ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int)]
 
 
 class _Walkers(C.Structure):
@@ -164,6 +165,8 @@ class Chain:
         self.S = len(w.t) * len(w.mu)
         self.n_max = int(w.n_max)
         self.K = w.trials_per_sweep if w.trials_per_sweep > 0 else self.n_max + 1
+        if getattr(w, "schedule", 0) == 1:
+            self.K = 1 + int(getattr(w, "mc_cycles", 10)) * self.n_max     # trials per REGC step, at most
         self.n_threads = n_threads or default_threads()
         self._slab = np.ascontiguousarray(w.slab, dtype=np.float64).reshape(-1, 3)
         sites = getattr(w, "sites", None)
@@ -192,6 +195,9 @@ class Chain:
             self._net = np.ascontiguousarray(net, dtype=np.float32).ravel()
             c.net = self._net.ctypes.data_as(C.POINTER(C.c_float))
         c.alpha = float(alpha)
+        c.schedule = int(getattr(w, "schedule", 0))
+        c.x0 = float(getattr(w, "x0", 0.99))
+        c.mc_cycles = int(getattr(w, "mc_cycles", 10))
         self.cfg = c
         S = self.S
         # initial state: empty walkers, walker w holds state w

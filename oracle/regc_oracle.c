@@ -127,6 +127,13 @@ typedef struct {
      * and the mixture weight alpha of the network branch (0: plain method) */
     const float *net;
     double alpha;
+    /* schedule: 0 = fixed-length sweeps of mixed trials (above); 1 = the paper's
+     * REGC step: a global coin chooses, with probability x0, one particle-exchange
+     * attempt per walker (removal or insertion with probability 1/2 each), else a
+     * replica-exchange step; then mc_cycles cycles of N displacement attempts */
+    int schedule;
+    double x0;
+    int mc_cycles;
 } orc_config;
 
 /* derived per-state constants */
@@ -423,8 +430,11 @@ static int site_occupied(const int32_t *site, int n, int k)
 }
 
 /* Returns 1 if the trial was accepted.  `lnk` holds log(k) for k = 0..n_max+1. */
+/* kind: -1 draws the move type from A0 with p_disp and p_ins; -2 draws a particle
+ * exchange (removal when A0 / 2^32 < 1/2, else insertion); 0 displacement,
+ * 1 insertion, 2 removal force it. */
 static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, double lnv,
-                 const orc_net *net, orc_walkers *W, int w, int64_t sweep, int t, float *margin)
+                 const orc_net *net, orc_walkers *W, int w, int64_t sweep, int t, float *margin, int kind)
 {
     uint32_t A[4], B[4];
     const uint32_t wid = (uint32_t)(w + c->walker_offset);
@@ -442,8 +452,10 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
     const uint64_t th_disp = (uint64_t)llround(c->p_disp * 4294967296.0);
     const uint64_t th_ins = th_disp + (uint64_t)llround(c->p_ins * 4294967296.0);
     const uint64_t a0 = A[0];
+    const int k = kind >= 0 ? kind
+                            : (kind == -2 ? (a0 < 0x80000000u ? 2 : 1) : (a0 < th_disp ? 0 : (a0 < th_ins ? 1 : 2)));
 
-    if (a0 < th_disp) {
+    if (k == 0) {
         /* ---- displacement, Eq. (7) ---- */
         st[ST_DISP_ATT]++;
         if (n == 0) { st[ST_EMPTY_REJ]++; return 0; }
@@ -492,7 +504,7 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
             return 1;
         }
         return 0;
-    } else if (a0 < th_ins) {
+    } else if (k == 1) {
         /* ---- insertion, Eq. (3) with the corrected exponent ---- */
         st[ST_INS_ATT]++;
         if (n >= c->n_max) { st[ST_CAP_REJ]++; return 0; }
@@ -647,6 +659,59 @@ static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W,
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's REGC step (Sec. II.A, Sec. III.A)                             */
+/* ------------------------------------------------------------------------- */
+/* Step q: a coin from Philox (0, q, 0xFFFFFFFF - class, 6), open uniform of word 0,
+ * below x0 -> every walker attempts one particle exchange with the reservoir
+ * (trial 0: removal or insertion with probability 1/2), otherwise the replica-
+ * exchange step q of the same four collective types.  Then every walker runs
+ * mc_cycles MC cycles of N displacement attempts (trials 1 .. mc_cycles N, N after
+ * the exchange attempt).  Samples after the step when (q+1) % sample_every == 0.
+ * Trace rows hold ceil((1 + mc_cycles n_max)/32) words per walker and step. */
+static int run_paper_schedule(const orc_config *c, const orc_statec *sc, const double *lnk, double lnv,
+                              const orc_net *net, orc_walkers *W, int64_t *step, int64_t n_steps, double *samp_e,
+                              int32_t *samp_n, int32_t *samp_s, int64_t samp_cap, int64_t *samp_count,
+                              uint32_t *trace_bits, int32_t *trace_n, int n_threads)
+{
+    const int S = c->n_t * c->n_mu;
+    const int Kmax = 1 + c->mc_cycles * c->n_max;
+    const int words = (Kmax + 31) / 32;
+    for (int64_t it = 0; it < n_steps; ++it) {
+        const int64_t q = *step;
+        if (c->sample_every > 0 && (q + 1) % c->sample_every == 0 && *samp_count + S > samp_cap) return -4;
+        uint32_t R[4];
+        philox_words(c->seed, 0u, (uint32_t)q, 0xFFFFFFFFu - (uint32_t)c->class_id, 6u, R);
+        const int gc = u32_open(R[0]) < c->x0;
+        if (!gc) swap_step(c, sc, W, q);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+        for (int w = 0; w < S; ++w) {
+            uint32_t *bits = trace_bits ? trace_bits + ((int64_t)it * S + w) * words : NULL;
+            float *mrow = W->margin ? W->margin + ((int64_t)it * S + w) * Kmax : NULL;
+            if (bits) memset(bits, 0, sizeof(uint32_t) * words);
+            if (mrow)
+                for (int t = 0; t < Kmax; ++t) mrow[t] = INFINITY;
+            if (gc && trial(c, sc, lnk, lnv, net, W, w, q, 0, mrow, -2) && bits) bits[0] |= 1u;
+            const int T = 1 + c->mc_cycles * W->n[w];
+            for (int t = 1; t < T; ++t) {
+                int acc = trial(c, sc, lnk, lnv, net, W, w, q, t, mrow ? mrow + t : NULL, 0);
+                if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
+            }
+            if (trace_n) trace_n[(int64_t)it * S + w] = W->n[w];
+        }
+        if (c->sample_every > 0 && (q + 1) % c->sample_every == 0) {
+            for (int w = 0; w < S; ++w) {
+                samp_e[*samp_count] = W->e[w];
+                samp_n[*samp_count] = W->n[w];
+                samp_s[*samp_count] = W->label[w];
+                (*samp_count)++;
+            }
+        }
+        *step = q + 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Driver                                                                    */
 /* ------------------------------------------------------------------------- */
 /* Runs sweeps [*sweep, *sweep + n_sweeps) of the whole REGC simulation.
@@ -656,7 +721,9 @@ static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W,
  * trace_bits: [n_sweeps][S][ceil(K/32)] accept bits (may be NULL);
  * trace_n:    [n_sweeps][S] N at each sweep end (may be NULL).
  * Returns 0, or -4 when the sample buffer is too small (nothing is lost: the
- * run stops before the sweep whose samples would not fit). */
+ * run stops before the sweep whose samples would not fit).
+ * With schedule 1 the unit is the paper's REGC step instead of the sweep
+ * (run_paper_schedule). */
 int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweeps,
             double *samp_e, int32_t *samp_n, int32_t *samp_s, int64_t samp_cap, int64_t *samp_count,
             uint32_t *trace_bits, int32_t *trace_n, int n_threads)
@@ -683,6 +750,11 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
         net_prepare(c->net, &netr);
         net = &netr;
     }
+    if (c->schedule == 1) {
+        rc = run_paper_schedule(c, sc, lnk, lnv, net, W, sweep, n_sweeps, samp_e, samp_n, samp_s, samp_cap,
+                                samp_count, trace_bits, trace_n, n_threads);
+        n_sweeps = 0;
+    }
     for (int64_t it = 0; it < n_sweeps; ++it) {
         const int64_t s = *sweep;
         if (c->sample_every > 0 && (s + 1) % c->sample_every == 0 && *samp_count + S > samp_cap) {
@@ -696,7 +768,7 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
             if (bits) memset(bits, 0, sizeof(uint32_t) * words);
             for (int t = 0; t < K; ++t) {
                 if (mrow) mrow[t] = INFINITY;
-                int acc = trial(c, sc, lnk, lnv, net, W, w, s, t, mrow ? mrow + t : NULL);
+                int acc = trial(c, sc, lnk, lnv, net, W, w, s, t, mrow ? mrow + t : NULL, -1);
                 if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
             }
             if (trace_n) trace_n[(int64_t)it * S + w] = W->n[w];

@@ -93,6 +93,13 @@ class Workload:
     swap_scheme: int = 0
     n_sweeps: int = 1000
     sites: Optional[np.ndarray] = None
+    # schedule 0: K-trial sweeps of mixed moves (the unit of a run is the sweep);
+    # schedule 1: the paper's REGC step (unit: the step): with probability x0 one
+    # particle-exchange attempt per walker, else a replica-exchange step, then
+    # mc_cycles cycles of N displacement attempts
+    schedule: int = 0
+    x0: float = 0.99
+    mc_cycles: int = 10
 
     @property
     def n_states(self) -> int:
@@ -104,6 +111,9 @@ class Workload:
 
     @property
     def trials(self) -> int:
+        """Trials per sweep (schedule 0), at most per REGC step (schedule 1)."""
+        if self.schedule == 1:
+            return 1 + self.mc_cycles * self.n_max
         return self.trials_per_sweep if self.trials_per_sweep > 0 else self.n_max + 1
 
     def replace(self, **kw) -> "Workload":
@@ -157,6 +167,12 @@ def small_lj(n_t: int = 2, n_mu: int = 2, n_max: int = 12, box: float = 6.0, hei
     return Workload(name="small-lj", slab=fcc100_slab(4, 2, box, rc=2.5), lx=box, ly=box,
                     zlo=0.0, zhi=height, t=linear_grid(t[0], t[1], n_t),
                     mu=linear_grid(mu[0], mu[1], n_mu), n_max=n_max, n_sweeps=n_sweeps, seed=seed)
+
+
+def paper_schedule(w: Workload, x0: float = 0.99, mc_cycles: int = 10, sample_every: int = 100) -> Workload:
+    """The workload run with the paper's REGC step (Sec. II.A): sample_every counts
+    REGC steps (the paper records after every 100 steps, Sec. III.A)."""
+    return w.replace(schedule=1, x0=x0, mc_cycles=mc_cycles, sample_every=sample_every)
 
 
 def random_configuration(rng: np.random.Generator, w: Workload, n: int, min_dist: float = 0.85,
