@@ -128,7 +128,18 @@ typedef struct {
  *                  (sweep launches, exchange, sweep-clock advance) in a hipGraph once
  *                  and replay it; the run is split into an eager prefix up to the next
  *                  exchange boundary, whole replays, and an eager remainder.  In graph
- *                  mode regc_timing_get's sweep figures cover whole replays. */
+ *                  mode regc_timing_get's sweep figures cover whole replays.
+ *  schedule        0: the sweeps above.  1: the paper's REGC step (Sec. II.A; the unit
+ *                  of regc_run, sample_every and the trace becomes the step): a coin
+ *                  (Philox block (0, step, 0xFFFFFFFF, 6), open uniform of word 0)
+ *                  below x0 gives every walker one particle-exchange attempt (trial 0:
+ *                  removal when A0 < 2^31, else insertion), otherwise the step is the
+ *                  replica-exchange step `step`; then every walker makes mc_cycles
+ *                  cycles of N displacement attempts (trials 1 .. mc_cycles N, N after
+ *                  trial 0).  p_disp, p_ins, trials_per_sweep and swap_every are not
+ *                  used.  Single-class contexts, no graph replay, no learned proposal.
+ *  x0              probability of the particle-exchange attempt (schedule 1).
+ *  mc_cycles       MC cycles after each attempt (schedule 1). */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -143,6 +154,9 @@ typedef struct {
     int split;
     int cull;
     int graph_intervals;
+    int schedule;
+    double x0;
+    int mc_cycles;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

@@ -132,6 +132,9 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->split = 0;
     o->cull = 0;
     o->graph_intervals = 0;
+    o->schedule = 0;
+    o->x0 = 0.99;
+    o->mc_cycles = 10;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -161,6 +164,12 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
                "walkers_per_block must be 0..%d", kMaxWalkersPerBlock);
     REGC_CHECK(o->split >= 0 && o->split <= 2, REGC_EINVAL, "split must be 0, 1 or 2");
     REGC_CHECK(o->graph_intervals >= 0 && o->graph_intervals <= 1000, REGC_EINVAL, "graph_intervals must be 0..1000");
+    REGC_CHECK(o->schedule == 0 || o->schedule == 1, REGC_EUNSUPPORTED, "unknown schedule %d", o->schedule);
+    if (o->schedule == 1) {
+        REGC_CHECK(o->x0 >= 0.0 && o->x0 <= 1.0, REGC_EINVAL, "x0 must lie in [0, 1]");
+        REGC_CHECK(o->mc_cycles >= 0 && o->mc_cycles <= 1000, REGC_EINVAL, "mc_cycles must be 0..1000");
+        REGC_CHECK(o->graph_intervals == 0, REGC_EUNSUPPORTED, "the paper schedule has no graph replay");
+    }
     return REGC_OK;
 }
 
@@ -228,7 +237,8 @@ static int ctx_alloc_and_init(regc_ctx *c)
     for (auto &k : c->cls) {
         k.off = W;
         k.S = (int)(k.t.size() * k.mu.size());
-        k.K = o.trials_per_sweep > 0 ? o.trials_per_sweep : k.sys.n_max + 1;
+        k.K = o.schedule == 1 ? 1 + o.mc_cycles * k.sys.n_max
+                              : (o.trials_per_sweep > 0 ? o.trials_per_sweep : k.sys.n_max + 1);
         W += k.S;
         kmax = std::max(kmax, k.K);
         nmax = std::max(nmax, k.sys.n_max);
@@ -418,6 +428,8 @@ static int create_common(int n_class, const regc_potential *pot, const regc_syst
 {
     REGC_CHECK(out, REGC_EINVAL, "null output pointer");
     REGC_CHECK(n_class >= 1, REGC_EINVAL, "need at least one class");
+    REGC_CHECK(!opts || opts->schedule != 1 || n_class == 1, REGC_EUNSUPPORTED,
+               "the paper schedule runs single-class contexts");
     *out = nullptr;
     for (int k = 0; k < n_class; ++k) {
         int rc = validate(pot, sys + k, grid + k, opts);
@@ -538,7 +550,13 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     int rc;
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
-    if (c->alpha > 0.0) {
+    if (c->opts.schedule == 1) {
+        PaperArgs pa{c->opts.x0, c->opts.mc_cycles};
+        if (c->opts.precision == REGC_FP64)
+            REGC_HIP(launch_paper_f64(a, pa, c->nblocks, c->wpb, c->smem, stream));
+        else
+            REGC_HIP(launch_paper_f32(a, pa, c->nblocks, c->wpb, c->smem, stream));
+    } else if (c->alpha > 0.0) {
         LearnArgs l{};
         const uint16_t *w = c->net_w.p;
         const float *bb = c->net_b.p;
@@ -593,6 +611,31 @@ static int launch_exchange(regc_ctx *c, int64_t q, hipStream_t stream, bool use_
     return REGC_OK;
 }
 
+// Philox4x32-10 on the host (the published definition: ten rounds of the two
+// multiplications 0xD2511F53 and 0xCD9E8D57, Weyl key increments 0x9E3779B9 and
+// 0xBB67AE85), for the paper schedule's per-step coin.
+static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c[1] ^ k0, n1 = (uint32_t)pb;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c[3] ^ k1, n3 = (uint32_t)pa;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// true when step q of the paper schedule is a particle-exchange (grand-canonical)
+// step, false when it is a replica-exchange step
+static bool paper_step_is_gc(const regc_ctx *c, int64_t q)
+{
+    uint32_t w[4] = {0u, (uint32_t)q, 0xFFFFFFFFu, 6u};
+    philox_host(w, (uint32_t)c->opts.seed, (uint32_t)(c->opts.seed >> 32));
+    return ((double)w[0] + 0.5) * (1.0 / 4294967296.0) < c->opts.x0;
+}
+
 // The captured graph bakes in the sample and trace bases: drop it when they move.
 static void invalidate_graph(regc_ctx *c)
 {
@@ -644,6 +687,24 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
     if (c->trace_cap > 0)
         REGC_CHECK(c->sweep + n_sweeps - c->trace_sweep0 <= c->trace_cap, REGC_ECAPACITY,
                    "trace capacity of %lld sweeps exceeded", (long long)c->trace_cap);
+    if (o.schedule == 1) {
+        // runs of steps without an exchange step go to one launch; an exchange step
+        // runs the exchange kernel first and starts the next launch
+        const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : 100;
+        int64_t q = c->sweep;
+        const int64_t end = c->sweep + n_sweeps;
+        while (q < end) {
+            int rc;
+            if (!paper_step_is_gc(c, q) && (rc = launch_exchange(c, q, c->stream, false))) return rc;
+            int64_t r = q + 1;
+            while (r < end && r - q < spl && paper_step_is_gc(c, r)) ++r;
+            if ((rc = launch_sweeps(c, q, (int)(r - q), c->stream, false))) return rc;
+            q = r;
+        }
+        c->sweep = end;
+        if (o.sample_every > 0) c->n_rec = c->sweep / o.sample_every - c->rec_base;
+        return REGC_OK;
+    }
     int64_t left = n_sweeps;
     auto eager = [&](int64_t count) -> int {
         int64_t rem = count;
@@ -699,6 +760,7 @@ extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
         return REGC_OK;
     }
     REGC_CHECK(c->cls.size() == 1, REGC_EUNSUPPORTED, "the learned proposal needs a single-class context");
+    REGC_CHECK(c->opts.schedule == 0, REGC_EUNSUPPORTED, "the learned proposal runs with the sweep schedule");
     int dev = 0, lds_max = 0;
     REGC_HIP(hipGetDevice(&dev));
     REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

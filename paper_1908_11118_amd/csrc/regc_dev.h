@@ -80,6 +80,12 @@ struct SweepArgs {
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
 };
 
+// The paper's REGC step (schedule 1): coin from Philox (0, step, 0xFFFFFFFF - class, 6).
+struct PaperArgs {
+    double x0;                   // probability of the particle-exchange attempt
+    int mc_cycles;               // MC cycles of N displacements after each attempt
+};
+
 struct SwapArgs {
     const ClassDev *cls;
     int32_t *label;
@@ -192,6 +198,10 @@ __host__ __device__ inline LearnLds learn_lds(int max_slab_len, int max_stencil,
 hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
                             hipStream_t s);
 hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
+                            hipStream_t s);
+hipError_t launch_paper_f64(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
+                            hipStream_t s);
+hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
                             hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
 hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s);

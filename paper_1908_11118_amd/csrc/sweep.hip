@@ -37,10 +37,12 @@
 
 #if defined(REGC_FP64)
 #define SWEEP_LAUNCH launch_sweep_f64
+#define PAPER_LAUNCH launch_paper_f64
 #define ENERGY_KERNEL energy_kernel_f64
 #define ENERGY_LAUNCH launch_energy_f64
 #else
 #define SWEEP_LAUNCH launch_sweep_f32
+#define PAPER_LAUNCH launch_paper_f32
 #define ENERGY_KERNEL energy_kernel_f32
 #define ENERGY_LAUNCH launch_energy_f32
 #endif
@@ -302,6 +304,229 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     }
 }
 
+// The paper's REGC step (Sec. II.A; Sec. III.A for the LJ run): for each step the
+// coin of Philox block (0, step, 0xFFFFFFFF - class, 6) -- open uniform of word 0
+// below x0 -- selects one particle-exchange attempt per walker (trial 0: removal
+// when A0 < 2^31, i.e. y1 < 1/2, else insertion); otherwise the host has run the
+// replica-exchange step before this launch.  Then mc_cycles cycles of N
+// displacement attempts, trials 1 .. mc_cycles N with N after trial 0.  Same
+// trial arithmetic as sweep_kernel (one wave per walker).  Single-class contexts.
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(SweepArgs a, PaperArgs pa)
+{
+    extern __shared__ __align__(32) unsigned char smem[];
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int waves = blockDim.x / kWave;
+    const int blk = blockIdx.x;
+    const ClassDev &C = a.cls[0];
+    const int nw = a.block_nw[blk];
+
+    const LdsLayout L = lds_layout(a.max_slab_len, a.max_stencil, a.gas_stride, a.max_slab_scan, waves, 0,
+                                   (int)sizeof(Real));
+    Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
+    int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
+    double *lnk = reinterpret_cast<double *>(smem + L.lnk);
+    Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)wave * a.gas_stride;
+
+    const int slab_len = C.slab_len;
+    for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
+#if defined(REGC_FP64)
+        const double *src = a.slab4 + 4 * (size_t)(C.slab_off + k);
+#else
+        const float *src = a.slab4f + 4 * (size_t)(C.slab_off + k);
+#endif
+        Real4 v;
+        v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
+        slab[k] = v;
+    }
+    const int n_st = C.bins ? C.ncx * C.ncy * 9 : 0;
+    for (int k = threadIdx.x; k < n_st; k += blockDim.x) stencil[k] = a.stencil[C.stencil_off + k];
+    for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
+    __syncthreads();
+    if (wave >= nw) return;
+
+    const int w = a.block_w0[blk] + wave;
+    const int n_max = C.n_max;
+    int n = a.n[w];
+    double e = a.e[w];
+    const int label = a.label[w];
+    const int sg = C.state_off + label;
+    const double beta = a.beta[sg];
+    const double lnz = a.lnz[sg];
+    const double lnzv = lnz + C.lnv;
+    {
+        const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            Real4 v;
+            v.x = (Real)src[3 * k]; v.y = (Real)src[3 * k + 1]; v.z = (Real)src[3 * k + 2]; v.w = 0;
+            gas[k] = v;
+        }
+    }
+    wave_sync();
+
+    Box b;
+    b.lx = (Real)C.lx; b.ly = (Real)C.ly; b.hx = (Real)C.half_lx; b.hy = (Real)C.half_ly;
+    b.ix = (Real)C.inv_lx; b.iy = (Real)C.inv_ly;
+    Pair gg, gs;
+    gg.sig2 = (Real)a.pot.sig2_gg; gg.eps4 = (Real)a.pot.eps4_gg; gg.shift = (Real)a.pot.shift_gg;
+    gg.rc2 = (Real)a.pot.rc2; gg.hc2 = (Real)a.pot.hc2_gg;
+    gs.sig2 = (Real)a.pot.sig2_gs; gs.eps4 = (Real)a.pot.eps4_gs; gs.shift = (Real)a.pot.shift_gs;
+    gs.rc2 = gg.rc2; gs.hc2 = (Real)a.pot.hc2_gs;
+    const bool ideal = a.pot.ideal != 0;
+    SlabView sv;
+    sv.atoms = slab; sv.stencil = stencil; sv.len = slab_len; sv.bins = C.bins;
+    sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
+    sv.inv_cap = C.bins ? 1.0f / (float)C.cap : 0.f;
+    sv.inv_cw_x = (Real)C.inv_cw_x; sv.inv_cw_y = (Real)C.inv_cw_y;
+    sv.top_plus_rc = (Real)(C.slab_top + sqrt(a.pot.rc2));
+    const double lx = C.lx, ly = C.ly, zlo = C.zlo, zhi = C.zhi, H = C.zhi - C.zlo;
+    const double md = a.max_disp;
+    const double tinv = 1.0 / beta;
+    const int slab_scan = C.bins ? 9 * C.cap : slab_len;
+
+    uint32_t stat = 0;
+    uint32_t useful = 0;
+    uint64_t cand = 0;
+    for (int it = 0; it < a.n_sweeps; ++it) {
+        const int64_t step = a.sweep0 + it;
+        const bool tracing = a.trace_bits != nullptr && (step - a.trace_sweep0) < a.trace_cap &&
+                             step >= a.trace_sweep0;
+        const uint4 coin = philox4x32_10(make_uint4(0u, (uint32_t)step, 0xFFFFFFFFu, 6u), a.key0, a.key1);
+        const bool exchange = uniform_open(coin.x) < pa.x0;
+        int T = 1 + pa.mc_cycles * n;
+        for (int t0 = 0; t0 < T; t0 += 32) {
+            const uint4 R = philox4x32_10(
+                make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)step, (uint32_t)w, (uint32_t)(lane & 1)),
+                a.key0, a.key1);
+            const double f0 = uniform_open(R.z), f1 = uniform_open(R.w), f2 = uniform_open(R.x);
+            const double f3 = log(uniform53(R.y, R.z));
+            uint32_t bits = 0;
+            for (int tt = 0; tt < 32 && t0 + tt < T; ++tt) {
+                const int t = t0 + tt;
+                if (t == 0 && !exchange) continue;
+                const uint32_t A0 = bcast(R.x, 2 * tt), A1 = bcast(R.y, 2 * tt);
+                // trial 0: removal when y1 = A0 / 2^32 < 1/2, else insertion; then displacements
+                const int kind = t == 0 ? (A0 < 0x80000000u ? 2 : 1) : 0;
+                stat += lane == 2 * kind;
+                bool accepted = false;
+                if (kind == 1 ? n >= n_max : n == 0) {
+                    stat += lane == (kind == 1 ? 6 : 7);
+                } else {
+                    const double lnU = bcast(f3, 2 * tt + 1);
+                    const double ux = bcast(f0, 2 * tt), uy = bcast(f1, 2 * tt), uz = bcast(f2, 2 * tt + 1);
+                    const int i = kind == 1 ? -1 : (int)(((uint64_t)A1 * (uint64_t)n) >> 32);
+                    const Real4 o = gas[kind == 1 ? 0 : i];
+                    double px = 0.0, py = 0.0, pz = 0.0, c;
+                    bool wall = false;
+                    if (kind == 0) {
+                        px = (double)o.x + md * (2.0 * ux - 1.0);
+                        py = (double)o.y + md * (2.0 * uy - 1.0);
+                        pz = (double)o.z + md * (2.0 * uz - 1.0);
+                        if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
+                        if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
+                        wall = pz < zlo || pz > zhi;
+                        c = 0.0;
+                    } else if (kind == 1) {
+                        px = lx * ux;
+                        py = ly * uy;
+                        pz = zlo + H * uz;
+                        c = lnzv - lnk[n + 1];
+                    } else {
+                        c = lnk[n] - lnzv;
+                    }
+                    if (wall) {
+                        stat += lane == 8;
+                    } else {
+                        const double thr = (c - lnU) * tinv;
+                        const Real qx = (Real)px, qy = (Real)py, qz = (Real)pz;
+                        double de = 0.0;
+                        bool core = false;
+                        if (!ideal) {
+                            Real pd;
+                            if (kind == 0)
+                                pd = partial_delta<true, true, 1, false>(gas, n, i, sv, b, gg, gs, lane, 0, qx, qy, qz,
+                                                                         o.x, o.y, o.z, nullptr, nullptr, core,
+                                                                         useful);
+                            else if (kind == 1)
+                                pd = partial_delta<true, false, 1, false>(gas, n, -1, sv, b, gg, gs, lane, 0, qx, qy,
+                                                                          qz, qx, qy, qz, nullptr, nullptr, core,
+                                                                          useful);
+                            else
+                                pd = partial_delta<false, true, 1, false>(gas, n, i, sv, b, gg, gs, lane, 0, o.x, o.y,
+                                                                          o.z, o.x, o.y, o.z, nullptr, nullptr, core,
+                                                                          useful);
+                            de = (double)pd;
+                            const uint64_t mult = kind == 0 ? 2 : 1;
+                            const Real zmin = kind == 0 ? (qz < o.z ? qz : o.z) : (kind == 1 ? qz : o.z);
+                            cand += mult * (uint64_t)((kind == 1 ? n : n - 1) +
+                                                      (zmin < sv.top_plus_rc ? slab_scan : 0));
+                        }
+                        if (core && kind != 2) {
+                            stat += lane == 9;
+                        } else if (de <= thr) {
+                            accepted = true;
+                            stat += lane == 2 * kind + 1;
+                            e += de;
+                            if (kind == 0) {
+                                if (lane == 0) {
+                                    Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
+                                    gas[i] = v;
+                                }
+                            } else if (kind == 1) {
+                                if (lane == 0) {
+                                    Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
+                                    gas[n] = v;
+                                }
+                                n += 1;
+                            } else {
+                                if (lane == 0 && i != n - 1) gas[i] = gas[n - 1];
+                                n -= 1;
+                            }
+                        }
+                    }
+                }
+                if (accepted) {
+                    bits |= 1u << tt;
+                    wave_sync();
+                }
+                if (t == 0) T = 1 + pa.mc_cycles * n;      // N after the exchange attempt
+            }
+            if (tracing && lane == 0)
+                a.trace_bits[((size_t)(step - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
+        }
+        if (lane == 0) {
+            if (tracing) {
+                // the words past this step's last trial hold no trial
+                uint32_t *row = a.trace_bits + ((size_t)(step - a.trace_sweep0) * a.n_walkers + w) * a.trace_words;
+                for (int wd = (T + 31) / 32; wd < a.trace_words; ++wd) row[wd] = 0u;
+                a.trace_n[(size_t)(step - a.trace_sweep0) * a.n_walkers + w] = n;
+            }
+            if (a.sample_every > 0 && (step + 1) % a.sample_every == 0) {
+                const int64_t rec = (step + 1) / a.sample_every - 1 - a.rec_base;
+                const size_t idx = (size_t)rec * a.n_walkers + w;
+                a.samp_e[idx] = e;
+                a.samp_n[idx] = n;
+                a.samp_s[idx] = label;
+                atomicAdd(a.hist + (size_t)sg * a.hist_stride + n, 1ull);
+            }
+        }
+    }
+
+    {
+        double *dst = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            const Real4 v = gas[k];
+            dst[3 * k] = (double)v.x; dst[3 * k + 1] = (double)v.y; dst[3 * k + 2] = (double)v.z;
+        }
+    }
+    if (lane == 0 && a.pairs) atomicAdd(a.pairs, (unsigned long long)cand);
+    if (lane < kNStat && stat) atomicAdd(a.stats + (size_t)sg * kNStat + lane, (unsigned long long)stat);
+    if (lane == 0) {
+        a.n[w] = n;
+        a.e[w] = e;
+    }
+}
+
 // Full recomputation of each walker's energy (gas-gas pairs once, gas-slab for
 // every atom), pair terms in Real, sums in FP64.  One wavefront per walker.
 __global__ void __launch_bounds__(256) ENERGY_KERNEL(EnergyArgs a)
@@ -354,6 +579,13 @@ hipError_t ENERGY_LAUNCH(const EnergyArgs &a, hipStream_t s)
 {
     const int per = 4;
     hipLaunchKernelGGL(ENERGY_KERNEL, dim3((a.n_walkers + per - 1) / per), dim3(kWave * per), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t PAPER_LAUNCH(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(paper_kernel, dim3(n_blocks), dim3(kWave * waves_per_block), smem, s, a, p);
     return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ class Opts(C.Structure):
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("sample_capacity", C.c_int64),
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
                 ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
-                ("graph_intervals", C.c_int)]
+                ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int)]
 
 
 _lib = None
@@ -201,6 +201,9 @@ class Regc:
         o.sample_capacity, o.trace_capacity = sample_capacity, trace_capacity
         o.walkers_per_block, o.sweeps_per_launch, o.slab_bins = walkers_per_block, sweeps_per_launch, slab_bins
         o.split, o.cull, o.graph_intervals = split, cull, graph_intervals
+        o.schedule = int(getattr(w0, "schedule", 0))
+        o.x0 = float(getattr(w0, "x0", 0.99))
+        o.mc_cycles = int(getattr(w0, "mc_cycles", 10))
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:

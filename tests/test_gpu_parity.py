@@ -313,3 +313,36 @@ def test_mbar_ideal_gas_iid_samples():
     assert np.allclose(got["mean_n"], ref["mean_n"], rtol=1e-9, atol=1e-9)
     assert np.allclose(got["f"], ref["f"] - ref["f"][0] + got["f"][0], atol=1e-8)
     mb.close()
+
+
+# ---------------------------------------------------------------------------
+# The paper's REGC step (x0 coin, one particle-exchange attempt, MC cycles)
+# ---------------------------------------------------------------------------
+def test_fp64_trajectories_paper_schedule_config1():
+    """64 replicas, x0 = 0.99, 10 MC cycles of N displacements per step, samples every
+    10 steps: identical decisions, exchanges, samples."""
+    w = W.paper_schedule(W.config1(), x0=0.99, mc_cycles=10, sample_every=10)
+    _fp64_trajectory(w, 300)
+
+
+@pytest.mark.parametrize("wpb,spl", [(1, 0), (4, 7)])
+def test_fp64_paper_schedule_variants(wpb, spl):
+    """Frequent exchange steps, few cycles, a binned slab, launch shapes."""
+    w = W.paper_schedule(W.config3_classes()[0].replace(t=W.linear_grid(0.6, 1.8, 4), mu=W.linear_grid(-6.0, -2.5, 4),
+                                                       n_max=60), x0=0.7, mc_cycles=2, sample_every=3)
+    _fp64_trajectory(w, 200, walkers_per_block=wpb, sweeps_per_launch=spl)
+    _fp64_trajectory(W.paper_schedule(W.ideal_gas(n_t=2, n_mu=3, n_max=30), x0=0.8, mc_cycles=1, sample_every=1), 400,
+                     walkers_per_block=wpb, sweeps_per_launch=spl)
+
+
+def test_paper_schedule_rejects_unsupported():
+    w = W.paper_schedule(W.small_lj())
+    with pytest.raises(regc.RegcError):
+        regc.Regc([w, w.replace(seed=2)], precision=regc.FP64)
+    with pytest.raises(regc.RegcError):
+        regc.Regc(w, precision=regc.FP64, graph_intervals=2)
+    net = regc.Mlp(W.mlp_pack(W.mlp_init(0)))
+    with regc.Regc(w, precision=regc.FP64) as g:
+        with pytest.raises(regc.RegcError):
+            g.set_proposal(net, 0.5)
+    net.close()
