@@ -298,10 +298,21 @@ def learned_leg(args):
     say(f"[learned] learned: reached={learned['reached']} t={learned['t_acc_s']:.2f} s sweeps={learned['sweeps']}")
     net.close()
     keep = ("reached", "t_acc_s", "sweeps", "max_se", "frac_within", "chi2", "ins_acc", "ms_per_sweep")
+    # the paper's REGC step (x0 = 0.99, 10 MC cycles of N displacements) from the same state
+    wp = W.paper_schedule(w, x0=0.99, mc_cycles=10, sample_every=1)
+    paper = P.time_to_accuracy(wp, blob, ref_m, ref_se, tau=args.learned_tau, chunk=50,
+                               max_seconds=args.learned_seconds, log=say)
+    say(f"[learned] paper schedule: reached={paper['reached']} t={paper['t_acc_s']:.2f} s steps={paper['sweeps']}")
     out["plain"] = {k: plain[k] for k in keep}
+    out["paper_schedule"] = {k: paper[k] for k in keep}
+    out["paper_schedule"]["steps"] = out["paper_schedule"].pop("sweeps")
+    out["paper_schedule"]["ms_per_step"] = out["paper_schedule"].pop("ms_per_sweep")
+    out["paper_schedule"]["x0"], out["paper_schedule"]["mc_cycles"] = 0.99, 10
     out["learned"] = {k: learned[k] for k in keep}
     out["learned"]["proposal"] = learned.get("proposal")
     out["efficiency_ratio_learned_over_plain"] = P.efficiency_ratio(plain, learned)
+    if plain["reached"] and paper["reached"]:
+        out["paper_schedule"]["t_acc_ratio_plain_over_paper"] = plain["t_acc_s"] / paper["t_acc_s"]
     if plain["reached"] and learned["reached"]:
         out["speedup_t_acc"] = plain["t_acc_s"] / learned["t_acc_s"]
     elif plain["reached"]:
