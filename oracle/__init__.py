@@ -65,13 +65,15 @@ class _Config(C.Structure):
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("walker_offset", C.c_int),
                 ("class_id", C.c_int), ("net", C.POINTER(C.c_float)), ("alpha", C.c_double),
-                ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int)]
+                ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
+                ("obs_dz", C.c_double), ("obs_layer_lo", C.c_double), ("obs_layer_hi", C.c_double),
+                ("obs_dr", C.c_double), ("obs_nr", C.c_int)]
 
 
 class _Walkers(C.Structure):
     _fields_ = [("n", _i32p), ("e", _dp), ("label", _i32p), ("wos", _i32p), ("xyz", _dp),
                 ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p),
-                ("margin", C.POINTER(C.c_float))]
+                ("margin", C.POINTER(C.c_float)), ("obs", _dp)]
 
 
 def _declare(L):
@@ -96,6 +98,11 @@ def _declare(L):
     L.orc_gumbel_argmax.argtypes = [C.POINTER(_Config), C.POINTER(C.c_float), C.c_uint32, C.c_uint32,
                                     C.c_uint32, _dp]
     L.orc_gumbel_argmax.restype = C.c_int
+    L.orc_obs_count.argtypes = [C.POINTER(_Config)]
+    L.orc_obs_count.restype = C.c_int
+    L.orc_observables.argtypes = [C.POINTER(_Config), _dp, C.c_int, _dp]
+    L.orc_mbar_observables.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _i32p, _dp, C.c_int, _dp, C.c_int,
+                                       _dp, _dp, C.c_int]
     L.orc_mbar_solve.argtypes = [C.c_int, _dp, _dp, _i64p, C.c_int64, _dp, _i32p, C.c_double,
                                  C.c_int, _dp, _dp, C.POINTER(C.c_int), _dp, C.c_int]
     L.orc_mbar_solve.restype = C.c_int
@@ -160,7 +167,7 @@ class Chain:
     method."""
 
     def __init__(self, w, n_threads: int | None = None, walker_offset: int = 0, class_id: int = 0,
-                 net=None, alpha: float = 0.0):
+                 net=None, alpha: float = 0.0, observables=None):
         self.w = w
         self.S = len(w.t) * len(w.mu)
         self.n_max = int(w.n_max)
@@ -198,7 +205,12 @@ class Chain:
         c.schedule = int(getattr(w, "schedule", 0))
         c.x0 = float(getattr(w, "x0", 0.99))
         c.mc_cycles = int(getattr(w, "mc_cycles", 10))
+        if observables:
+            c.obs_dz = float(observables["dz"])
+            c.obs_layer_lo, c.obs_layer_hi = (float(v) for v in observables["layer"])
+            c.obs_dr, c.obs_nr = float(observables["dr"]), int(observables["nr"])
         self.cfg = c
+        self.n_obs = lib().orc_obs_count(C.byref(c))
         S = self.S
         # initial state: empty walkers, walker w holds state w
         self.n = np.zeros(S, dtype=np.int32)
@@ -258,6 +270,9 @@ class Chain:
         tb = np.zeros((n_sweeps, S, words), dtype=np.uint32) if trace else None
         tn = np.zeros((n_sweeps, S), dtype=np.int32) if trace else None
         W = self._walkers()
+        ob = np.zeros((max(n_samp, 1), self.n_obs), dtype=np.float64) if self.n_obs else None
+        if ob is not None:
+            W.obs = _p(ob, _dp)
         mg = np.zeros((n_sweeps, S, self.K), dtype=np.float32) if margins else None
         if margins:
             W.margin = mg.ctypes.data_as(C.POINTER(C.c_float))
@@ -272,6 +287,16 @@ class Chain:
             out["bits"], out["trace_n"] = tb, tn
         if margins:
             out["margin"] = mg
+        if ob is not None:
+            out["obs"] = ob[:k]
+        return out
+
+    def observables(self, xyz):
+        """Observables (z-bin counts, layer pair counts by lateral distance, layer
+        population) of one configuration."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(self.n_obs)
+        lib().orc_observables(C.byref(self.cfg), _p(x, _dp), x.shape[0], _p(out, _dp))
         return out
 
     def voxel_of(self, p) -> int:
@@ -355,3 +380,21 @@ def mbar_targets(tbeta, tlnz, e, n, logd, n_max, n_threads=None):
                            _p(logd, _dp), n_max, _p(f, _dp), _p(mn, _dp), _p(me, _dp), _p(me2, _dp),
                            _p(pn, _dp), _p(ph, _i32p), n_threads or default_threads())
     return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "p_n": pn, "phase": ph}
+
+
+def mbar_observables(tbeta, tlnz, e, n, logd, n_max, obs, n_threads=None):
+    """Reweighted observables at T target states: mean [T, n_obs] and the average
+    conditional on N, cond [T, n_max+1, n_obs] (0 where p(N) = 0)."""
+    tbeta = np.ascontiguousarray(tbeta, dtype=np.float64)
+    tlnz = np.ascontiguousarray(tlnz, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    logd = np.ascontiguousarray(logd, dtype=np.float64)
+    obs = np.ascontiguousarray(obs, dtype=np.float64)
+    T, no = len(tbeta), obs.shape[1]
+    mean = np.zeros((T, no))
+    cond = np.zeros((T, n_max + 1, no))
+    lib().orc_mbar_observables(T, _p(tbeta, _dp), _p(tlnz, _dp), len(e), _p(e, _dp), _p(n, _i32p), _p(logd, _dp),
+                               n_max, _p(obs, _dp), no, _p(mean, _dp), _p(cond, _dp), n_threads or default_threads())
+    return mean, cond
+

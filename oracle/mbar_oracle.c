@@ -148,3 +148,42 @@ void orc_mbar_targets(int T, const double *tbeta, const double *tlnz, int64_t ns
         free(hist);
     }
 }
+
+/* Reweighted observables (Sec. II.B, Eq. (11), read with Omega_{l,m} -- all samples
+ * of a sampled state -- in the denominator, i.e. the MBAR weights above): for each
+ * target t the weights w_n(t); obs [ns][n_obs] per-sample values (any real
+ * observable, e.g. histogram counts).
+ *   mean [T][n_obs]          = sum_n w_n obs_n                      (<A>_t)
+ *   cond [T][n_max+1][n_obs] = sum_{N_n = N} w_n obs_n / p_t(N)    (<A | N>_t;
+ *                              0 where p_t(N) = 0)
+ * The joint <A chi_N>_t of Eq. (11) as printed is p_t(N) cond.  Either output may
+ * be NULL. */
+void orc_mbar_observables(int T, const double *tbeta, const double *tlnz, int64_t ns, const double *e,
+                          const int32_t *nn, const double *logd, int n_max, const double *obs, int n_obs,
+                          double *mean, double *cond, int n_threads)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+    for (int t = 0; t < T; ++t) {
+        double ft = mbar_free_energy(tbeta[t], tlnz[t], ns, e, nn, logd);
+        double *pn = (double *)calloc((size_t)n_max + 1, sizeof(double));
+        double *acc = (double *)calloc(((size_t)n_max + 1) * n_obs, sizeof(double));
+        for (int64_t n = 0; n < ns; ++n) {
+            double w = exp(ft - (tbeta[t] * e[n] - (double)nn[n] * tlnz[t]) - logd[n]);
+            pn[nn[n]] += w;
+            for (int k = 0; k < n_obs; ++k) acc[(size_t)nn[n] * n_obs + k] += w * obs[(size_t)n * n_obs + k];
+        }
+        for (int k = 0; k < n_obs; ++k) {
+            double m = 0.0;
+            for (int N = 0; N <= n_max; ++N) m += acc[(size_t)N * n_obs + k];
+            if (mean) mean[(size_t)t * n_obs + k] = m;
+        }
+        if (cond)
+            for (int N = 0; N <= n_max; ++N)
+                for (int k = 0; k < n_obs; ++k)
+                    cond[((size_t)t * (n_max + 1) + N) * n_obs + k] =
+                        pn[N] > 0.0 ? acc[(size_t)N * n_obs + k] / pn[N] : 0.0;
+        free(pn);
+        free(acc);
+    }
+}
+

@@ -134,6 +134,16 @@ typedef struct {
     int schedule;
     double x0;
     int mc_cycles;
+    /* per-sample structural observables (Sec. III.A: axial density, lateral radial
+     * distribution of a layer), recorded with every sample when obs_dz > 0:
+     *   counts of particles in z bins of width obs_dz from zlo (n_z = ceil(H/dz)
+     *   bins, the last one closed at zhi);
+     *   counts of unordered pairs of particles both in the layer
+     *   obs_layer_lo <= z < obs_layer_hi whose lateral minimum-image distance lies
+     *   in [k dr, (k+1) dr), k < obs_nr;
+     *   the number of particles in the layer. */
+    double obs_dz, obs_layer_lo, obs_layer_hi, obs_dr;
+    int obs_nr;
 } orc_config;
 
 /* derived per-state constants */
@@ -396,6 +406,44 @@ int orc_gumbel_argmax(const orc_config *c, const float *logit, uint32_t t, uint3
 }
 
 /* ------------------------------------------------------------------------- */
+/* Structural observables of one configuration                               */
+/* ------------------------------------------------------------------------- */
+int orc_obs_count(const orc_config *c)
+{
+    if (c->obs_dz <= 0.0) return 0;
+    return (int)ceil((c->zhi - c->zlo) / c->obs_dz) + c->obs_nr + 1;
+}
+
+void orc_observables(const orc_config *c, const double *xyz, int n, double *out)
+{
+    const int nz = (int)ceil((c->zhi - c->zlo) / c->obs_dz);
+    const int no = nz + c->obs_nr + 1;
+    for (int k = 0; k < no; ++k) out[k] = 0.0;
+    int in_layer = 0;
+    for (int i = 0; i < n; ++i) {
+        const double z = xyz[3 * i + 2];
+        int kz = (int)floor((z - c->zlo) / c->obs_dz);
+        kz = kz < 0 ? 0 : (kz > nz - 1 ? nz - 1 : kz);
+        out[kz] += 1.0;
+        if (z >= c->obs_layer_lo && z < c->obs_layer_hi) ++in_layer;
+    }
+    for (int i = 0; i < n; ++i) {
+        const double zi = xyz[3 * i + 2];
+        if (!(zi >= c->obs_layer_lo && zi < c->obs_layer_hi)) continue;
+        for (int j = i + 1; j < n; ++j) {
+            const double zj = xyz[3 * j + 2];
+            if (!(zj >= c->obs_layer_lo && zj < c->obs_layer_hi)) continue;
+            const double dx = min_image(xyz[3 * i] - xyz[3 * j], c->lx);
+            const double dy = min_image(xyz[3 * i + 1] - xyz[3 * j + 1], c->ly);
+            const double r = sqrt(dx * dx + dy * dy);
+            const int kr = (int)floor(r / c->obs_dr);
+            if (kr < c->obs_nr) out[nz + kr] += 1.0;
+        }
+    }
+    out[nz + c->obs_nr] = (double)in_layer;
+}
+
+/* ------------------------------------------------------------------------- */
 /* One trial move of one walker                                              */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -412,6 +460,8 @@ typedef struct {
      * decisions from their thresholds (|ln A - ln U|, and the Gumbel-max gap of a
      * network-drawn voxel); +inf for trials the network took no part in */
     float *margin;
+    /* [samples][n_obs] or NULL: the observables of every recorded sample */
+    double *obs;
 } orc_walkers;
 
 /* Metropolis decision on x = ln(acceptance ratio): accept when x >= 0, else
@@ -700,6 +750,9 @@ static int run_paper_schedule(const orc_config *c, const orc_statec *sc, const d
         }
         if (c->sample_every > 0 && (q + 1) % c->sample_every == 0) {
             for (int w = 0; w < S; ++w) {
+                if (W->obs && c->obs_dz > 0.0)
+                    orc_observables(c, W->xyz + (int64_t)w * c->n_max * 3, W->n[w],
+                                    W->obs + *samp_count * orc_obs_count(c));
                 samp_e[*samp_count] = W->e[w];
                 samp_n[*samp_count] = W->n[w];
                 samp_s[*samp_count] = W->label[w];
@@ -775,6 +828,9 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
         }
         if (c->sample_every > 0 && (s + 1) % c->sample_every == 0) {
             for (int w = 0; w < S; ++w) {
+                if (W->obs && c->obs_dz > 0.0)
+                    orc_observables(c, W->xyz + (int64_t)w * c->n_max * 3, W->n[w],
+                                    W->obs + *samp_count * orc_obs_count(c));
                 samp_e[*samp_count] = W->e[w];
                 samp_n[*samp_count] = W->n[w];
                 samp_s[*samp_count] = W->label[w];
