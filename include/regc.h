@@ -309,6 +309,44 @@ int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter);
 
 void regc_mbar_destroy(regc_mbar *mb);
 
+/* ---- structural observables (Sec. III.A) and their reweighting (Eq. (11)) ---- */
+/* Per recorded sample, counts from the walker's configuration:
+ *   n_z = ceil((z_hi - z_lo)/dz) axial bins: particles with floor((z - z_lo)/dz) = k
+ *   (clamped to the last bin);
+ *   n_r lateral bins: unordered pairs of particles both in the layer
+ *   layer_lo <= z < layer_hi whose minimum-image distance in x-y lies in
+ *   [k dr, (k+1) dr);
+ *   1 more: the number of particles in the layer.
+ * n_obs = n_z + n_r + 1 (n_z of the largest gas height for a batch). */
+typedef struct {
+    double dz;
+    double layer_lo, layer_hi;
+    double dr;
+    int n_r;
+} regc_observables;
+
+/* Records the observables with every sample from now on (spec NULL: stop).  Call
+ * before the sampling to analyse; not with graph replay (EUNSUPPORTED).  Runs
+ * split their launches at sample boundaries while observables are on. */
+int regc_set_observables(regc_ctx *ctx, const regc_observables *spec);
+/* Device view of the observable records [records][W][n_obs] (uint32), in the order
+ * of the samples (regc_get_samples). */
+int regc_observables_device(regc_ctx *ctx, const uint32_t **obs_dev, int *n_obs);
+
+/* Host copy of the observable records held (as regc_get_samples: n_out records of
+ * W walkers, at most cap_records). */
+int regc_get_observables(regc_ctx *ctx, uint32_t *obs, int64_t cap_records, int64_t *n_out);
+/* Observables of the samples given to regc_mbar_set_samples, same order, obs
+ * [ns][n_obs] uint32 (host, or device when on_device).  regc_mbar_load_run loads
+ * them with the samples when the run recorded observables. */
+int regc_mbar_set_observables(regc_mbar *mb, const uint32_t *obs, int n_obs, int on_device);
+/* Reweighted observables on a target grid (after regc_mbar_solve): mean
+ * [nT*nMu][n_obs] = sum_n w_n(t) obs_n; cond [nT][n_max+1][n_obs] = the average
+ * conditional on N (the phase of Sec. II.B), which depends on T only (0 where no
+ * sample has that N).  The joint average of Eq. (11) as printed is p(N) cond,
+ * p(N) from regc_mbar_targets.  Either output may be NULL. */
+int regc_mbar_observables(regc_mbar *mb, const regc_grid *targets, double *mean, double *cond);
+
 /* ---- learned insertion proposal (not in the paper; keeps its statistics) ---- */
 /* A multilayer perceptron maps the 16^3 occupancy grid of the gas region (voxel
  * (iz*16 + iy)*16 + ix, cells of lx/16 x ly/16 x (z_hi - z_lo)/16, indices clamped)

@@ -29,6 +29,7 @@ UNITS = [
     ("learned.hip", "learned_f64.o", ["-DREGC_FP64", "-ffp-contract=off"]),
     ("learned.hip", "learned_f32.o", ["-DREGC_FP32"]),
     ("swap.hip", "swap.o", ["-ffp-contract=off"]),
+    ("obs.hip", "obs.o", ["-ffp-contract=off"]),
     ("mbar.hip", "mbar.o", []),
     ("mlp.hip", "mlp.o", []),
     ("api.cpp", "api.o", ["-x", "hip"]),

@@ -71,6 +71,12 @@ struct regc_ctx {
     bool timing = false;
     std::vector<TimingPair> ev_sweep, ev_swap;
 
+    // structural observables recorded with the samples
+    bool obs_on = false;
+    regc_observables obs_spec{};
+    int obs_nz = 0, n_obs = 0;
+    DevBuf<uint32_t> obs_d;             // [rec_cap][W][n_obs]
+
     // learned insertion proposal (alpha > 0: the learned kernel runs the sweeps)
     double alpha = 0.0;
     DevBuf<uint16_t> net_w;                 // w1 | w2p | w3p | w4p (bfloat16)
@@ -636,6 +642,33 @@ static bool paper_step_is_gc(const regc_ctx *c, int64_t q)
     return ((double)w[0] + 0.5) * (1.0 / 4294967296.0) < c->opts.x0;
 }
 
+// Observables of every walker for the record that ends at `sweep` (a sample point).
+static int launch_obs_record(regc_ctx *c, int64_t sweep, hipStream_t stream)
+{
+    const regc_opts &o = c->opts;
+    if (!c->obs_on || o.sample_every <= 0 || sweep % o.sample_every != 0 || sweep == 0) return REGC_OK;
+    const int64_t rec = sweep / o.sample_every - 1 - c->rec_base;
+    REGC_CHECK(rec >= 0 && rec < c->rec_cap, REGC_ECAPACITY, "observable record %lld outside the buffer",
+               (long long)rec);
+    ObsArgs a{};
+    a.cls = c->cls_d.p;
+    a.walker_class = c->walker_class_d.p;
+    a.n_walkers = c->W;
+    a.n = c->n_d.p;
+    a.xyz = c->xyz_d.p;
+    a.xyz_stride = c->nmax_all;
+    a.dz = c->obs_spec.dz;
+    a.layer_lo = c->obs_spec.layer_lo;
+    a.layer_hi = c->obs_spec.layer_hi;
+    a.dr = c->obs_spec.dr;
+    a.n_z = c->obs_nz;
+    a.n_r = c->obs_spec.n_r;
+    a.n_obs = c->n_obs;
+    a.out = c->obs_d.p + (size_t)rec * c->W * c->n_obs;
+    REGC_HIP(launch_observables(a, stream));
+    return REGC_OK;
+}
+
 // The captured graph bakes in the sample and trace bases: drop it when they move.
 static void invalidate_graph(regc_ctx *c)
 {
@@ -697,8 +730,11 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
             int rc;
             if (!paper_step_is_gc(c, q) && (rc = launch_exchange(c, q, c->stream, false))) return rc;
             int64_t r = q + 1;
-            while (r < end && r - q < spl && paper_step_is_gc(c, r)) ++r;
+            while (r < end && r - q < spl && paper_step_is_gc(c, r) &&
+                   !(c->obs_on && o.sample_every > 0 && r % o.sample_every == 0))
+                ++r;
             if ((rc = launch_sweeps(c, q, (int)(r - q), c->stream, false))) return rc;
+            if ((rc = launch_obs_record(c, r, c->stream))) return rc;
             q = r;
         }
         c->sweep = end;
@@ -713,9 +749,12 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
             if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
             const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
             chunk = std::min<int64_t>(chunk, spl);
+            if (c->obs_on && o.sample_every > 0)
+                chunk = std::min<int64_t>(chunk, o.sample_every - c->sweep % o.sample_every);
             int rc = launch_sweeps(c, c->sweep, (int)chunk, c->stream, false);
             if (rc) return rc;
             c->sweep += chunk;
+            if ((rc = launch_obs_record(c, c->sweep, c->stream))) return rc;
             rem -= chunk;
             if (o.swap_every > 0 && c->sweep % o.swap_every == 0) {
                 rc = launch_exchange(c, c->sweep / o.swap_every - 1, c->stream, false);
@@ -786,6 +825,54 @@ extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
     REGC_HIP(hipStreamSynchronize(c->stream));
     c->learn_smem = smem;
     c->alpha = alpha;
+    return REGC_OK;
+}
+
+extern "C" int regc_set_observables(regc_ctx *c, const regc_observables *spec)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    if (!spec) {
+        c->obs_on = false;
+        return REGC_OK;
+    }
+    REGC_CHECK(c->opts.graph_intervals == 0, REGC_EUNSUPPORTED, "observables are not recorded in graph replay");
+    REGC_CHECK(c->opts.sample_every > 0 && c->rec_cap > 0, REGC_ESTATE, "the context records no samples");
+    REGC_CHECK(spec->dz > 0 && spec->dr > 0 && spec->n_r >= 0 && spec->layer_hi >= spec->layer_lo, REGC_EINVAL,
+               "bad observable spec");
+    int nz = 0;
+    for (auto &k : c->cls) nz = std::max(nz, (int)std::ceil((k.sys.z_hi - k.sys.z_lo) / spec->dz));
+    const int n_obs = nz + spec->n_r + 1;
+    REGC_CHECK(n_obs <= 2048, REGC_EINVAL, "%d observable bins (at most 2048)", n_obs);
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    int rc;
+    if (n_obs != c->n_obs || !c->obs_d.p) {
+        if ((rc = c->obs_d.alloc((size_t)c->rec_cap * c->W * n_obs))) return rc;
+    }
+    REGC_HIP(hipMemset(c->obs_d.p, 0, sizeof(uint32_t) * (size_t)c->rec_cap * c->W * n_obs));
+    c->obs_spec = *spec;
+    c->obs_nz = nz;
+    c->n_obs = n_obs;
+    c->obs_on = true;
+    return REGC_OK;
+}
+
+extern "C" int regc_observables_device(regc_ctx *c, const uint32_t **obs_dev, int *n_obs)
+{
+    REGC_CHECK(c && obs_dev && n_obs, REGC_EINVAL, "null argument");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    *obs_dev = c->obs_d.p;
+    *n_obs = c->n_obs;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_observables(regc_ctx *c, uint32_t *obs, int64_t cap_records, int64_t *n_out)
+{
+    REGC_CHECK(c && obs && n_out, REGC_EINVAL, "null argument");
+    REGC_CHECK(c->obs_d.p && c->n_obs > 0, REGC_ESTATE, "no observables recorded");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    const int64_t k = std::min(cap_records, c->n_rec);
+    REGC_HIP(hipMemcpy(obs, c->obs_d.p, sizeof(uint32_t) * (size_t)k * c->W * c->n_obs, hipMemcpyDeviceToHost));
+    *n_out = k;
     return REGC_OK;
 }
 
@@ -1129,5 +1216,14 @@ extern "C" int regc_mbar_load_run(regc_mbar *mb, regc_ctx *c, int cls, int64_t s
                          cnt * sizeof(int32_t), recs, hipMemcpyDeviceToDevice));
     REGC_HIP(hipMemcpy2D(s.p, cnt * sizeof(int32_t), c->samp_s.p + skip_records * W + off, W * sizeof(int32_t),
                          cnt * sizeof(int32_t), recs, hipMemcpyDeviceToDevice));
-    return regc_mbar_set_samples(mb, recs * cnt, e.p, n.p, s.p, 1);
+    if ((rc = regc_mbar_set_samples(mb, recs * cnt, e.p, n.p, s.p, 1))) return rc;
+    if (c->obs_d.p && c->n_obs > 0) {
+        DevBuf<uint32_t> ob;
+        const size_t no = c->n_obs;
+        if ((rc = ob.alloc(recs * cnt * no))) return rc;
+        REGC_HIP(hipMemcpy2D(ob.p, cnt * no * sizeof(uint32_t), c->obs_d.p + (skip_records * W + off) * no,
+                             W * no * sizeof(uint32_t), cnt * no * sizeof(uint32_t), recs, hipMemcpyDeviceToDevice));
+        if ((rc = regc_mbar_set_observables(mb, ob.p, (int)no, 1))) return rc;
+    }
+    return REGC_OK;
 }

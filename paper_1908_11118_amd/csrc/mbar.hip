@@ -309,6 +309,126 @@ __global__ void mbar_target_eval(int nT, int nMu, int nN, const double *tpart, c
     }
 }
 
+// Observables: gather into sorted order
+__global__ void mbar_gather_obs(int64_t ns, int n_obs, const int32_t *perm, const uint32_t *in, uint32_t *out)
+{
+    const int64_t total = ns * n_obs;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / n_obs;
+        const int k = (int)(q - i * n_obs);
+        out[q] = in[(int64_t)perm[i] * n_obs + k];
+    }
+}
+
+// Per chunk c (one N) and target temperature t (grid y): the scale mx = max of
+// y_i = -beta_t E_i - logD_i, s0 = sum exp(y_i - mx) and s_k = sum exp(y_i - mx) obs_ik,
+// every sum in sample order (deterministic).  out[(c nT + t)(n_obs + 2) + {0, 1, 2 + k}].
+__global__ void __launch_bounds__(kMbarThreads) mbar_obs_chunk(int nT, int n_obs, const double *tbeta, const double *e,
+                                                            const double *logd, const int *chunk_b,
+                                                            const int *chunk_e, const uint32_t *obs, double *out)
+{
+    __shared__ double w[kChunk];
+    __shared__ double red[kMbarThreads / 64];
+    const int c = blockIdx.x, t = blockIdx.y;
+    const int b = chunk_b[c], cnt = chunk_e[c] - b;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const double bt = tbeta[t];
+    double mx = -INFINITY;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const double y = -bt * e[b + i] - logd[b + i];
+        w[i] = y;
+        mx = y > mx ? y : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(mx, o);
+        mx = v > mx ? v : mx;
+    }
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    mx = red[0];
+    for (int k = 1; k < kMbarThreads / 64; ++k) mx = red[k] > mx ? red[k] : mx;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) w[i] = exp(w[i] - mx);
+    __syncthreads();
+    double *o = out + ((size_t)c * nT + t) * (n_obs + 2);
+    if (threadIdx.x == 0) {
+        double s0 = 0.0;
+        for (int i = 0; i < cnt; ++i) s0 += w[i];
+        o[0] = mx;
+        o[1] = s0;
+    }
+    for (int k = threadIdx.x; k < n_obs; k += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < cnt; ++i) acc += w[i] * (double)obs[(size_t)(b + i) * n_obs + k];
+        o[2 + k] = acc;
+    }
+}
+
+// Per target temperature t (block): the chunks of each N combined in order into the
+// conditional average cond[t][N][k] and G(N) = ln sum_{N_n = N} exp(-beta_t E - logD);
+// then for every target mu: p(N) = exp(N lnz + G(N) - lse) and mean = sum_N p(N) cond.
+__global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *part, const int *seg_c0,
+                              const int *seg_c1, const double *tlnz, double *cond, double *mean)
+{
+    extern __shared__ double G[];     // [nN]
+    const int t = blockIdx.x;
+    const size_t stride = (size_t)n_obs + 2;
+    for (int N = 0; N < nN; ++N) {
+        double M = -INFINITY;
+        for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+            const double m = part[((size_t)c * nT + t) * stride];
+            M = m > M ? m : M;
+        }
+        double s0 = 0.0;
+        if (M != -INFINITY)
+            for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+                const double *o = part + ((size_t)c * nT + t) * stride;
+                if (o[0] != -INFINITY) s0 += o[1] * exp(o[0] - M);
+            }
+        if (threadIdx.x == 0) G[N] = (M == -INFINITY || s0 <= 0.0) ? -INFINITY : M + log(s0);
+        for (int k = threadIdx.x; k < n_obs; k += blockDim.x) {
+            double a = 0.0;
+            if (M != -INFINITY)
+                for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+                    const double *o = part + ((size_t)c * nT + t) * stride;
+                    if (o[0] != -INFINITY) a += o[2 + k] * exp(o[0] - M);
+                }
+            const double v = s0 > 0.0 ? a / s0 : 0.0;
+            if (cond) cond[((size_t)t * nN + N) * n_obs + k] = v;
+        }
+    }
+    __syncthreads();
+    if (!mean) return;
+    for (int m = 0; m < nMu; ++m) {
+        const double lz = tlnz[t * nMu + m];
+        double mx = -INFINITY;
+        for (int N = 0; N < nN; ++N)
+            if (G[N] != -INFINITY) mx = fmax(mx, (double)N * lz + G[N]);
+        double sum = 0.0;
+        for (int N = 0; N < nN; ++N)
+            if (G[N] != -INFINITY) sum += exp((double)N * lz + G[N] - mx);
+        const double lse = mx + log(sum);
+        for (int k = threadIdx.x; k < n_obs; k += blockDim.x) {
+            double acc = 0.0;
+            for (int N = 0; N < nN; ++N) {
+                if (G[N] == -INFINITY) continue;
+                double a = 0.0, s0 = 0.0, M = -INFINITY;
+                for (int c = seg_c0[N]; c < seg_c1[N]; ++c) M = fmax(M, part[((size_t)c * nT + t) * stride]);
+                for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
+                    const double *o = part + ((size_t)c * nT + t) * stride;
+                    if (o[0] == -INFINITY) continue;
+                    const double sc = exp(o[0] - M);
+                    s0 += o[1] * sc;
+                    a += o[2 + k] * sc;
+                }
+                acc += exp((double)N * lz + G[N] - lse) * (a / s0);
+            }
+            mean[((size_t)t * nMu + m) * n_obs + k] = acc;
+        }
+    }
+}
+
 }  // namespace regc
 
 using namespace regc;
@@ -319,6 +439,9 @@ struct regc_mbar {
     std::vector<double> t, mu, beta_l, lnz;
     hipStream_t stream = nullptr;
     DevBuf<double> beta_d, lnz_d, lnomega_d, f_d, fnew_d, logA_d, partial_d, delta_d, e_d, logd_d;
+    DevBuf<int32_t> perm_d;           // sorted position -> original sample index
+    DevBuf<uint32_t> obs_d;           // observables in sorted order [ns][n_obs]
+    int n_obs = 0;
     DevBuf<int> chunk_n_d, chunk_b_d, chunk_e_d, seg_c0_d, seg_c1_d;
     int64_t ns = 0;
     int nchunks = 0;
@@ -386,7 +509,8 @@ extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e,
     hipStream_t s = mb->stream;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     DevBuf<double> e_in;
-    DevBuf<int32_t> n_in, s_in, idx, idx_out;
+    DevBuf<int32_t> n_in, s_in, idx;
+    DevBuf<int32_t> &idx_out = mb->perm_d;
     DevBuf<uint32_t> keys, keys_out;
     DevBuf<unsigned long long> omega, seg;
     DevBuf<int> bad;
@@ -463,6 +587,7 @@ extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e,
     mb->ns = ns;
     mb->have_samples = true;
     mb->solved = false;
+    mb->n_obs = 0;
     return REGC_OK;
 }
 
@@ -675,6 +800,60 @@ extern "C" int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double
     if (mean_e2) REGC_HIP(hipMemcpy(mean_e2, me2_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
     if (phase) REGC_HIP(hipMemcpy(phase, ph_d.p, sizeof(int32_t) * nK, hipMemcpyDeviceToHost));
     if (p_n) REGC_HIP(hipMemcpy(p_n, pn_d.p, sizeof(double) * nK * mb->nN, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_set_observables(regc_mbar *mb, const uint32_t *obs, int n_obs, int on_device)
+{
+    REGC_CHECK(mb && obs, REGC_EINVAL, "null argument");
+    REGC_CHECK(mb->have_samples, REGC_ESTATE, "set the samples first");
+    REGC_CHECK(n_obs > 0 && n_obs <= 4096, REGC_EINVAL, "n_obs must be 1..4096");
+    hipStream_t s = mb->stream;
+    const size_t count = (size_t)mb->ns * n_obs;
+    DevBuf<uint32_t> in;
+    int rc;
+    if ((rc = in.alloc(count)) || (rc = mb->obs_d.alloc(count))) return rc;
+    REGC_HIP(hipMemcpyAsync(in.p, obs, sizeof(uint32_t) * count,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(mbar_gather_obs, dim3(grid), dim3(256), 0, s, (int64_t)mb->ns, n_obs, mb->perm_d.p, in.p,
+                       mb->obs_d.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    mb->n_obs = n_obs;
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_observables(regc_mbar *mb, const regc_grid *targets, double *mean, double *cond)
+{
+    REGC_CHECK(mb && targets && targets->t && targets->mu, REGC_EINVAL, "null argument");
+    REGC_CHECK(mb->solved, REGC_ESTATE, "solve first");
+    REGC_CHECK(mb->n_obs > 0, REGC_ESTATE, "no observables loaded");
+    const int nT = targets->n_t, nMu = targets->n_mu, nK = nT * nMu, no = mb->n_obs;
+    REGC_CHECK(nT > 0 && nMu > 0, REGC_EINVAL, "empty target grid");
+    std::vector<double> tb(nT), tz(nK);
+    for (int l = 0; l < nT; ++l) {
+        REGC_CHECK(targets->t[l] > 0, REGC_EINVAL, "target temperatures must be positive");
+        tb[l] = 1.0 / targets->t[l];
+        for (int m = 0; m < nMu; ++m) tz[l * nMu + m] = lnz_of(targets->t[l], targets->mu[m], mb->lambda1);
+    }
+    hipStream_t s = mb->stream;
+    DevBuf<double> tb_d, tz_d, part, cond_d, mean_d;
+    int rc;
+    if ((rc = tb_d.alloc(nT)) || (rc = tz_d.alloc(nK)) || (rc = part.alloc((size_t)mb->nchunks * nT * (no + 2))) ||
+        (rc = cond_d.alloc(cond ? (size_t)nT * mb->nN * no : 1)) || (rc = mean_d.alloc(mean ? (size_t)nK * no : 1)))
+        return rc;
+    REGC_HIP(hipMemcpyAsync(tb_d.p, tb.data(), sizeof(double) * nT, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(tz_d.p, tz.data(), sizeof(double) * nK, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(mbar_obs_chunk, dim3(mb->nchunks, nT), dim3(kMbarThreads), 0, s, nT, no, tb_d.p, mb->e_d.p,
+                       mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, mb->obs_d.p, part.p);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mbar_obs_eval, dim3(nT), dim3(256), sizeof(double) * mb->nN, s, nT, nMu, mb->nN, no, part.p,
+                       mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d.p, cond ? cond_d.p : nullptr, mean ? mean_d.p : nullptr);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    if (cond) REGC_HIP(hipMemcpy(cond, cond_d.p, sizeof(double) * (size_t)nT * mb->nN * no, hipMemcpyDeviceToHost));
+    if (mean) REGC_HIP(hipMemcpy(mean, mean_d.p, sizeof(double) * (size_t)nK * no, hipMemcpyDeviceToHost));
     return REGC_OK;
 }
 

@@ -80,6 +80,19 @@ struct SweepArgs {
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
 };
 
+// Structural observables of every walker at a sample point (see regc.h).
+struct ObsArgs {
+    const ClassDev *cls;
+    const int *walker_class;
+    int n_walkers;
+    const int32_t *n;
+    const double *xyz;
+    int xyz_stride;
+    double dz, layer_lo, layer_hi, dr;
+    int n_z, n_r, n_obs;
+    uint32_t *out;               // [W][n_obs] of this record
+};
+
 // The paper's REGC step (schedule 1): coin from Philox (0, step, 0xFFFFFFFF - class, 6).
 struct PaperArgs {
     double x0;                   // probability of the particle-exchange attempt
@@ -204,6 +217,7 @@ hipError_t launch_paper_f64(const SweepArgs &a, const PaperArgs &p, int n_blocks
 hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
                             hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
+hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s);
 hipError_t launch_clock_set(int64_t *clock, int64_t value, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs &a, hipStream_t s);

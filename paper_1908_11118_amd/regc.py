@@ -32,7 +32,8 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
-           "regc_set_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_strerror", "regc_last_error"]
+           "regc_set_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
+           "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables", "regc_strerror", "regc_last_error"]
 
 
 class RegcError(RuntimeError):
@@ -60,6 +61,11 @@ class System(C.Structure):
 
 class Grid(C.Structure):
     _fields_ = [("n_t", C.c_int), ("n_mu", C.c_int), ("t", _dp), ("mu", _dp)]
+
+
+class ObsSpec(C.Structure):
+    _fields_ = [("dz", C.c_double), ("layer_lo", C.c_double), ("layer_hi", C.c_double), ("dr", C.c_double),
+                ("n_r", C.c_int)]
 
 
 class Opts(C.Structure):
@@ -138,6 +144,11 @@ def lib():
         L.regc_set_proposal.argtypes = [vp, vp, C.c_double]
         L.regc_get_proposal_stats.argtypes = [vp, _i64p]
         L.regc_capture_voxels.argtypes = [vp, vp, vp]
+        L.regc_set_observables.argtypes = [vp, C.POINTER(ObsSpec)]
+        L.regc_observables_device.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int)]
+        L.regc_get_observables.argtypes = [vp, _u32p, C.c_int64, _i64p]
+        L.regc_mbar_set_observables.argtypes = [vp, vp, C.c_int, C.c_int]
+        L.regc_mbar_observables.argtypes = [vp, C.POINTER(Grid), _dp, _dp]
         L.regc_strerror.argtypes = [C.c_int]
         L.regc_strerror.restype = C.c_char_p
         L.regc_last_error.restype = C.c_char_p
@@ -218,6 +229,7 @@ class Regc:
         _check(lib().regc_get_layout(h, None, offs, cnts))
         self.offsets, self.counts = list(offs), list(cnts)
         self.W = sum(self.counts)
+        self.n_obs = 0
         self.n_max_all = max(w.n_max for w in wl)
         self.K_max = max(w.trials for w in wl)
         s = stream if stream is not None else _torch_stream()
@@ -343,6 +355,27 @@ class Regc:
         mixture weight alpha (mlp None or alpha 0: the plain method)."""
         _check(lib().regc_set_proposal(self.h, mlp.h if mlp is not None else None, float(alpha)))
 
+    def set_observables(self, dz: float, layer, dr: float, nr: int):
+        """Record per-sample axial z-bin counts, layer pair counts by lateral distance
+        and the layer population with every sample (None-like nr < 0 switches off)."""
+        if nr < 0:
+            _check(lib().regc_set_observables(self.h, None))
+            self.n_obs = 0
+            return
+        spec = ObsSpec(float(dz), float(layer[0]), float(layer[1]), float(dr), int(nr))
+        _check(lib().regc_set_observables(self.h, C.byref(spec)))
+        p, k = C.c_void_p(), C.c_int()
+        _check(lib().regc_observables_device(self.h, C.byref(p), C.byref(k)))
+        self.n_obs = k.value
+
+    def observables(self):
+        """Observable records [records * W, n_obs] (uint32), in the order of samples()."""
+        recs = self.sample_count() // max(self.W, 1)
+        out = np.zeros((max(recs, 1), self.W, self.n_obs), np.uint32)
+        got = C.c_int64()
+        _check(lib().regc_get_observables(self.h, _p(out, _u32p), recs, C.byref(got)))
+        return out[: got.value].reshape(-1, self.n_obs)
+
     def capture_voxels(self, vox_dev_ptr: int, n_dev_ptr: int):
         """Voxel lists [W][n_max] (uint16) and N [W] of the walkers into device memory
         (asynchronous on the context's stream)."""
@@ -416,6 +449,22 @@ class Mbar:
         _check(lib().regc_mbar_targets(self.h, C.byref(g), _p(f, _dp), _p(mn, _dp), _p(me, _dp), _p(me2, _dp),
                                        _p(pn, _dp), _p(ph, _i32p)))
         return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "p_n": pn, "phase": ph}
+
+    def set_observables(self, obs):
+        """Per-sample observables [ns, n_obs] in the order of the samples (uint32)."""
+        ob = np.ascontiguousarray(obs, dtype=np.uint32)
+        _check(lib().regc_mbar_set_observables(self.h, ob.ctypes.data_as(C.c_void_p), ob.shape[1], 0))
+        self.n_obs = ob.shape[1]
+
+    def observables(self, t, mu, n_obs: int):
+        """Reweighted observables: mean [nT, nMu, n_obs] and the average conditional on
+        N, cond [nT, n_max+1, n_obs]."""
+        keep = []
+        g = _grid(t, mu, keep)
+        mean = np.zeros((len(t), len(mu), n_obs))
+        cond = np.zeros((len(t), self.n_max + 1, n_obs))
+        _check(lib().regc_mbar_observables(self.h, C.byref(g), _p(mean, _dp), _p(cond, _dp)))
+        return mean, cond
 
     def timing(self):
         ms = C.c_double()

@@ -346,3 +346,76 @@ def test_paper_schedule_rejects_unsupported():
         with pytest.raises(regc.RegcError):
             g.set_proposal(net, 0.5)
     net.close()
+
+
+# ---------------------------------------------------------------------------
+# Structural observables with the samples, and their reweighting
+# ---------------------------------------------------------------------------
+OBS = dict(dz=0.12, layer=(0.6, 1.6), dr=0.1, nr=28)
+
+
+def test_fp64_observables_match_the_oracle():
+    """Per-sample axial counts and layer pair counts: bit-exact against the oracle
+    along identical FP64 trajectories (samples every sweep and every 3 sweeps)."""
+    for w, sweeps in ((W.config1(), 120), (W.small_lj(n_t=2, n_mu=3, n_max=16, mu=(-4.0, -2.0)).replace(
+            sample_every=3), 150)):
+        _say(f"[observables] {w.name} sweeps={sweeps}")
+        ref = oracle.Chain(w, observables=OBS)
+        r = ref.run(sweeps)
+        with regc.Regc(w, precision=regc.FP64, sample_capacity=(sweeps // w.sample_every + 1) * w.n_states) as g:
+            g.set_observables(OBS["dz"], OBS["layer"], OBS["dr"], OBS["nr"])
+            g.run(sweeps)
+            smp = g.samples()
+            ob = g.observables()
+        assert np.array_equal(smp["n"], r["n"])
+        assert ob.shape == r["obs"].shape
+        assert np.array_equal(ob.astype(np.float64), r["obs"])
+        assert r["obs"][:, -1].max() > 0          # the layer is populated
+
+
+def test_mbar_observables_match_the_oracle():
+    w = W.small_lj(n_t=2, n_mu=3, n_max=16, mu=(-4.5, -2.5)).replace(sample_every=1)
+    ref = oracle.Chain(w, observables=OBS)
+    ref.run(300)
+    out = ref.run(3000)
+    beta, lnz = oracle.state_arrays(w)
+    omega = np.bincount(out["state"], minlength=w.n_states)
+    f, logd, ok, _, _ = oracle.mbar_solve(beta, lnz, omega, out["e"], out["n"], tol=1e-12)
+    assert ok
+    tt, tm = np.array([0.95, 1.2, 1.45]), np.array([-4.2, -3.1])
+    tb = np.repeat(1.0 / tt, len(tm))
+    tz = np.array([oracle.state_lnz(T, m) for T in tt for m in tm])
+    mean_ref, cond_ref = oracle.mbar_observables(tb, tz, out["e"], out["n"], logd, w.n_max, out["obs"])
+    mb = regc.Mbar(w.t, w.mu, w.n_max)
+    mb.set_samples(out["e"], out["n"], out["state"])
+    mb.solve(tol=1e-12, max_iter=20000)
+    mb.set_observables(out["obs"].astype(np.uint32))
+    mean, cond = mb.observables(tt, tm, out["obs"].shape[1])
+    mb.close()
+    scale = np.abs(mean_ref).max()
+    assert np.abs(mean.reshape(-1, mean.shape[-1]) - mean_ref).max() <= 1e-8 * scale
+    # the conditional average depends on T only; the oracle repeats it for every mu
+    cref = cond_ref.reshape(len(tt), len(tm), w.n_max + 1, -1)[:, 0]
+    assert np.abs(cond - cref).max() <= 1e-8 * max(1.0, np.abs(cref).max())
+
+
+def test_mbar_load_run_carries_the_observables():
+    w = W.small_lj(n_t=2, n_mu=2, n_max=12).replace(sample_every=2)
+    with regc.Regc(w, precision=regc.FP64, sample_capacity=400 * w.n_states) as g:
+        g.set_observables(OBS["dz"], OBS["layer"], OBS["dr"], OBS["nr"])
+        g.run(600)
+        smp = g.samples()
+        ob = g.observables()
+        a = regc.Mbar(w.t, w.mu, w.n_max)
+        a.load_run(g, 0, 20)
+        a.solve(tol=1e-11, max_iter=20000)
+        m1, c1 = a.observables(w.t, w.mu, g.n_obs)
+    b = regc.Mbar(w.t, w.mu, w.n_max)
+    skip = 20 * w.n_states
+    b.set_samples(smp["e"][skip:], smp["n"][skip:], smp["state"][skip:])
+    b.solve(tol=1e-11, max_iter=20000)
+    b.set_observables(ob[skip:])
+    m2, c2 = b.observables(w.t, w.mu, ob.shape[1])
+    a.close()
+    b.close()
+    assert np.allclose(m1, m2, rtol=1e-12, atol=1e-12) and np.allclose(c1, c2, rtol=1e-12, atol=1e-12)
