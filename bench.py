@@ -222,9 +222,15 @@ def main():
         gm = regc.Regc(wm, precision=prec, sample_capacity=args.mbar_records * w.n_states,
                        walkers_per_block=args.wpb)
         gm.set_walkers(wk["n"], wk["xyz"], label=wk["label"])
+        # structural observables with every record: axial density in 0.12-sigma bins and
+        # the lateral pair distribution of the first adsorbed layer (0.6 <= z < 1.6)
+        gm.set_observables(0.12, (0.6, 1.6), 0.05, 120)
         print(f"[bench] reweighting leg: collecting {args.mbar_records} records", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_rec = time.perf_counter()
         gm.run(args.mbar_records)
         gm.sync()
+        t_rec = time.perf_counter() - t_rec
         mb = regc.Mbar(w.t, w.mu, w.n_max)
         mb.load_run(gm, 0, 0)
         ns = args.mbar_records * w.n_states
@@ -233,6 +239,14 @@ def main():
         tr = mb.targets(W.linear_grid(0.5, 2.0, 64), W.linear_grid(-8.0, -2.0, 64))
         per_iter = ms / max(nit, 1)
         L = len(w.t)
+        tt_obs = W.linear_grid(0.5, 2.0, 16)
+        t_obs = time.perf_counter()
+        mean_o, cond_o = mb.observables(tt_obs, W.linear_grid(-8.0, -2.0, 64), gm.n_obs)
+        t_obs = time.perf_counter() - t_obs
+        result["observables"] = {"n_obs": gm.n_obs, "bins": f"{gm.n_obs - 121} axial (0.12) + 120 lateral (0.05, layer 0.6-1.6) + 1",
+                                 "recording_ms_per_record": 1e3 * t_rec / args.mbar_records,
+                                 "reweight_targets": "16 T x 64 mu", "reweight_s": t_obs,
+                                 "fp64_fma_per_s": 16 * ns * gm.n_obs / t_obs}
         result["mbar"] = {"states": w.n_states, "samples": ns, "iterations": nit, "converged": bool(conv),
                           "max_delta_f": delta, "ms_per_iteration": per_iter,
                           "fp64_exp_per_s": L * ns / (per_iter * 1e-3),
