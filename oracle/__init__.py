@@ -73,7 +73,7 @@ class _Config(C.Structure):
 class _Walkers(C.Structure):
     _fields_ = [("n", _i32p), ("e", _dp), ("label", _i32p), ("wos", _i32p), ("xyz", _dp),
                 ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p),
-                ("margin", C.POINTER(C.c_float)), ("obs", _dp)]
+                ("margin", C.POINTER(C.c_float)), ("obs", _dp), ("min_e", _dp), ("min_xyz", _dp)]
 
 
 def _declare(L):
@@ -98,6 +98,7 @@ def _declare(L):
     L.orc_gumbel_argmax.argtypes = [C.POINTER(_Config), C.POINTER(C.c_float), C.c_uint32, C.c_uint32,
                                     C.c_uint32, _dp]
     L.orc_gumbel_argmax.restype = C.c_int
+    L.orc_aiat_phase.argtypes = [C.c_int, _dp, C.c_int, _dp, _i32p]
     L.orc_obs_count.argtypes = [C.POINTER(_Config)]
     L.orc_obs_count.restype = C.c_int
     L.orc_observables.argtypes = [C.POINTER(_Config), _dp, C.c_int, _dp]
@@ -223,6 +224,9 @@ class Chain:
         self.swap_att = np.zeros((4, S), dtype=np.int64)
         self.swap_acc = np.zeros((4, S), dtype=np.int64)
         self.sweep = np.zeros(1, dtype=np.int64)
+        # lowest-energy recorded configuration per N
+        self.min_e = np.full(self.n_max + 1, np.inf)
+        self.min_xyz = np.zeros((self.n_max + 1, self.n_max, 3))
 
     def _walkers(self):
         W = _Walkers()
@@ -232,6 +236,7 @@ class Chain:
         W.site = _p(self.site, _i32p) if self.w.mode == 2 else None
         W.stats = _p(self.stats, _i64p)
         W.swap_att, W.swap_acc = _p(self.swap_att, _i64p), _p(self.swap_acc, _i64p)
+        W.min_e, W.min_xyz = _p(self.min_e, _dp), _p(self.min_xyz, _dp)
         return W
 
     def set_walkers(self, n, xyz, e=None, label=None):
@@ -397,4 +402,13 @@ def mbar_observables(tbeta, tlnz, e, n, logd, n_max, obs, n_threads=None):
     lib().orc_mbar_observables(T, _p(tbeta, _dp), _p(tlnz, _dp), len(e), _p(e, _dp), _p(n, _i32p), _p(logd, _dp),
                                n_max, _p(obs, _dp), no, _p(mean, _dp), _p(cond, _dp), n_threads or default_threads())
     return mean, cond
+
+
+def aiat_phase(min_e, mu):
+    """aiAT@REGC phase (the N of lowest E_min(N) - E_min(0) - N mu) at each mu."""
+    me = np.ascontiguousarray(min_e, dtype=np.float64)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    out = np.zeros(len(m), dtype=np.int32)
+    lib().orc_aiat_phase(len(me) - 1, _p(me, _dp), len(m), _p(m, _dp), _p(out, _i32p))
+    return out
 

@@ -462,6 +462,11 @@ typedef struct {
     float *margin;
     /* [samples][n_obs] or NULL: the observables of every recorded sample */
     double *obs;
+    /* lowest-energy recorded configuration of each N (Sec. III.A, aiAT@REGC step
+     * (i)), or NULL: min_e [n_max+1] (+inf where N was never recorded), min_xyz
+     * [n_max+1][n_max][3]; updated at every sample point, walkers in index order,
+     * replaced only by a strictly lower energy */
+    double *min_e, *min_xyz;
 } orc_walkers;
 
 /* Metropolis decision on x = ln(acceptance ratio): accept when x >= 0, else
@@ -750,6 +755,11 @@ static int run_paper_schedule(const orc_config *c, const orc_statec *sc, const d
         }
         if (c->sample_every > 0 && (q + 1) % c->sample_every == 0) {
             for (int w = 0; w < S; ++w) {
+                if (W->min_e && W->e[w] < W->min_e[W->n[w]]) {
+                    W->min_e[W->n[w]] = W->e[w];
+                    memcpy(W->min_xyz + (int64_t)W->n[w] * c->n_max * 3, W->xyz + (int64_t)w * c->n_max * 3,
+                           sizeof(double) * 3 * (size_t)W->n[w]);
+                }
                 if (W->obs && c->obs_dz > 0.0)
                     orc_observables(c, W->xyz + (int64_t)w * c->n_max * 3, W->n[w],
                                     W->obs + *samp_count * orc_obs_count(c));
@@ -828,6 +838,11 @@ int orc_run(const orc_config *c, orc_walkers *W, int64_t *sweep, int64_t n_sweep
         }
         if (c->sample_every > 0 && (s + 1) % c->sample_every == 0) {
             for (int w = 0; w < S; ++w) {
+                if (W->min_e && W->e[w] < W->min_e[W->n[w]]) {
+                    W->min_e[W->n[w]] = W->e[w];
+                    memcpy(W->min_xyz + (int64_t)W->n[w] * c->n_max * 3, W->xyz + (int64_t)w * c->n_max * 3,
+                           sizeof(double) * 3 * (size_t)W->n[w]);
+                }
                 if (W->obs && c->obs_dz > 0.0)
                     orc_observables(c, W->xyz + (int64_t)w * c->n_max * 3, W->n[w],
                                     W->obs + *samp_count * orc_obs_count(c));
@@ -863,3 +878,25 @@ double orc_swap_lnratio(double beta_a, double lnz_a, double beta_b, double lnz_b
 {
     return (beta_a - beta_b) * (e_i - e_j) + (double)(n_j - n_i) * (lnz_a - lnz_b);
 }
+
+/* aiAT@REGC phase map (Sec. III.A, Eq. (12)): with the free energies of the phases
+ * approximated by their lowest sampled energies, dG_N(mu) = E_min(N) - E_min(0) - N mu
+ * (the frozen slab has no energy of its own); the phase at mu is the N of lowest
+ * dG among the recorded N (smallest N on ties).  phase [n_mu]. */
+void orc_aiat_phase(int n_max, const double *min_e, int n_mu, const double *mu, int32_t *phase)
+{
+    for (int m = 0; m < n_mu; ++m) {
+        double best = INFINITY;
+        int arg = -1;
+        for (int N = 0; N <= n_max; ++N) {
+            if (!(min_e[N] < INFINITY)) continue;
+            const double g = min_e[N] - (min_e[0] < INFINITY ? min_e[0] : 0.0) - (double)N * mu[m];
+            if (g < best) {
+                best = g;
+                arg = N;
+            }
+        }
+        phase[m] = arg;
+    }
+}
+
