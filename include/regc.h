@@ -347,6 +347,20 @@ int regc_mbar_set_observables(regc_mbar *mb, const uint32_t *obs, int n_obs, int
  * p(N) from regc_mbar_targets.  Either output may be NULL. */
 int regc_mbar_observables(regc_mbar *mb, const regc_grid *targets, double *mean, double *cond);
 
+/* ---- aiAT@REGC (Sec. III.A, Eq. (12)) ---- */
+/* From now on, at every sample point, keep per class and N the recorded
+ * configuration of lowest energy (walkers in index order, replaced only by a
+ * strictly lower energy).  Not with graph replay. */
+int regc_track_minima(regc_ctx *ctx, int on);
+/* e_min [n_max+1] of class cls (HUGE_VAL where N was never recorded) and, if xyz is
+ * not NULL, the configurations xyz [n_max+1][n_max][3] (first N rows valid). */
+int regc_get_minima(regc_ctx *ctx, int cls, double *e_min, double *xyz);
+/* The aiAT@REGC phase at each mu: the recorded N of lowest
+ * dG_N = E_min(N) - E_min(0) - N mu (free energies approximated by the lowest
+ * energies, the frozen slab contributing nothing; smallest N on ties, -1 if no N
+ * was recorded).  Host computation on the e_min array. */
+int regc_aiat_phase(const double *e_min, int n_max, int n_mu, const double *mu, int32_t *phase);
+
 /* ---- learned insertion proposal (not in the paper; keeps its statistics) ---- */
 /* A multilayer perceptron maps the 16^3 occupancy grid of the gas region (voxel
  * (iz*16 + iy)*16 + ix, cells of lx/16 x ly/16 x (z_hi - z_lo)/16, indices clamped)

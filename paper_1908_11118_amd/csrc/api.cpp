@@ -76,6 +76,11 @@ struct regc_ctx {
     regc_observables obs_spec{};
     int obs_nz = 0, n_obs = 0;
     DevBuf<uint32_t> obs_d;             // [rec_cap][W][n_obs]
+    // lowest-energy recorded configuration per (class, N)
+    bool min_on = false;
+    DevBuf<unsigned long long> minkey_d, minold_d;
+    DevBuf<int> minw_d;
+    DevBuf<double> mine_d, minxyz_d;
 
     // learned insertion proposal (alpha > 0: the learned kernel runs the sweeps)
     double alpha = 0.0;
@@ -646,7 +651,25 @@ static bool paper_step_is_gc(const regc_ctx *c, int64_t q)
 static int launch_obs_record(regc_ctx *c, int64_t sweep, hipStream_t stream)
 {
     const regc_opts &o = c->opts;
-    if (!c->obs_on || o.sample_every <= 0 || sweep % o.sample_every != 0 || sweep == 0) return REGC_OK;
+    if (o.sample_every <= 0 || sweep % o.sample_every != 0 || sweep == 0) return REGC_OK;
+    if (c->min_on) {
+        MinArgs m{};
+        m.walker_class = c->walker_class_d.p;
+        m.n_walkers = c->W;
+        m.n_class = (int)c->cls.size();
+        m.nN = c->nmax_all + 1;
+        m.n = c->n_d.p;
+        m.e = c->e_d.p;
+        m.xyz = c->xyz_d.p;
+        m.xyz_stride = c->nmax_all;
+        m.key = c->minkey_d.p;
+        m.old_key = c->minold_d.p;
+        m.widx = c->minw_d.p;
+        m.e_min = c->mine_d.p;
+        m.xyz_min = c->minxyz_d.p;
+        REGC_HIP(launch_minima(m, stream));
+    }
+    if (!c->obs_on) return REGC_OK;
     const int64_t rec = sweep / o.sample_every - 1 - c->rec_base;
     REGC_CHECK(rec >= 0 && rec < c->rec_cap, REGC_ECAPACITY, "observable record %lld outside the buffer",
                (long long)rec);
@@ -731,7 +754,7 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
             if (!paper_step_is_gc(c, q) && (rc = launch_exchange(c, q, c->stream, false))) return rc;
             int64_t r = q + 1;
             while (r < end && r - q < spl && paper_step_is_gc(c, r) &&
-                   !(c->obs_on && o.sample_every > 0 && r % o.sample_every == 0))
+                   !((c->obs_on || c->min_on) && o.sample_every > 0 && r % o.sample_every == 0))
                 ++r;
             if ((rc = launch_sweeps(c, q, (int)(r - q), c->stream, false))) return rc;
             if ((rc = launch_obs_record(c, r, c->stream))) return rc;
@@ -749,7 +772,7 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
             if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
             const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
             chunk = std::min<int64_t>(chunk, spl);
-            if (c->obs_on && o.sample_every > 0)
+            if ((c->obs_on || c->min_on) && o.sample_every > 0)
                 chunk = std::min<int64_t>(chunk, o.sample_every - c->sweep % o.sample_every);
             int rc = launch_sweeps(c, c->sweep, (int)chunk, c->stream, false);
             if (rc) return rc;
@@ -862,6 +885,74 @@ extern "C" int regc_observables_device(regc_ctx *c, const uint32_t **obs_dev, in
     REGC_HIP(hipStreamSynchronize(c->stream));
     *obs_dev = c->obs_d.p;
     *n_obs = c->n_obs;
+    return REGC_OK;
+}
+
+extern "C" int regc_track_minima(regc_ctx *c, int on)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    if (!on) {
+        c->min_on = false;
+        return REGC_OK;
+    }
+    REGC_CHECK(c->opts.graph_intervals == 0, REGC_EUNSUPPORTED, "minima are not tracked in graph replay");
+    REGC_CHECK(c->opts.sample_every > 0, REGC_ESTATE, "the context records no samples");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (!c->minkey_d.p) {
+        const size_t slots = c->cls.size() * (size_t)(c->nmax_all + 1);
+        int rc;
+        if ((rc = c->minkey_d.alloc(slots)) || (rc = c->minold_d.alloc(slots)) || (rc = c->minw_d.alloc(slots)) ||
+            (rc = c->mine_d.alloc(slots)) || (rc = c->minxyz_d.alloc(slots * c->nmax_all * 3)))
+            return rc;
+        std::vector<unsigned long long> k(slots, ~0ull);
+        std::vector<int> wi(slots, 0x7fffffff);
+        std::vector<double> e(slots, HUGE_VAL);
+        REGC_HIP(hipMemcpy(c->minkey_d.p, k.data(), slots * sizeof(unsigned long long), hipMemcpyHostToDevice));
+        REGC_HIP(hipMemcpy(c->minw_d.p, wi.data(), slots * sizeof(int), hipMemcpyHostToDevice));
+        REGC_HIP(hipMemcpy(c->mine_d.p, e.data(), slots * sizeof(double), hipMemcpyHostToDevice));
+        REGC_HIP(hipMemset(c->minxyz_d.p, 0, slots * c->nmax_all * 3 * sizeof(double)));
+    }
+    c->min_on = true;
+    return REGC_OK;
+}
+
+extern "C" int regc_get_minima(regc_ctx *c, int cls, double *e_min, double *xyz)
+{
+    REGC_CHECK(c && e_min, REGC_EINVAL, "null argument");
+    REGC_CHECK(cls >= 0 && cls < (int)c->cls.size(), REGC_EINVAL, "class index out of range");
+    REGC_CHECK(c->minkey_d.p, REGC_ESTATE, "minima are not tracked");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    const size_t nN = c->nmax_all + 1, nmc = c->cls[cls].sys.n_max;
+    std::vector<double> e(nN);
+    REGC_HIP(hipMemcpy(e.data(), c->mine_d.p + cls * nN, nN * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t N = 0; N <= nmc; ++N) e_min[N] = e[N];
+    if (xyz) {
+        std::vector<double> x(nN * c->nmax_all * 3);
+        REGC_HIP(hipMemcpy(x.data(), c->minxyz_d.p + cls * nN * c->nmax_all * 3, x.size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+        for (size_t N = 0; N <= nmc; ++N)
+            for (size_t j = 0; j < nmc * 3; ++j) xyz[(N * nmc) * 3 + j] = x[(N * c->nmax_all) * 3 + j];
+    }
+    return REGC_OK;
+}
+
+extern "C" int regc_aiat_phase(const double *e_min, int n_max, int n_mu, const double *mu, int32_t *phase)
+{
+    REGC_CHECK(e_min && mu && phase && n_max >= 0 && n_mu >= 0, REGC_EINVAL, "bad argument");
+    const double e0 = e_min[0] < HUGE_VAL ? e_min[0] : 0.0;
+    for (int m = 0; m < n_mu; ++m) {
+        double best = HUGE_VAL;
+        int arg = -1;
+        for (int N = 0; N <= n_max; ++N) {
+            if (!(e_min[N] < HUGE_VAL)) continue;
+            const double g = e_min[N] - e0 - (double)N * mu[m];
+            if (g < best) {
+                best = g;
+                arg = N;
+            }
+        }
+        phase[m] = arg;
+    }
     return REGC_OK;
 }
 

@@ -53,6 +53,64 @@ __global__ void __launch_bounds__(64) obs_kernel(ObsArgs a)
     for (int k = lane; k < a.n_obs; k += 64) out[k] = hist[k];
 }
 
+// IEEE double -> unsigned key of the same order (zero of either sign as +0)
+__device__ __forceinline__ unsigned long long energy_key(double e)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(e == 0.0 ? 0.0 : e);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ unsigned long long load_u64(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int load_i32(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One workgroup: (0) remember the keys, (1) atomic minimum of every walker's energy
+// key per (class, N), (2) among walkers at a new strict minimum the lowest index,
+// (3) that walker stores its energy and configuration; the index slots are cleared.
+// The result is the oracle's sequential rule (walkers in index order, replaced only
+// by a strictly lower energy).
+__global__ void __launch_bounds__(1024) minima_kernel(MinArgs a)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int slots = a.n_class * a.nN;
+    for (int k = tid; k < slots; k += nt) a.old_key[k] = load_u64(a.key + k);
+    __syncthreads();
+    for (int w = tid; w < a.n_walkers; w += nt)
+        atomicMin(a.key + a.walker_class[w] * a.nN + a.n[w], energy_key(a.e[w]));
+    __syncthreads();
+    for (int w = tid; w < a.n_walkers; w += nt) {
+        const int k = a.walker_class[w] * a.nN + a.n[w];
+        const unsigned long long ek = energy_key(a.e[w]);
+        if (ek == load_u64(a.key + k) && ek < a.old_key[k]) atomicMin(a.widx + k, w);
+    }
+    __syncthreads();
+    for (int w = tid; w < a.n_walkers; w += nt) {
+        const int k = a.walker_class[w] * a.nN + a.n[w];
+        if (load_i32(a.widx + k) != w) continue;
+        a.e_min[k] = a.e[w];
+        const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
+        double *dst = a.xyz_min + (size_t)k * a.xyz_stride * 3;
+        for (int q = 0; q < 3 * a.n[w]; ++q) dst[q] = src[q];
+    }
+    __syncthreads();
+    for (int w = tid; w < a.n_walkers; w += nt) {
+        const int k = a.walker_class[w] * a.nN + a.n[w];
+        if (load_i32(a.widx + k) == w) a.widx[k] = 0x7fffffff;
+    }
+}
+
+hipError_t launch_minima(const MinArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(minima_kernel, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s)
 {
     if (a.n_obs > kObsMaxBins) return hipErrorInvalidValue;

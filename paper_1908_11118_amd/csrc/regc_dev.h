@@ -93,6 +93,20 @@ struct ObsArgs {
     uint32_t *out;               // [W][n_obs] of this record
 };
 
+// Lowest-energy recorded configuration per (class, N), updated at sample points.
+struct MinArgs {
+    const int *walker_class;
+    int n_walkers, n_class, nN;  // nN = largest n_max + 1
+    const int32_t *n;
+    const double *e;
+    const double *xyz;
+    int xyz_stride;
+    unsigned long long *key, *old_key;   // [n_class][nN] ordered energy bits (~0: none)
+    int *widx;                           // [n_class][nN] INT_MAX between updates
+    double *e_min;                       // [n_class][nN]
+    double *xyz_min;                     // [n_class][nN][xyz_stride][3]
+};
+
 // The paper's REGC step (schedule 1): coin from Philox (0, step, 0xFFFFFFFF - class, 6).
 struct PaperArgs {
     double x0;                   // probability of the particle-exchange attempt
@@ -218,6 +232,7 @@ hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks
                             hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
+hipError_t launch_minima(const MinArgs &a, hipStream_t s);
 hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s);
 hipError_t launch_clock_set(int64_t *clock, int64_t value, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs &a, hipStream_t s);

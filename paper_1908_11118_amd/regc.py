@@ -33,7 +33,8 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
            "regc_set_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
-           "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables", "regc_strerror", "regc_last_error"]
+           "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables",
+           "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error"]
 
 
 class RegcError(RuntimeError):
@@ -145,6 +146,9 @@ def lib():
         L.regc_get_proposal_stats.argtypes = [vp, _i64p]
         L.regc_capture_voxels.argtypes = [vp, vp, vp]
         L.regc_set_observables.argtypes = [vp, C.POINTER(ObsSpec)]
+        L.regc_track_minima.argtypes = [vp, C.c_int]
+        L.regc_get_minima.argtypes = [vp, C.c_int, _dp, _dp]
+        L.regc_aiat_phase.argtypes = [_dp, C.c_int, C.c_int, _dp, _i32p]
         L.regc_observables_device.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int)]
         L.regc_get_observables.argtypes = [vp, _u32p, C.c_int64, _i64p]
         L.regc_mbar_set_observables.argtypes = [vp, vp, C.c_int, C.c_int]
@@ -368,6 +372,17 @@ class Regc:
         _check(lib().regc_observables_device(self.h, C.byref(p), C.byref(k)))
         self.n_obs = k.value
 
+    def track_minima(self, on: bool = True):
+        _check(lib().regc_track_minima(self.h, int(on)))
+
+    def minima(self, cls: int = 0):
+        """(e_min [n_max+1], xyz [n_max+1, n_max, 3]) of class cls."""
+        nm = self.workloads[cls].n_max
+        e = np.zeros(nm + 1)
+        x = np.zeros((nm + 1, nm, 3))
+        _check(lib().regc_get_minima(self.h, cls, _p(e, _dp), _p(x, _dp)))
+        return e, x
+
     def observables(self):
         """Observable records [records * W, n_obs] (uint32), in the order of samples()."""
         recs = self.sample_count() // max(self.W, 1)
@@ -548,3 +563,13 @@ class Mlp:
         st = C.c_int64()
         _check(lib().regc_mlp_timing(self.h, C.byref(ms), C.byref(st)))
         return ms.value, st.value
+
+
+def aiat_phase(e_min, mu):
+    """aiAT@REGC phase map along mu from the lowest recorded energies per N."""
+    e = np.ascontiguousarray(e_min, dtype=np.float64)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    out = np.zeros(len(m), dtype=np.int32)
+    _check(lib().regc_aiat_phase(_p(e, _dp), len(e) - 1, len(m), _p(m, _dp), _p(out, _i32p)))
+    return out
+

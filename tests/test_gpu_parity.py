@@ -419,3 +419,45 @@ def test_mbar_load_run_carries_the_observables():
     a.close()
     b.close()
     assert np.allclose(m1, m2, rtol=1e-12, atol=1e-12) and np.allclose(c1, c2, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# aiAT@REGC: lowest recorded energy and configuration per N
+# ---------------------------------------------------------------------------
+def test_fp64_minima_and_aiat_map_match_the_oracle():
+    w = W.config1()
+    sweeps = 200
+    _say("[minima] config1")
+    ref = oracle.Chain(w)
+    ref.run(sweeps)
+    with regc.Regc(w, precision=regc.FP64, sample_capacity=(sweeps + 1) * w.n_states) as g:
+        g.track_minima(True)
+        g.run(sweeps)
+        e_min, xyz = g.minima(0)
+    seen = np.isfinite(ref.min_e)
+    assert np.array_equal(np.isfinite(e_min), seen)
+    assert np.allclose(e_min[seen], ref.min_e[seen], rtol=1e-10, atol=1e-9)
+    for N in np.nonzero(seen)[0]:
+        assert np.array_equal(xyz[N, :N], ref.min_xyz[N, :N]), N
+    mu = np.linspace(-9.0, -1.0, 161)
+    assert np.array_equal(regc.aiat_phase(e_min, mu), oracle.aiat_phase(ref.min_e, mu))
+
+
+def test_fp64_minima_per_class_of_a_batch():
+    classes = _batch_classes()
+    sweeps = 45
+    with regc.Regc(classes, precision=regc.FP64, sample_capacity=(sweeps // 3 + 1) * sum(
+            w.n_states for w in classes)) as g:
+        g.track_minima(True)
+        g.run(sweeps)
+        mins = [g.minima(c) for c in range(len(classes))]
+        offs = g.offsets
+    for c, w in enumerate(classes):
+        ref = oracle.Chain(w, walker_offset=offs[c], class_id=c)
+        ref.run(sweeps)
+        e_min, xyz = mins[c]
+        seen = np.isfinite(ref.min_e)
+        assert np.array_equal(np.isfinite(e_min), seen), c
+        assert np.allclose(e_min[seen], ref.min_e[seen], rtol=1e-10, atol=1e-9), c
+        for N in np.nonzero(seen)[0]:
+            assert np.array_equal(xyz[N, :N], ref.min_xyz[N, :N]), (c, N)
