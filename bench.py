@@ -225,6 +225,7 @@ def main():
         # structural observables with every record: axial density in 0.12-sigma bins and
         # the lateral pair distribution of the first adsorbed layer (0.6 <= z < 1.6)
         gm.set_observables(0.12, (0.6, 1.6), 0.05, 120)
+        gm.track_minima(True)
         print(f"[bench] reweighting leg: collecting {args.mbar_records} records", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t_rec = time.perf_counter()
@@ -247,6 +248,18 @@ def main():
                                  "recording_ms_per_record": 1e3 * t_rec / args.mbar_records,
                                  "reweight_targets": "16 T x 64 mu", "reweight_s": t_obs,
                                  "fp64_fma_per_s": 16 * ns * gm.n_obs / t_obs}
+        # aiAT@REGC phase map (lowest sampled energy per N) against the reweighted one
+        e_min, _ = gm.minima(0)
+        tmu = W.linear_grid(-8.0, -2.0, 64)
+        ai = regc.aiat_phase(e_min, tmu)
+        mb_phase = np.asarray(tr["phase"]).reshape(64, 64)
+        agree = mb_phase == ai[None, :]
+        low = mb_phase <= w.n_max // 4
+        result["aiat_vs_mbar"] = {"grid": "64 T x 64 mu", "agree_fraction": float(agree.mean()),
+                                  "agree_fraction_where_mbar_N_le_nmax_4": float(agree[low].mean()) if low.any()
+                                  else None,
+                                  "aiat_phases": int(len(set(ai.tolist()))),
+                                  "mbar_phases": int(len(set(mb_phase.ravel().tolist())))}
         result["mbar"] = {"states": w.n_states, "samples": ns, "iterations": nit, "converged": bool(conv),
                           "max_delta_f": delta, "ms_per_iteration": per_iter,
                           "fp64_exp_per_s": L * ns / (per_iter * 1e-3),
