@@ -67,13 +67,15 @@ class _Config(C.Structure):
                 ("class_id", C.c_int), ("net", C.POINTER(C.c_float)), ("alpha", C.c_double),
                 ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
                 ("obs_dz", C.c_double), ("obs_layer_lo", C.c_double), ("obs_layer_hi", C.c_double),
-                ("obs_dr", C.c_double), ("obs_nr", C.c_int)]
+                ("obs_dr", C.c_double), ("obs_nr", C.c_int), ("md_steps", C.c_int), ("md_dt", C.c_double),
+                ("md_tau", C.c_double)]
 
 
 class _Walkers(C.Structure):
     _fields_ = [("n", _i32p), ("e", _dp), ("label", _i32p), ("wos", _i32p), ("xyz", _dp),
                 ("site", _i32p), ("stats", _i64p), ("swap_att", _i64p), ("swap_acc", _i64p),
-                ("margin", C.POINTER(C.c_float)), ("obs", _dp), ("min_e", _dp), ("min_xyz", _dp)]
+                ("margin", C.POINTER(C.c_float)), ("obs", _dp), ("min_e", _dp), ("min_xyz", _dp),
+                ("vel", _dp), ("tv", _dp)]
 
 
 def _declare(L):
@@ -98,6 +100,8 @@ def _declare(L):
     L.orc_gumbel_argmax.argtypes = [C.POINTER(_Config), C.POINTER(C.c_float), C.c_uint32, C.c_uint32,
                                     C.c_uint32, _dp]
     L.orc_gumbel_argmax.restype = C.c_int
+    L.orc_md_forces.argtypes = [C.POINTER(_Config), _dp, C.c_int, _dp]
+    L.orc_md_forces.restype = C.c_double
     L.orc_aiat_phase.argtypes = [C.c_int, _dp, C.c_int, _dp, _i32p]
     L.orc_obs_count.argtypes = [C.POINTER(_Config)]
     L.orc_obs_count.restype = C.c_int
@@ -206,6 +210,9 @@ class Chain:
         c.schedule = int(getattr(w, "schedule", 0))
         c.x0 = float(getattr(w, "x0", 0.99))
         c.mc_cycles = int(getattr(w, "mc_cycles", 10))
+        c.md_steps = int(getattr(w, "md_steps", 0))
+        c.md_dt = float(getattr(w, "md_dt", 0.005))
+        c.md_tau = float(getattr(w, "md_tau", 0.1))
         if observables:
             c.obs_dz = float(observables["dz"])
             c.obs_layer_lo, c.obs_layer_hi = (float(v) for v in observables["layer"])
@@ -227,6 +234,9 @@ class Chain:
         # lowest-energy recorded configuration per N
         self.min_e = np.full(self.n_max + 1, np.inf)
         self.min_xyz = np.zeros((self.n_max + 1, self.n_max, 3))
+        # molecular dynamics: velocities and the temperature they belong to (0: none yet)
+        self.vel = np.zeros((S, self.n_max, 3))
+        self.tv = np.zeros(S)
 
     def _walkers(self):
         W = _Walkers()
@@ -237,6 +247,7 @@ class Chain:
         W.stats = _p(self.stats, _i64p)
         W.swap_att, W.swap_acc = _p(self.swap_att, _i64p), _p(self.swap_acc, _i64p)
         W.min_e, W.min_xyz = _p(self.min_e, _dp), _p(self.min_xyz, _dp)
+        W.vel, W.tv = _p(self.vel, _dp), _p(self.tv, _dp)
         return W
 
     def set_walkers(self, n, xyz, e=None, label=None):
@@ -303,6 +314,13 @@ class Chain:
         out = np.zeros(self.n_obs)
         lib().orc_observables(C.byref(self.cfg), _p(x, _dp), x.shape[0], _p(out, _dp))
         return out
+
+    def md_forces(self, xyz):
+        """(potential energy, forces [n, 3]) of a configuration."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        f = np.zeros_like(x)
+        e = lib().orc_md_forces(C.byref(self.cfg), _p(x, _dp), x.shape[0], _p(f, _dp))
+        return e, f
 
     def voxel_of(self, p) -> int:
         q = np.ascontiguousarray(p, dtype=np.float64).reshape(3)

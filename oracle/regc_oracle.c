@@ -144,6 +144,12 @@ typedef struct {
      *   the number of particles in the layer. */
     double obs_dz, obs_layer_lo, obs_layer_hi, obs_dr;
     int obs_nr;
+    /* canonical part of the paper's REGC step by molecular dynamics (Sec. II.A:
+     * "S parallel molecular dynamics ... runs", Sec. II.A.3): md_steps > 0 replaces
+     * the MC cycles by md_steps velocity-Verlet steps of md_dt (unit mass) with the
+     * stochastic velocity-rescaling thermostat of time constant md_tau (0: none) */
+    int md_steps;
+    double md_dt, md_tau;
 } orc_config;
 
 /* derived per-state constants */
@@ -467,6 +473,9 @@ typedef struct {
      * [n_max+1][n_max][3]; updated at every sample point, walkers in index order,
      * replaced only by a strictly lower energy */
     double *min_e, *min_xyz;
+    /* molecular dynamics: velocities [S][n_max][3] and the temperature they were
+     * drawn or last thermalised at, per walker (0: not initialised) */
+    double *vel, *tv;
 } orc_walkers;
 
 /* Metropolis decision on x = ln(acceptance ratio): accept when x >= 0, else
@@ -714,6 +723,155 @@ static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Molecular dynamics for the canonical part of the REGC step               */
+/* ------------------------------------------------------------------------- */
+/* Standard normals by Box-Muller from two open uniforms:
+ * sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2). */
+static void box_muller(uint32_t w1, uint32_t w2, double *z0, double *z1)
+{
+    const double r = sqrt(-2.0 * log(u32_open(w1)));
+    const double a = 6.283185307179586 * u32_open(w2);
+    *z0 = r * cos(a);
+    *z1 = r * sin(a);
+}
+
+/* three normals of Philox block (t, q, walker, tag): words (0,1) and (2,3) */
+static void normals3(const orc_config *c, uint32_t t, uint32_t q, uint32_t wid, uint32_t tag, double z[3])
+{
+    uint32_t R[4];
+    double unused;
+    philox_words(c->seed, t, q, wid, tag, R);
+    box_muller(R[0], R[1], &z[0], &z[1]);
+    box_muller(R[2], R[3], &z[2], &unused);
+}
+
+/* Forces (negative gradient of the truncated-shifted LJ energy; the shift does not
+ * act) on every gas particle from the other gas particles and the slab, and the
+ * potential energy E = sum over gas pairs + gas-slab pairs.  Particle i sums its
+ * partners in order: gas j = 0..n-1 (j != i), then the slab atoms in input order. */
+static double md_forces(const orc_config *c, const double *xyz, int n, double *f)
+{
+    const double rc2 = c->rc * c->rc;
+    double e = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double fx = 0.0, fy = 0.0, fz = 0.0, ei = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = min_image(xyz[3 * i] - xyz[3 * j], c->lx);
+            const double dy = min_image(xyz[3 * i + 1] - xyz[3 * j + 1], c->ly);
+            const double dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rc2) continue;
+            const double s2 = (c->sig_gg * c->sig_gg) / r2, s6 = s2 * s2 * s2;
+            const double g = 24.0 * c->eps_gg * (2.0 * s6 * s6 - s6) / r2;     /* -phi'(r)/r */
+            fx += g * dx; fy += g * dy; fz += g * dz;
+            ei += 0.5 * orc_lj(r2, c->eps_gg, c->sig_gg, c->rc, c->shifted);
+        }
+        for (int a = 0; a < c->n_slab; ++a) {
+            const double *sa = c->slab + 3 * a;
+            const double dx = min_image(xyz[3 * i] - sa[0], c->lx);
+            const double dy = min_image(xyz[3 * i + 1] - sa[1], c->ly);
+            const double dz = xyz[3 * i + 2] - sa[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rc2) continue;
+            const double s2 = (c->sig_gs * c->sig_gs) / r2, s6 = s2 * s2 * s2;
+            const double g = 24.0 * c->eps_gs * (2.0 * s6 * s6 - s6) / r2;
+            fx += g * dx; fy += g * dy; fz += g * dz;
+            ei += orc_lj(r2, c->eps_gs, c->sig_gs, c->rc, c->shifted);
+        }
+        f[3 * i] = fx; f[3 * i + 1] = fy; f[3 * i + 2] = fz;
+        e += ei;
+    }
+    return e;
+}
+
+double orc_md_forces(const orc_config *c, const double *xyz, int n, double *f) { return md_forces(c, xyz, n, f); }
+
+/* Stochastic velocity rescaling (Bussi, Donadio, Parrinello, J. Chem. Phys. 126,
+ * 014101 (2007)): the kinetic energy K of Nf = 3N degrees of freedom is moved to
+ *   K' = c K + (1 - c) Kbar (R1^2 + S)/Nf + 2 sqrt(c (1 - c) K Kbar / Nf) R1,
+ * c = exp(-dt/tau), Kbar = Nf kT / 2, R1 a standard normal, S the sum of Nf - 1
+ * squared standard normals; velocities scale by sqrt(K'/K).  R1: word pair (0,1)
+ * of Philox block (t, q, walker, 2); S: the normals of blocks (t, q, walker, 16 + b),
+ * four per block (Box-Muller on word pairs (0,1), (2,3)), the first Nf - 1 of them. */
+static void md_thermostat(const orc_config *c, double *v, int n, double T, uint32_t t, uint32_t q, uint32_t wid)
+{
+    const int nf = 3 * n;
+    double K = 0.0;
+    for (int k = 0; k < nf; ++k) K += 0.5 * v[k] * v[k];
+    if (!(K > 0.0)) return;
+    const double Kbar = 0.5 * nf * T;
+    const double cc = exp(-c->md_dt / c->md_tau);
+    uint32_t R[4];
+    double r1, unused;
+    philox_words(c->seed, t, q, wid, 2u, R);
+    box_muller(R[0], R[1], &r1, &unused);
+    double S = 0.0;
+    for (int b = 0; 4 * b < nf - 1; ++b) {
+        double z[4];
+        philox_words(c->seed, t, q, wid, 16u + (uint32_t)b, R);
+        box_muller(R[0], R[1], &z[0], &z[1]);
+        box_muller(R[2], R[3], &z[2], &z[3]);
+        for (int k = 0; k < 4 && 4 * b + k < nf - 1; ++k) S += z[k] * z[k];
+    }
+    const double K2 = cc * K + (1.0 - cc) * Kbar * (r1 * r1 + S) / nf + 2.0 * sqrt(cc * (1.0 - cc) * K * Kbar / nf) * r1;
+    const double alpha = sqrt(K2 / K);
+    for (int k = 0; k < nf; ++k) v[k] *= alpha;
+}
+
+/* md_steps velocity-Verlet steps of walker w in REGC step q (forces at the start
+ * recomputed, positions wrapped in x, y and reflected at the walls in z); the
+ * running energy becomes the potential energy of the final configuration. */
+static void md_run(const orc_config *c, const orc_statec *sc, orc_walkers *W, int w, int64_t q)
+{
+    const int n = W->n[w];
+    if (n == 0) return;
+    const double T = 1.0 / sc[W->label[w]].beta, dt = c->md_dt;
+    const uint32_t wid = (uint32_t)(w + c->walker_offset);
+    double *x = W->xyz + (int64_t)w * c->n_max * 3, *v = W->vel + (int64_t)w * c->n_max * 3;
+    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double e = md_forces(c, x, n, f);
+    for (int st = 0; st < c->md_steps; ++st) {
+        for (int k = 0; k < 3 * n; ++k) v[k] += 0.5 * dt * f[k];
+        for (int i = 0; i < n; ++i) {
+            double *p = x + 3 * i, *u = v + 3 * i;
+            p[0] += dt * u[0]; p[1] += dt * u[1]; p[2] += dt * u[2];
+            if (p[0] < 0.0) p[0] += c->lx; else if (p[0] >= c->lx) p[0] -= c->lx;
+            if (p[1] < 0.0) p[1] += c->ly; else if (p[1] >= c->ly) p[1] -= c->ly;
+            if (p[2] < c->zlo) { p[2] = 2.0 * c->zlo - p[2]; u[2] = -u[2]; }
+            else if (p[2] > c->zhi) { p[2] = 2.0 * c->zhi - p[2]; u[2] = -u[2]; }
+        }
+        e = md_forces(c, x, n, f);
+        for (int k = 0; k < 3 * n; ++k) v[k] += 0.5 * dt * f[k];
+        if (c->md_tau > 0.0) md_thermostat(c, v, n, T, (uint32_t)(1 + st), (uint32_t)q, wid);
+    }
+    W->e[w] = e;
+    free(f);
+}
+
+/* Before the exchange attempt of step q: velocities of a walker not initialised
+ * are drawn from the Maxwell-Boltzmann law at its state's T (particle i: normals of
+ * block (0x80000000 + i, q, walker, 4)); a walker whose state T changed since (an
+ * exchange) has its velocities scaled by sqrt(T_new / T_old). */
+static void md_prepare(const orc_config *c, const orc_statec *sc, orc_walkers *W, int w, int64_t q)
+{
+    const double T = 1.0 / sc[W->label[w]].beta;
+    const uint32_t wid = (uint32_t)(w + c->walker_offset);
+    double *v = W->vel + (int64_t)w * c->n_max * 3;
+    if (W->tv[w] == 0.0) {
+        for (int i = 0; i < W->n[w]; ++i) {
+            double z[3];
+            normals3(c, 0x80000000u + (uint32_t)i, (uint32_t)q, wid, 4u, z);
+            for (int k = 0; k < 3; ++k) v[3 * i + k] = sqrt(T) * z[k];
+        }
+    } else if (W->tv[w] != T) {
+        const double s = sqrt(T / W->tv[w]);
+        for (int k = 0; k < 3 * W->n[w]; ++k) v[k] *= s;
+    }
+    W->tv[w] = T;
+}
+
+/* ------------------------------------------------------------------------- */
 /* The paper's REGC step (Sec. II.A, Sec. III.A)                             */
 /* ------------------------------------------------------------------------- */
 /* Step q: a coin from Philox (0, q, 0xFFFFFFFF - class, 6), open uniform of word 0,
@@ -745,11 +903,33 @@ static int run_paper_schedule(const orc_config *c, const orc_statec *sc, const d
             if (bits) memset(bits, 0, sizeof(uint32_t) * words);
             if (mrow)
                 for (int t = 0; t < Kmax; ++t) mrow[t] = INFINITY;
+            const int md = c->md_steps > 0;
+            if (md) md_prepare(c, sc, W, w, q);
+            const int n_before = W->n[w];
             if (gc && trial(c, sc, lnk, lnv, net, W, w, q, 0, mrow, -2) && bits) bits[0] |= 1u;
-            const int T = 1 + c->mc_cycles * W->n[w];
-            for (int t = 1; t < T; ++t) {
-                int acc = trial(c, sc, lnk, lnv, net, W, w, q, t, mrow ? mrow + t : NULL, 0);
-                if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
+            if (md) {
+                /* the inserted particle gets Maxwell-Boltzmann velocities (block (0, q,
+                 * walker, 3)); the removed slot takes the last particle's velocity */
+                double *v = W->vel + (int64_t)w * c->n_max * 3;
+                const uint32_t wid = (uint32_t)(w + c->walker_offset);
+                if (W->n[w] > n_before) {
+                    double z[3];
+                    normals3(c, 0u, (uint32_t)q, wid, 3u, z);
+                    const double T = 1.0 / sc[W->label[w]].beta;
+                    for (int k = 0; k < 3; ++k) v[3 * n_before + k] = sqrt(T) * z[k];
+                } else if (W->n[w] < n_before) {
+                    uint32_t A[4];
+                    philox_words(c->seed, 0u, (uint32_t)q, wid, 0u, A);
+                    const int i = (int)(((uint64_t)A[1] * (uint64_t)n_before) >> 32);
+                    if (i != n_before - 1) memcpy(v + 3 * i, v + 3 * (n_before - 1), 3 * sizeof(double));
+                }
+                md_run(c, sc, W, w, q);
+            } else {
+                const int T = 1 + c->mc_cycles * W->n[w];
+                for (int t = 1; t < T; ++t) {
+                    int acc = trial(c, sc, lnk, lnv, net, W, w, q, t, mrow ? mrow + t : NULL, 0);
+                    if (bits && acc) bits[t >> 5] |= 1u << (t & 31);
+                }
             }
             if (trace_n) trace_n[(int64_t)it * S + w] = W->n[w];
         }

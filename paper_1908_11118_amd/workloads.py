@@ -100,6 +100,12 @@ class Workload:
     schedule: int = 0
     x0: float = 0.99
     mc_cycles: int = 10
+    # schedule 1 with md_steps > 0: the canonical part is md_steps velocity-Verlet steps
+    # of md_dt (unit mass) under the stochastic velocity-rescaling thermostat (time md_tau;
+    # 0: none) instead of the MC cycles
+    md_steps: int = 0
+    md_dt: float = 0.005
+    md_tau: float = 0.1
 
     @property
     def n_states(self) -> int:
@@ -173,6 +179,12 @@ def paper_schedule(w: Workload, x0: float = 0.99, mc_cycles: int = 10, sample_ev
     """The workload run with the paper's REGC step (Sec. II.A): sample_every counts
     REGC steps (the paper records after every 100 steps, Sec. III.A)."""
     return w.replace(schedule=1, x0=x0, mc_cycles=mc_cycles, sample_every=sample_every)
+
+
+def paper_schedule_md(w: Workload, x0: float = 0.99, md_steps: int = 10, md_dt: float = 0.005,
+                      md_tau: float = 0.1, sample_every: int = 100) -> Workload:
+    """The paper's REGC step with molecular dynamics as the canonical part (REGCMD)."""
+    return w.replace(schedule=1, x0=x0, md_steps=md_steps, md_dt=md_dt, md_tau=md_tau, sample_every=sample_every)
 
 
 def random_configuration(rng: np.random.Generator, w: Workload, n: int, min_dist: float = 0.85,
