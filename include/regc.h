@@ -139,7 +139,19 @@ typedef struct {
  *                  trial 0).  p_disp, p_ins, trials_per_sweep and swap_every are not
  *                  used.  Single-class contexts, no graph replay, no learned proposal.
  *  x0              probability of the particle-exchange attempt (schedule 1).
- *  mc_cycles       MC cycles after each attempt (schedule 1). */
+ *  mc_cycles       MC cycles after each attempt (schedule 1).
+ *  md_steps        schedule 1: > 0 replaces the MC cycles by md_steps velocity-Verlet
+ *                  steps (unit mass) of every walker: forces of the truncated-shifted
+ *                  LJ energy, positions wrapped in x, y and reflected at the z walls,
+ *                  then the stochastic velocity-rescaling thermostat (Bussi, Donadio,
+ *                  Parrinello 2007; R1 from Philox block (1 + s, step, walker, 2), the
+ *                  chi-square part from blocks (1 + s, step, walker, 16 + b)).  Missing
+ *                  velocities (new context, regc_set_walkers, regc_restore) are drawn
+ *                  from the Maxwell-Boltzmann law at the state's T at the next step
+ *                  (particle i: block (2^31 + i, step, walker, 4)); an inserted
+ *                  particle's from block (0, step, walker, 3); after an exchange the
+ *                  velocities are scaled by sqrt(T_new / T_old).  Normals by Box-Muller.
+ *  md_dt, md_tau   time step and thermostat time constant (0: no thermostat). */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -157,6 +169,8 @@ typedef struct {
     int schedule;
     double x0;
     int mc_cycles;
+    int md_steps;
+    double md_dt, md_tau;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

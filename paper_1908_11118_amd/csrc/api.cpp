@@ -71,6 +71,9 @@ struct regc_ctx {
     bool timing = false;
     std::vector<TimingPair> ev_sweep, ev_swap;
 
+    // molecular dynamics (paper schedule with md_steps > 0)
+    DevBuf<double> vel_d, tv_d;
+
     // structural observables recorded with the samples
     bool obs_on = false;
     regc_observables obs_spec{};
@@ -146,6 +149,9 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->schedule = 0;
     o->x0 = 0.99;
     o->mc_cycles = 10;
+    o->md_steps = 0;
+    o->md_dt = 0.005;
+    o->md_tau = 0.1;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -180,6 +186,8 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
         REGC_CHECK(o->x0 >= 0.0 && o->x0 <= 1.0, REGC_EINVAL, "x0 must lie in [0, 1]");
         REGC_CHECK(o->mc_cycles >= 0 && o->mc_cycles <= 1000, REGC_EINVAL, "mc_cycles must be 0..1000");
         REGC_CHECK(o->graph_intervals == 0, REGC_EUNSUPPORTED, "the paper schedule has no graph replay");
+        REGC_CHECK(o->md_steps >= 0 && o->md_steps <= 100000 && o->md_dt > 0 && o->md_tau >= 0, REGC_EINVAL,
+                   "bad molecular-dynamics parameters");
     }
     return REGC_OK;
 }
@@ -347,6 +355,11 @@ static int ctx_alloc_and_init(regc_ctx *c)
     c->split = split;
     c->cull = cull;
     c->smem = smem_for(wpb);
+    if (o.schedule == 1 && o.md_steps > 0) {
+        c->smem = lds_round(c->smem) + md_lds_bytes(nmax, wpb);
+        REGC_CHECK(c->smem <= (size_t)lds_max, REGC_EUNSUPPORTED, "molecular dynamics needs %zu bytes of LDS",
+                   c->smem);
+    }
     std::vector<int> bcls, bw0, bnw;
     c->walker_class.assign(W, 0);
     // blocks of the costliest classes first (largest n_max + slab candidates), so the
@@ -405,6 +418,11 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
         (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)) || (rc = c->clock_d.alloc(1)))
         return rc;
+    if (o.schedule == 1 && o.md_steps > 0) {
+        if ((rc = c->vel_d.alloc((size_t)W * nmax * 3)) || (rc = c->tv_d.alloc(W))) return rc;
+        REGC_HIP(hipMemset(c->vel_d.p, 0, sizeof(double) * (size_t)W * nmax * 3));
+        REGC_HIP(hipMemset(c->tv_d.p, 0, sizeof(double) * W));
+    }
     if ((rc = upload(c->cls_d.p, cd.data(), sizeof(ClassDev) * n_class)) ||
         (rc = upload(c->block_class_d.p, bcls.data(), sizeof(int) * bcls.size())) ||
         (rc = upload(c->block_w0_d.p, bw0.data(), sizeof(int) * bw0.size())) ||
@@ -562,7 +580,14 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
     if (c->opts.schedule == 1) {
-        PaperArgs pa{c->opts.x0, c->opts.mc_cycles};
+        PaperArgs pa{};
+        pa.x0 = c->opts.x0;
+        pa.mc_cycles = c->opts.mc_cycles;
+        pa.md_steps = c->opts.md_steps;
+        pa.md_dt = c->opts.md_dt;
+        pa.md_tau = c->opts.md_tau;
+        pa.vel = c->vel_d.p;
+        pa.tv = c->tv_d.p;
         if (c->opts.precision == REGC_FP64)
             REGC_HIP(launch_paper_f64(a, pa, c->nblocks, c->wpb, c->smem, stream));
         else
@@ -1069,6 +1094,7 @@ extern "C" int regc_set_walkers(regc_ctx *c, const int32_t *n, const double *xyz
     }
     int rc = run_energy(c, c->e_d.p);
     if (rc) return rc;
+    if (c->tv_d.p) REGC_HIP(hipMemsetAsync(c->tv_d.p, 0, sizeof(double) * c->W, c->stream));   // fresh velocities
     REGC_HIP(hipStreamSynchronize(c->stream));
     return REGC_OK;
 }
@@ -1277,6 +1303,7 @@ extern "C" int regc_restore(regc_ctx *c, const void *buf, size_t size)
     c->trace_sweep0 = c->sweep;
     invalidate_graph(c);
     REGC_HIP(hipMemset(c->hist_d.p, 0, sizeof(unsigned long long) * W * (c->nmax_all + 1)));
+    if (c->tv_d.p) REGC_HIP(hipMemset(c->tv_d.p, 0, sizeof(double) * W));   // velocities are not checkpointed
     return REGC_OK;
 }
 

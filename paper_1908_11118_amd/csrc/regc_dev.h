@@ -111,7 +111,19 @@ struct MinArgs {
 struct PaperArgs {
     double x0;                   // probability of the particle-exchange attempt
     int mc_cycles;               // MC cycles of N displacements after each attempt
+    // molecular dynamics as the canonical part (md_steps > 0 replaces the MC cycles)
+    int md_steps;
+    double md_dt, md_tau;        // time step (unit mass), thermostat time (0: none)
+    double *vel;                 // [W][xyz_stride][3] velocities
+    double *tv;                  // [W] temperature of the velocities (0: not drawn yet)
 };
+
+// LDS of the MD part after the sweep layout: per walker velocities and forces
+// (double [gas_stride][3] each).
+__host__ __device__ inline size_t md_lds_bytes(int gas_stride, int walkers)
+{
+    return (size_t)walkers * gas_stride * 48;
+}
 
 struct SwapArgs {
     const ClassDev *cls;

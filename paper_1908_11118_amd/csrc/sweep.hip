@@ -304,6 +304,132 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     }
 }
 
+// ---- molecular dynamics for the canonical part of the REGC step ----
+// Standard normals by Box-Muller: sqrt(-2 ln u1) (cos, sin)(2 pi u2), u open uniforms.
+__device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double &z0, double &z1)
+{
+    const double r = sqrt(-2.0 * log(uniform_open(w1)));
+    const double t = 6.283185307179586 * uniform_open(w2);
+    z0 = r * cos(t);
+    z1 = r * sin(t);
+}
+
+__device__ __forceinline__ double md_min_image(double d, double box)
+{
+    return d > 0.5 * box ? d - box : (d < -0.5 * box ? d + box : d);
+}
+
+// Forces on the walker's particles (lane-strided over particles; each particle sums
+// its gas partners in index order, then every packed slab entry) and the potential
+// energy (FP64, wave-uniform).  Truncated-shifted LJ; the shift does not act on forces.
+__device__ double md_forces(const Real4 *gas, int n, const SlabView &sv, const PotDev &pot, const Box &b, double *f,
+                            int lane)
+{
+    double e = 0.0;
+    if (!pot.ideal) {
+        const double lx = (double)b.lx, ly = (double)b.ly;
+        for (int i = lane; i < n; i += kWave) {
+            const double xi = (double)gas[i].x, yi = (double)gas[i].y, zi = (double)gas[i].z;
+            double fx = 0.0, fy = 0.0, fz = 0.0, ei = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const double dx = md_min_image(xi - (double)gas[j].x, lx);
+                const double dy = md_min_image(yi - (double)gas[j].y, ly);
+                const double dz = zi - (double)gas[j].z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= pot.rc2) continue;
+                const double s2 = pot.sig2_gg / r2, s6 = s2 * s2 * s2;
+                const double g = 6.0 * pot.eps4_gg * (2.0 * s6 * s6 - s6) / r2;
+                fx += g * dx; fy += g * dy; fz += g * dz;
+                ei += 0.5 * (pot.eps4_gg * (s6 * s6 - s6) - pot.shift_gg);
+            }
+            const int ns = sv.bins ? sv.ncx * sv.ncy * sv.cap : sv.len;
+            for (int k = 0; k < ns; ++k) {
+                const Real4 sa = sv.atoms[k];
+                const double dx = md_min_image(xi - (double)sa.x, lx);
+                const double dy = md_min_image(yi - (double)sa.y, ly);
+                const double dz = zi - (double)sa.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= pot.rc2) continue;
+                const double s2 = pot.sig2_gs / r2, s6 = s2 * s2 * s2;
+                const double g = 6.0 * pot.eps4_gs * (2.0 * s6 * s6 - s6) / r2;
+                fx += g * dx; fy += g * dy; fz += g * dz;
+                ei += pot.eps4_gs * (s6 * s6 - s6) - pot.shift_gs;
+            }
+            f[3 * i] = fx; f[3 * i + 1] = fy; f[3 * i + 2] = fz;
+            e += ei;
+        }
+    } else {
+        for (int i = lane; i < n; i += kWave) f[3 * i] = f[3 * i + 1] = f[3 * i + 2] = 0.0;
+    }
+    wave_sync();
+    return wave_sum(e);
+}
+
+// md_steps velocity-Verlet steps with the stochastic velocity-rescaling thermostat
+// (Bussi, Donadio, Parrinello 2007): K' = c K + (1-c) Kbar (R1^2 + S)/Nf
+// + 2 sqrt(c (1-c) K Kbar / Nf) R1 with c = exp(-dt/tau), Kbar = Nf T / 2, Nf = 3N,
+// R1 from Philox block (1 + step, q, walker, 2) words (0,1), S the squares of the
+// first Nf - 1 normals of blocks (1 + step, q, walker, 16 + b) (four per block).
+// Returns the potential energy of the final configuration.
+__device__ double md_run(Real4 *gas, double *v, double *f, int n, double T, const SlabView &sv, const PotDev &pot,
+                         const Box &b, double zlo, double zhi, const PaperArgs &pa, int64_t q, int w, uint32_t k0,
+                         uint32_t k1, int lane)
+{
+    const double dt = pa.md_dt, lx = (double)b.lx, ly = (double)b.ly;
+    double e = md_forces(gas, n, sv, pot, b, f, lane);
+    for (int st = 0; st < pa.md_steps; ++st) {
+        for (int i = lane; i < n; i += kWave) {
+            double *u = v + 3 * i;
+            const double *g = f + 3 * i;
+            u[0] += 0.5 * dt * g[0]; u[1] += 0.5 * dt * g[1]; u[2] += 0.5 * dt * g[2];
+            double px = (double)gas[i].x + dt * u[0], py = (double)gas[i].y + dt * u[1], pz = (double)gas[i].z + dt * u[2];
+            if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
+            if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
+            if (pz < zlo) { pz = 2.0 * zlo - pz; u[2] = -u[2]; }
+            else if (pz > zhi) { pz = 2.0 * zhi - pz; u[2] = -u[2]; }
+            Real4 nv; nv.x = (Real)px; nv.y = (Real)py; nv.z = (Real)pz; nv.w = 0;
+            gas[i] = nv;
+        }
+        wave_sync();
+        e = md_forces(gas, n, sv, pot, b, f, lane);
+        double kin = 0.0;
+        for (int i = lane; i < n; i += kWave) {
+            double *u = v + 3 * i;
+            const double *g = f + 3 * i;
+            u[0] += 0.5 * dt * g[0]; u[1] += 0.5 * dt * g[1]; u[2] += 0.5 * dt * g[2];
+            kin += 0.5 * u[0] * u[0] + 0.5 * u[1] * u[1] + 0.5 * u[2] * u[2];
+        }
+        if (pa.md_tau > 0.0) {
+            const double K = wave_sum(kin);
+            if (K > 0.0) {
+                const int nf = 3 * n;
+                const uint4 R = philox4x32_10(make_uint4((uint32_t)(1 + st), (uint32_t)q, (uint32_t)w, 2u), k0, k1);
+                double r1, unused;
+                box_muller(R.x, R.y, r1, unused);
+                double s = 0.0;
+                for (int blk = lane; 4 * blk < nf - 1; blk += kWave) {
+                    const uint4 Q = philox4x32_10(make_uint4((uint32_t)(1 + st), (uint32_t)q, (uint32_t)w,
+                                                             16u + (uint32_t)blk), k0, k1);
+                    double z[4];
+                    box_muller(Q.x, Q.y, z[0], z[1]);
+                    box_muller(Q.z, Q.w, z[2], z[3]);
+                    for (int k = 0; k < 4 && 4 * blk + k < nf - 1; ++k) s += z[k] * z[k];
+                }
+                const double S = wave_sum(s);
+                const double Kbar = 0.5 * nf * T;
+                const double c = exp(-dt / pa.md_tau);
+                const double K2 = c * K + (1.0 - c) * Kbar * (r1 * r1 + S) / nf +
+                                  2.0 * sqrt(c * (1.0 - c) * K * Kbar / nf) * r1;
+                const double alpha = sqrt(K2 / K);
+                for (int k = lane; k < nf; k += kWave) v[k] *= alpha;
+            }
+        }
+        wave_sync();
+    }
+    return e;
+}
+
 // The paper's REGC step (Sec. II.A; Sec. III.A for the LJ run): for each step the
 // coin of Philox block (0, step, 0xFFFFFFFF - class, 6) -- open uniform of word 0
 // below x0 -- selects one particle-exchange attempt per walker (trial 0: removal
@@ -327,6 +453,9 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
     int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
     double *lnk = reinterpret_cast<double *>(smem + L.lnk);
     Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)wave * a.gas_stride;
+    const bool use_md = pa.md_steps > 0;
+    double *mdv = reinterpret_cast<double *>(smem + lds_round(L.total)) + (size_t)wave * a.gas_stride * 6;
+    double *mdf = mdv + (size_t)a.gas_stride * 3;
 
     const int slab_len = C.slab_len;
     for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
@@ -346,6 +475,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
     if (wave >= nw) return;
 
     const int w = a.block_w0[blk] + wave;
+    double tv = use_md ? pa.tv[w] : 0.0;
     const int n_max = C.n_max;
     int n = a.n[w];
     double e = a.e[w];
@@ -361,6 +491,8 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
             v.x = (Real)src[3 * k]; v.y = (Real)src[3 * k + 1]; v.z = (Real)src[3 * k + 2]; v.w = 0;
             gas[k] = v;
         }
+        if (use_md)
+            for (int k = lane; k < 3 * n; k += kWave) mdv[k] = pa.vel[(size_t)w * a.xyz_stride * 3 + k];
     }
     wave_sync();
 
@@ -393,7 +525,28 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
                              step >= a.trace_sweep0;
         const uint4 coin = philox4x32_10(make_uint4(0u, (uint32_t)step, 0xFFFFFFFFu, 6u), a.key0, a.key1);
         const bool exchange = uniform_open(coin.x) < pa.x0;
-        int T = 1 + pa.mc_cycles * n;
+        if (use_md) {
+            // velocities: drawn at the state's T when none exist, rescaled after a change of T
+            const double Tw = 1.0 / beta;
+            if (tv == 0.0) {
+                for (int i = lane; i < n; i += kWave) {
+                    const uint4 R = philox4x32_10(make_uint4(0x80000000u + (uint32_t)i, (uint32_t)step, (uint32_t)w, 4u),
+                                                  a.key0, a.key1);
+                    double z0, z1, z2, z3;
+                    box_muller(R.x, R.y, z0, z1);
+                    box_muller(R.z, R.w, z2, z3);
+                    mdv[3 * i] = sqrt(Tw) * z0; mdv[3 * i + 1] = sqrt(Tw) * z1; mdv[3 * i + 2] = sqrt(Tw) * z2;
+                }
+            } else if (tv != Tw) {
+                const double sc = sqrt(Tw / tv);
+                for (int k = lane; k < 3 * n; k += kWave) mdv[k] *= sc;
+            }
+            tv = Tw;
+            wave_sync();
+        }
+        const int n_before = n;
+        int i_removed = -1;
+        int T = use_md ? 1 : 1 + pa.mc_cycles * n;
         for (int t0 = 0; t0 < T; t0 += 32) {
             const uint4 R = philox4x32_10(
                 make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)step, (uint32_t)w, (uint32_t)(lane & 1)),
@@ -480,6 +633,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
                                 n += 1;
                             } else {
                                 if (lane == 0 && i != n - 1) gas[i] = gas[n - 1];
+                                i_removed = i;
                                 n -= 1;
                             }
                         }
@@ -489,10 +643,27 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
                     bits |= 1u << tt;
                     wave_sync();
                 }
-                if (t == 0) T = 1 + pa.mc_cycles * n;      // N after the exchange attempt
+                if (t == 0 && !use_md) T = 1 + pa.mc_cycles * n;      // N after the exchange attempt
             }
             if (tracing && lane == 0)
                 a.trace_bits[((size_t)(step - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
+        }
+        if (use_md) {
+            // the inserted particle's velocity (Philox block (0, step, walker, 3)); the
+            // removed slot takes the last particle's; then the MD run
+            const double Tw = 1.0 / beta;
+            if (n > n_before && lane == 0) {
+                const uint4 R = philox4x32_10(make_uint4(0u, (uint32_t)step, (uint32_t)w, 3u), a.key0, a.key1);
+                double z0, z1, z2, z3;
+                box_muller(R.x, R.y, z0, z1);
+                box_muller(R.z, R.w, z2, z3);
+                mdv[3 * n_before] = sqrt(Tw) * z0; mdv[3 * n_before + 1] = sqrt(Tw) * z1;
+                mdv[3 * n_before + 2] = sqrt(Tw) * z2;
+            } else if (n < n_before && lane == 0 && i_removed != n_before - 1) {
+                for (int k = 0; k < 3; ++k) mdv[3 * i_removed + k] = mdv[3 * (n_before - 1) + k];
+            }
+            wave_sync();
+            if (n > 0) e = md_run(gas, mdv, mdf, n, Tw, sv, a.pot, b, zlo, zhi, pa, step, w, a.key0, a.key1, lane);
         }
         if (lane == 0) {
             if (tracing) {
@@ -517,6 +688,10 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
         for (int k = lane; k < n; k += kWave) {
             const Real4 v = gas[k];
             dst[3 * k] = (double)v.x; dst[3 * k + 1] = (double)v.y; dst[3 * k + 2] = (double)v.z;
+        }
+        if (use_md) {
+            for (int k = lane; k < 3 * n; k += kWave) pa.vel[(size_t)w * a.xyz_stride * 3 + k] = mdv[k];
+            if (lane == 0) pa.tv[w] = tv;
         }
     }
     if (lane == 0 && a.pairs) atomicAdd(a.pairs, (unsigned long long)cand);

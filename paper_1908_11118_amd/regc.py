@@ -75,7 +75,8 @@ class Opts(C.Structure):
                 ("sample_every", C.c_int), ("swap_scheme", C.c_int), ("sample_capacity", C.c_int64),
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
                 ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
-                ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int)]
+                ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
+                ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double)]
 
 
 _lib = None
@@ -219,6 +220,9 @@ class Regc:
         o.schedule = int(getattr(w0, "schedule", 0))
         o.x0 = float(getattr(w0, "x0", 0.99))
         o.mc_cycles = int(getattr(w0, "mc_cycles", 10))
+        o.md_steps = int(getattr(w0, "md_steps", 0))
+        o.md_dt = float(getattr(w0, "md_dt", 0.005))
+        o.md_tau = float(getattr(w0, "md_tau", 0.1))
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:

@@ -461,3 +461,64 @@ def test_fp64_minima_per_class_of_a_batch():
         assert np.allclose(e_min[seen], ref.min_e[seen], rtol=1e-10, atol=1e-9), c
         for N in np.nonzero(seen)[0]:
             assert np.array_equal(xyz[N, :N], ref.min_xyz[N, :N]), (c, N)
+
+
+# ---------------------------------------------------------------------------
+# Molecular dynamics as the canonical part of the REGC step
+# ---------------------------------------------------------------------------
+def _md_trajectory(w, steps, atol=1e-9):
+    _say(f"[md] {w.name} steps={steps}")
+    ref = oracle.Chain(w)
+    r = ref.run(steps, trace=True)
+    with regc.Regc(w, precision=regc.FP64, trace_capacity=steps,
+                   sample_capacity=(steps // max(w.sample_every, 1) + 1) * w.n_states) as g:
+        g.run(steps)
+        bits, nps = g.trace(steps)
+        wk = g.walkers()
+        st = g.stats()
+        smp = g.samples()
+    assert _first_divergence(bits, r["bits"], nps, r["trace_n"]) is None
+    assert np.array_equal(wk["n"], ref.n) and np.array_equal(wk["label"], ref.label)
+    assert np.array_equal(st["stats"], ref.stats) and np.array_equal(st["swap_acc"], ref.swap_acc)
+    for k in range(ref.S):
+        assert np.allclose(wk["xyz"][k, : ref.n[k]], ref.xyz[k, : ref.n[k]], rtol=0, atol=atol), k
+    assert np.allclose(wk["e"], ref.e, rtol=1e-9, atol=1e-9)
+    assert np.array_equal(smp["n"], r["n"])
+    assert np.allclose(smp["e"], r["e"], rtol=1e-9, atol=1e-9)
+    return ref
+
+
+def test_fp64_md_trajectories_config1():
+    """64 replicas, x0 = 0.9, 10 velocity-Verlet steps with the thermostat per REGC
+    step: identical exchange decisions and N, positions within 1e-9 after 300 MD steps."""
+    ref = _md_trajectory(W.paper_schedule_md(W.config1(), x0=0.9, md_steps=10, sample_every=5), 30)
+    assert ref.n.sum() > 0
+
+
+def test_fp64_md_variants():
+    # no thermostat (NVE between exchange attempts), a binned slab, frequent exchanges
+    w = W.paper_schedule_md(W.config3_classes()[0].replace(t=W.linear_grid(0.6, 1.8, 3),
+                                                          mu=W.linear_grid(-4.0, -2.5, 3), n_max=60),
+                            x0=0.7, md_steps=4, md_dt=0.004, md_tau=0.0, sample_every=2)
+    _md_trajectory(w, 40)
+    _md_trajectory(W.paper_schedule_md(W.ideal_gas(n_t=2, n_mu=2, n_max=30), x0=0.8, md_steps=3, sample_every=1), 60)
+
+
+def test_fp32_md_lj_mean_n_matches_the_monte_carlo_oracle():
+    w = W.small_lj(n_t=2, n_mu=2, n_max=14, mu=(-4.5, -3.0)).replace(sample_every=1)
+    ref = oracle.Chain(w)
+    ref.run(1000)
+    r = ref.run(20000)
+    wm = W.paper_schedule_md(w, x0=0.7, md_steps=5, md_dt=0.005, md_tau=0.05, sample_every=1)
+    steps = 30000
+    with regc.Regc(wm, precision=regc.FP32PAIR, sample_capacity=steps * w.n_states) as g:
+        g.run(2000)
+        g.clear_samples()
+        g.run(steps)
+        smp = g.samples()
+    na, _ = per_state_series(r, w.n_states)
+    nb, _ = per_state_series(smp, w.n_states)
+    for s in range(w.n_states):
+        ma, sa = batch_means(na[:, s])
+        mb, sb = batch_means(nb[:, s])
+        assert abs(ma - mb) < 4 * math.hypot(sa, sb) + 1e-9, (s, ma, mb, sa, sb)
