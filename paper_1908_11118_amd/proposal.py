@@ -117,6 +117,37 @@ def reference(workload, sweeps: int = 100000, burnin: int = 2000, seed: int = 4,
     return mean_se(_per_state(np.concatenate(parts_s), np.concatenate(parts_n), S))
 
 
+class _Series:
+    """Per-state N series held as running prefix sums: batch-means statistics of all
+    samples so far in O(states x batches) per check."""
+
+    def __init__(self, S: int, n_batches: int = 20):
+        self.S, self.nb = S, n_batches
+        self.cs = np.zeros((1024, S))       # cs[k] = sum of the first k records
+        self.L = 0
+
+    def add(self, state, n):
+        rec = np.asarray(n, dtype=np.float64).reshape(-1, self.S)
+        st = np.asarray(state).reshape(-1, self.S)
+        by_state = np.zeros_like(rec)
+        np.put_along_axis(by_state, st, rec, axis=1)
+        k = rec.shape[0]
+        while self.L + k + 1 > self.cs.shape[0]:
+            self.cs = np.concatenate([self.cs, np.zeros_like(self.cs)])
+        self.cs[self.L + 1:self.L + k + 1] = self.cs[self.L] + np.cumsum(by_state, axis=0)
+        self.L += k
+
+    def mean_se(self):
+        L, nb = self.L, self.nb
+        m = self.cs[L] / max(L, 1)
+        b = L // nb
+        if b < 1:
+            return m, np.full(self.S, np.inf)
+        edges = self.cs[np.arange(nb + 1) * b]
+        bm = (edges[1:] - edges[:-1]) / b
+        return m, bm.std(axis=0, ddof=1) / math.sqrt(nb)
+
+
 def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["regc.Mlp"] = None,
                      alpha: float = 0.0, precision: int = regc.FP32PAIR, chunk: int = 250,
                      max_sweeps: int = 200000, max_seconds: float = 1e9, tau: float = 0.1, frac: float = 0.98,
@@ -124,10 +155,10 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
     """Runs from the checkpoint `blob` (written by equilibrated_state with the same
     seed) until the accuracy target is met or max_sweeps / max_seconds of GPU time
     are spent; returns {"t_acc_s", "sweeps", "reached", "max_se", "frac_within",
-    "chi2", "ins_acc", ...}."""
+    "chi2", "ins_acc", ...}.  (Sweeps are REGC steps for the paper's schedule.)"""
     w = workload.replace(seed=seed, sample_every=1)
     S = w.n_states
-    parts_s, parts_n = [], []
+    series = _Series(S)
     t_gpu = 0.0
     res = {"reached": False}
     with regc.Regc(w, precision=precision, sample_capacity=chunk * S) as g:
@@ -146,9 +177,8 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
             done += chunk
             smp = g.samples()
             g.clear_samples()
-            parts_s.append(smp["state"])
-            parts_n.append(smp["n"])
-            m, se = mean_se(_per_state(np.concatenate(parts_s), np.concatenate(parts_n), S))
+            series.add(smp["state"], smp["n"])
+            m, se = series.mean_se()
             z = (m - ref_mean) / np.sqrt(se ** 2 + ref_se ** 2)
             within = float(np.mean(np.abs(z) <= 3.0))
             chi2 = float(np.mean(z ** 2))
