@@ -107,6 +107,14 @@ def test_fp64_dense_walkers(split, cull):
     assert wk["n"].max() > 100
 
 
+def test_fp64_walkers_beyond_the_register_slots():
+    """N above 128: particles whose coordinates and per-particle energies live in
+    LDS rather than in the two register slots of a lane (one wave per walker)."""
+    w = W.config2(40).replace(t=np.array([0.8, 1.2]), mu=np.array([-2.0, -1.0]), n_max=210, sample_every=4)
+    _, wk = _fp64_trajectory(w, 40)
+    assert wk["n"].max() > 150
+
+
 def test_fp64_edge_cases():
     # N capped at 1, one state, no exchange, K = 1 trial per sweep
     _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=500).replace(swap_every=0), 500)
