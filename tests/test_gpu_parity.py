@@ -107,9 +107,9 @@ def test_fp64_dense_walkers(split, cull):
     assert wk["n"].max() > 100
 
 
-def test_fp64_walkers_beyond_the_register_slots():
-    """N above 128: particles whose coordinates and per-particle energies live in
-    LDS rather than in the two register slots of a lane (one wave per walker)."""
+def test_fp64_walkers_above_two_wave_widths():
+    """N above 128 up to the cap: the gas loop of one wave per walker runs more than
+    one step of two candidates per lane."""
     w = W.config2(40).replace(t=np.array([0.8, 1.2]), mu=np.array([-2.0, -1.0]), n_max=210, sample_every=4)
     _, wk = _fp64_trajectory(w, 40)
     assert wk["n"].max() > 150
