@@ -428,12 +428,20 @@ void regc_mlp_destroy(regc_mlp *mlp);
  * evaluated on the occupancy left after the removal), the Metropolis-Hastings form
  * that keeps Eq. (1) the stationary law for any network.  Displacements are
  * unchanged.  The call copies the network's current parameters (bfloat16) into the
- * context: call it again after training to refresh.  mlp = NULL or alpha = 0
- * restores the plain method.  Single-class contexts only (EUNSUPPORTED for a
- * batch); alpha outside [0, 1] is EINVAL.  With a proposal set, every walker runs
- * in a workgroup of its own (256 threads); the walkers_per_block, split, cull and
+ * context: call it again after training to refresh.  This call sets the same
+ * network and alpha for every class of the context; mlp = NULL or alpha = 0
+ * restores the plain method.  Alpha outside [0, 1] is EINVAL; a context of more
+ * than 8 classes or one run with the paper's REGC step (schedule 1) is
+ * EUNSUPPORTED.  With a proposal set on any class, every walker runs in a
+ * workgroup of its own (256 threads); the walkers_per_block, split, cull and
  * slab-binning options then have no effect. */
 int regc_set_proposal(regc_ctx *ctx, regc_mlp *mlp, double alpha);
+
+/* The same for class cls (0-based, in the order given to regc_create_batch) of a
+ * batch: one network per slab class, whose 16^3 grid spans that class's box.  A
+ * class without a network (never set, mlp = NULL or alpha = 0) inserts uniformly
+ * as in the plain method.  cls out of range is EINVAL. */
+int regc_set_class_proposal(regc_ctx *ctx, int cls, regc_mlp *mlp, double alpha);
 
 /* Training data for the proposal network: writes, asynchronously on the
  * context's stream, the voxel of every particle of every walker into the device

@@ -85,8 +85,9 @@ struct regc_ctx {
     DevBuf<int> minw_d;
     DevBuf<double> mine_d, minxyz_d;
 
-    // learned insertion proposal (alpha > 0: the learned kernel runs the sweeps)
-    double alpha = 0.0;
+    // learned insertion proposal, per class (any alpha > 0: the learned kernel runs the sweeps);
+    // net_w / net_b hold one network per class, allocated at the first proposal
+    std::vector<double> alpha;
     DevBuf<uint16_t> net_w;                 // w1 | w2p | w3p | w4p (bfloat16)
     DevBuf<float> net_b;                    // b1 | b2 | b3 | b4
     DevBuf<unsigned long long> net_ev_d;    // proposal counters [4]
@@ -530,6 +531,17 @@ static int record_event(regc_ctx *c, std::vector<TimingPair> &v, bool start)
     return REGC_OK;
 }
 
+// Weights and biases of one proposal network in the sampler's layout.
+static constexpr size_t kNetWords = 2 * (size_t)kNetNV * kNetH + 2 * (size_t)kNetH * kNetH;
+static constexpr size_t kNetBiases = 3 * (size_t)kNetH + kNetNV;
+
+static bool learned_on(const regc_ctx *c)
+{
+    for (double a : c->alpha)
+        if (a > 0.0) return true;
+    return false;
+}
+
 static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream, bool use_clock)
 {
     SweepArgs a{};
@@ -592,19 +604,24 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
             REGC_HIP(launch_paper_f64(a, pa, c->nblocks, c->wpb, c->smem, stream));
         else
             REGC_HIP(launch_paper_f32(a, pa, c->nblocks, c->wpb, c->smem, stream));
-    } else if (c->alpha > 0.0) {
+    } else if (learned_on(c)) {
         LearnArgs l{};
-        const uint16_t *w = c->net_w.p;
-        const float *bb = c->net_b.p;
-        l.net.w1 = w;
-        l.net.w2 = w + (size_t)kNetNV * kNetH;
-        l.net.w3 = l.net.w2 + (size_t)kNetH * kNetH;
-        l.net.w4 = l.net.w3 + (size_t)kNetH * kNetH;
-        l.net.b1 = bb;
-        l.net.b2 = bb + kNetH;
-        l.net.b3 = bb + 2 * kNetH;
-        l.net.b4 = bb + 3 * kNetH;
-        l.alpha = c->alpha;
+        for (size_t k = 0; k < c->cls.size(); ++k) {
+            l.alpha[k] = c->alpha[k];
+            if (c->alpha[k] == 0.0) continue;
+            const uint16_t *w = c->net_w.p + k * kNetWords;
+            const float *bb = c->net_b.p + k * kNetBiases;
+            NetDev &d = l.net[k];
+            d.w1 = w;
+            d.w2 = w + (size_t)kNetNV * kNetH;
+            d.w3 = d.w2 + (size_t)kNetH * kNetH;
+            d.w4 = d.w3 + (size_t)kNetH * kNetH;
+            d.b1 = bb;
+            d.b2 = bb + kNetH;
+            d.b3 = bb + 2 * kNetH;
+            d.b4 = bb + 3 * kNetH;
+        }
+        l.walker_class = c->walker_class_d.p;
         l.evals = c->net_ev_d.p;
         if (c->opts.precision == REGC_FP64)
             REGC_HIP(launch_learned_f64(a, l, c->learn_smem, stream));
@@ -836,17 +853,23 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
     return REGC_OK;
 }
 
-extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
+// Installs (mlp, alpha) as the insertion proposal of class cls, or of every class
+// when cls < 0; mlp = NULL or alpha = 0 removes it.
+static int set_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
 {
     REGC_CHECK(c, REGC_EINVAL, "null context");
     REGC_CHECK(alpha >= 0.0 && alpha <= 1.0, REGC_EINVAL, "mixture weight %g outside [0, 1]", alpha);
+    REGC_CHECK(cls < (int)c->cls.size(), REGC_EINVAL, "class index %d out of range", cls);
     REGC_HIP(hipStreamSynchronize(c->stream));
     invalidate_graph(c);
+    c->alpha.resize(c->cls.size(), 0.0);
+    const int k0 = cls < 0 ? 0 : cls, k1 = cls < 0 ? (int)c->cls.size() : cls + 1;
     if (!mlp || alpha == 0.0) {
-        c->alpha = 0.0;
+        for (int k = k0; k < k1; ++k) c->alpha[k] = 0.0;
         return REGC_OK;
     }
-    REGC_CHECK(c->cls.size() == 1, REGC_EUNSUPPORTED, "the learned proposal needs a single-class context");
+    REGC_CHECK(c->cls.size() <= (size_t)kMaxLearnClasses, REGC_EUNSUPPORTED,
+               "the learned proposal takes at most %d classes", kMaxLearnClasses);
     REGC_CHECK(c->opts.schedule == 0, REGC_EUNSUPPORTED, "the learned proposal runs with the sweep schedule");
     int dev = 0, lds_max = 0;
     REGC_HIP(hipGetDevice(&dev));
@@ -856,24 +879,37 @@ extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
     REGC_CHECK(smem <= (size_t)lds_max, REGC_EUNSUPPORTED, "a walker needs %zu bytes of LDS, the device allows %d",
                smem, lds_max);
     int rc;
-    const size_t nw = 2 * (size_t)kNetNV * kNetH + 2 * (size_t)kNetH * kNetH, nb = 3 * kNetH + kNetNV;
-    if (!c->net_w.p && (rc = c->net_w.alloc(nw))) return rc;
-    if (!c->net_b.p && (rc = c->net_b.alloc(nb))) return rc;
+    const size_t ncls = c->cls.size();
+    if (!c->net_w.p && (rc = c->net_w.alloc(ncls * kNetWords))) return rc;
+    if (!c->net_b.p && (rc = c->net_b.alloc(ncls * kNetBiases))) return rc;
     if (!c->net_ev_d.p) {
         if ((rc = c->net_ev_d.alloc(4))) return rc;
         REGC_HIP(hipMemset(c->net_ev_d.p, 0, 4 * sizeof(unsigned long long)));
     }
-    uint16_t *w = c->net_w.p;
-    float *b = c->net_b.p;
-    if ((rc = mlp_export_sampler(mlp, c->opts.precision == REGC_FP64, w, w + (size_t)kNetNV * kNetH,
-                                 w + (size_t)kNetNV * kNetH + kNetH * kNetH,
-                                 w + (size_t)kNetNV * kNetH + 2 * kNetH * kNetH, b, b + kNetH, b + 2 * kNetH,
-                                 b + 3 * kNetH, c->stream)))
-        return rc;
+    for (int k = k0; k < k1; ++k) {
+        uint16_t *w = c->net_w.p + (size_t)k * kNetWords;
+        float *b = c->net_b.p + (size_t)k * kNetBiases;
+        if ((rc = mlp_export_sampler(mlp, c->opts.precision == REGC_FP64, w, w + (size_t)kNetNV * kNetH,
+                                     w + (size_t)kNetNV * kNetH + kNetH * kNetH,
+                                     w + (size_t)kNetNV * kNetH + 2 * kNetH * kNetH, b, b + kNetH, b + 2 * kNetH,
+                                     b + 3 * kNetH, c->stream)))
+            return rc;
+        c->alpha[k] = alpha;
+    }
     REGC_HIP(hipStreamSynchronize(c->stream));
     c->learn_smem = smem;
-    c->alpha = alpha;
     return REGC_OK;
+}
+
+extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
+{
+    return set_proposal(c, -1, mlp, alpha);
+}
+
+extern "C" int regc_set_class_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
+{
+    REGC_CHECK(cls >= 0, REGC_EINVAL, "class index %d out of range", cls);
+    return set_proposal(c, cls, mlp, alpha);
 }
 
 extern "C" int regc_set_observables(regc_ctx *c, const regc_observables *spec)

@@ -464,7 +464,10 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     extern __shared__ __align__(32) unsigned char smem[];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int w = blockIdx.x;
-    const ClassDev &C = a.cls[0];
+    const int cid = l.walker_class[w];
+    const ClassDev &C = a.cls[cid];
+    const NetDev &net = l.net[cid];
+    const double alpha = l.alpha[cid];
     const LearnLds L = learn_lds(a.max_slab_len, a.max_stencil, a.gas_stride, (int)sizeof(Real));
     Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
     int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
@@ -483,9 +486,11 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     S.logit = reinterpret_cast<float *>(smem + L.logit);
     {
         float *bias = reinterpret_cast<float *>(smem + L.bias);
-        for (int k = tid; k < kNetNV; k += kLT) bias[k] = l.net.b4[k];
-        for (int k = tid; k < 3 * kNetH; k += kLT)
-            bias[kNetNV + k] = k < kNetH ? l.net.b1[k] : (k < 2 * kNetH ? l.net.b2[k - kNetH] : l.net.b3[k - 2 * kNetH]);
+        if (alpha > 0.0) {
+            for (int k = tid; k < kNetNV; k += kLT) bias[k] = net.b4[k];
+            for (int k = tid; k < 3 * kNetH; k += kLT)
+                bias[kNetNV + k] = k < kNetH ? net.b1[k] : (k < 2 * kNetH ? net.b2[k - kNetH] : net.b3[k - 2 * kNetH]);
+        }
         S.b4 = bias;
         S.b1 = bias + kNetNV;
         S.b2 = S.b1 + kNetH;
@@ -561,7 +566,6 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     const double lx = C.lx, ly = C.ly, zlo = C.zlo, zhi = C.zhi, H = C.zhi - C.zlo;
     const double md = a.max_disp;
     const double tinv = 1.0 / beta;
-    const double alpha = l.alpha;
 
     uint32_t stat = 0;          // wave 0: lane k < kNStat holds counter k
     uint32_t useful = 0;        // (unused pair counter of the shared helper)
@@ -606,11 +610,19 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
                         if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
                         if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
                         wall = pz < zlo || pz > zhi;
+                    } else if (alpha == 0.0) {
+                        // a class without a network: the plain method (q = 1/V)
+                        if (kind == 1) {
+                            px = lx * ux;
+                            py = ly * uy;
+                            pz = zlo + H * uz;
+                        }
+                        c = kind == 1 ? lnzv - lnk[n + 1] : lnk[n] - lnzv;
                     } else {
                         // network output for occ(X) (insertion, cached while X's occupancy
                         // stands) or occ(X \ i) (removal)
                         if (kind == 2 || !cached) {
-                            lse = net_forward(l.net, S, kind == 2 ? vold : -1, tid, wave, lane);
+                            lse = net_forward(net, S, kind == 2 ? vold : -1, tid, wave, lane);
                             ++ev_pass;
                         } else {
                             ++ev_hit;

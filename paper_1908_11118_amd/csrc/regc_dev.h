@@ -198,9 +198,12 @@ struct NetDev {
     const float *b1, *b2, *b3, *b4;
 };
 
+constexpr int kMaxLearnClasses = 8;  // classes of a batch that can each carry a network
+
 struct LearnArgs {
-    NetDev net;
-    double alpha;                    // mixture weight of the network branch (> 0)
+    NetDev net[kMaxLearnClasses];    // per class (entries of classes without a network unused)
+    double alpha[kMaxLearnClasses];  // per class mixture weight of the network branch (0: uniform insertion)
+    const int *walker_class;         // class of every walker
     unsigned long long *evals;       // [0] network passes, [1] insertions served from the cached pass,
                                      // [2] network-branch insertions, [3] of them accepted
 };

@@ -32,7 +32,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
-           "regc_set_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
+           "regc_set_proposal", "regc_set_class_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
            "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables",
            "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error"]
 
@@ -144,6 +144,7 @@ def lib():
         L.regc_mlp_destroy.argtypes = [vp]
         L.regc_mlp_destroy.restype = None
         L.regc_set_proposal.argtypes = [vp, vp, C.c_double]
+        L.regc_set_class_proposal.argtypes = [vp, C.c_int, vp, C.c_double]
         L.regc_get_proposal_stats.argtypes = [vp, _i64p]
         L.regc_capture_voxels.argtypes = [vp, vp, vp]
         L.regc_set_observables.argtypes = [vp, C.POINTER(ObsSpec)]
@@ -358,10 +359,15 @@ class Regc:
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().regc_restore(self.h, buf, len(blob)))
 
-    def set_proposal(self, mlp, alpha: float):
+    def set_proposal(self, mlp, alpha: float, cls: Optional[int] = None):
         """Learned insertion proposal from the network's current parameters with
-        mixture weight alpha (mlp None or alpha 0: the plain method)."""
-        _check(lib().regc_set_proposal(self.h, mlp.h if mlp is not None else None, float(alpha)))
+        mixture weight alpha, for class `cls` of a batch or for every class (mlp None
+        or alpha 0: the plain method)."""
+        h = mlp.h if mlp is not None else None
+        if cls is None:
+            _check(lib().regc_set_proposal(self.h, h, float(alpha)))
+        else:
+            _check(lib().regc_set_class_proposal(self.h, int(cls), h, float(alpha)))
 
     def set_observables(self, dz: float, layer, dr: float, nr: int):
         """Record per-sample axial z-bin counts, layer pair counts by lateral distance

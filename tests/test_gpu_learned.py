@@ -124,8 +124,62 @@ def test_alpha_zero_and_errors():
     assert _first_divergence(bits, r["bits"], nps, r["trace_n"]) is None
     with regc.Regc([w, w.replace(seed=3)], precision=regc.FP64, sample_capacity=0) as g:
         with pytest.raises(regc.RegcError):
-            g.set_proposal(net, 0.5)
+            g.set_proposal(net, 0.5, cls=2)          # no such class
+        with pytest.raises(regc.RegcError):
+            g.set_proposal(net, -0.1, cls=0)
+    with regc.Regc(W.paper_schedule(w), precision=regc.FP64, sample_capacity=0) as g:
+        with pytest.raises(regc.RegcError):
+            g.set_proposal(net, 0.5)                 # the paper's step keeps uniform insertion
     net.close()
+
+
+def _batch_classes():
+    """Three slab classes of different box, n_max and grid (swaps within a class)."""
+    c3 = W.config3_classes()
+    out = [c3[1].replace(t=W.linear_grid(0.6, 1.8, 3), mu=W.linear_grid(-5.0, -2.5, 4), n_max=70),
+           W.small_lj(n_t=2, n_mu=3, n_max=30, mu=(-4.0, -2.0)),
+           c3[0].replace(t=W.linear_grid(0.7, 1.5, 4), mu=W.linear_grid(-6.0, -3.0, 2), n_max=50)]
+    return [w.replace(sample_every=3, swap_every=10) for w in out]
+
+
+@pytest.mark.parametrize("graph", [0, 2])
+def test_learned_fp64_uneven_batch_one_network_per_class(graph):
+    """A batch of three slab classes in the same launches, each class with its own
+    network over its own box (the last class without one, inserting uniformly):
+    every class's trajectories equal a lone oracle learned chain with the batch's
+    walker offsets; with graph replay of whole exchange intervals too."""
+    classes = _batch_classes()
+    setup = [(_net(11), 0.6), (None, 0.0), (_net(12, out_scale=2.0), 0.9)]
+    sweeps = 45
+    _say(f"[learned batch] {len(classes)} classes, graph={graph}")
+    nets = [regc.Mlp(p) if p is not None else None for p, _ in setup]
+    with regc.Regc(classes, precision=regc.FP64, trace_capacity=sweeps, graph_intervals=graph,
+                   sample_capacity=0) as g:
+        for c, (net, (_, alpha)) in enumerate(zip(nets, setup)):
+            g.set_proposal(net, alpha, cls=c)
+        g.run(20)
+        g.run(sweeps - 20)
+        bits, nps = g.trace(sweeps)
+        wk = g.walkers()
+        st = g.stats()
+        ps = g.proposal_stats()
+        offs, cnts = g.offsets, g.counts
+    for net in nets:
+        if net is not None:
+            net.close()
+    assert ps["drawn"] > 0 and ps["passes"] > 0
+    for c, w in enumerate(classes):
+        params, alpha = setup[c]
+        ref = oracle.Chain(w, walker_offset=offs[c], class_id=c, net=params, alpha=alpha)
+        r = ref.run(sweeps, trace=True)
+        sl = slice(offs[c], offs[c] + cnts[c])
+        words = r["bits"].shape[2]
+        where = _first_divergence(bits[:, sl, :words], r["bits"], nps[:, sl], r["trace_n"])
+        assert where is None, f"class {c}: {where}"
+        assert np.array_equal(wk["n"][sl], ref.n) and np.array_equal(wk["label"][sl], ref.label)
+        assert np.allclose(wk["e"][sl], ref.e, rtol=1e-10, atol=1e-9)
+        assert np.array_equal(st["stats"][sl], ref.stats)
+        assert np.array_equal(st["swap_acc"][:, sl], ref.swap_acc)
 
 
 def test_learned_fp32_ideal_gas_poisson():
@@ -176,3 +230,40 @@ def test_learned_fp32_lj_mean_n_matches_the_plain_oracle():
         ma, sa = batch_means(na[:, s])
         mb, sb = batch_means(nb[:, s])
         assert abs(ma - mb) < 4 * math.hypot(sa, sb) + 1e-9, (s, ma, mb, sa, sb)
+
+
+def test_learned_fp32_batch_one_network_per_class_mean_n():
+    """The full stack at a small size: two slab classes of different box in one
+    batch, each with its own MFMA network (random weights) in the sweep, FP32 pairs:
+    every state's mean N agrees with the plain FP64 oracle run of that class within
+    4 standard errors."""
+    classes = [W.small_lj(n_t=2, n_mu=2, n_max=14, mu=(-4.5, -3.0)).replace(sample_every=1),
+               W.small_lj(n_t=2, n_mu=2, n_max=18, box=7.5, height=5.0, mu=(-4.0, -3.0)).replace(sample_every=1)]
+    sweeps = 16000
+    _say(f"[learned fp32 batch] {len(classes)} classes sweeps={sweeps}")
+    nets = [regc.Mlp(_net(21, out_scale=2.0)), regc.Mlp(_net(22, out_scale=2.0))]
+    with regc.Regc(classes, precision=regc.FP32PAIR, sample_capacity=sweeps * sum(w.n_states for w in classes)) as g:
+        g.set_proposal(nets[0], 0.7, cls=0)
+        g.set_proposal(nets[1], 0.9, cls=1)
+        g.run(1000)
+        g.clear_samples()
+        g.run(sweeps)
+        smp = g.samples()
+        ps = g.proposal_stats()
+        offs, cnts = g.offsets, g.counts
+    for net in nets:
+        net.close()
+    assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
+    W_all = sum(cnts)
+    for c, w in enumerate(classes):
+        ref = oracle.Chain(w, walker_offset=offs[c], class_id=c)
+        ref.run(1000)
+        r = ref.run(sweeps)
+        sl = slice(offs[c], offs[c] + cnts[c])
+        mine = {k: smp[k].reshape(-1, W_all)[:, sl].ravel() for k in ("n", "e", "state")}
+        na, _ = per_state_series(r, w.n_states)
+        nb, _ = per_state_series(mine, w.n_states)
+        for s in range(w.n_states):
+            ma, sa = batch_means(na[:, s])
+            mb, sb = batch_means(nb[:, s])
+            assert abs(ma - mb) < 4 * math.hypot(sa, sb) + 1e-9, (c, s, ma, mb, sa, sb)
