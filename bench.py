@@ -17,7 +17,10 @@ terms x 25 flops / kernel time from HIP events on the context stream), the CPU
 oracle's trial rate on the host cores on a bounded sample of the same workload,
 and the reweighting of 1024 states x ~10^6 samples.  A last leg measures the
 wall time to a target accuracy of <N>(T, mu) with and without the learned insertion
-proposal on the 64-replica system (--learned-seconds 0 skips it).
+proposal on the 64-replica system (--learned-seconds 0 skips it).  --full-stack adds
+the 4096-replica uneven batch with one learned proposal per slab class, per-class
+reweighting maps and an FP64 oracle check on a 64-replica subset (off by default:
+it takes minutes of GPU and host time).
 """
 from __future__ import annotations
 
@@ -83,6 +86,16 @@ def main():
     ap.add_argument("--learned-capture", type=int, default=10000, help="plain sweeps per seed captured for training")
     ap.add_argument("--learned-train-steps", type=int, default=20000, help="Adam steps of the proposal network")
     ap.add_argument("--learned-reference", type=int, default=100000, help="sweeps of the FP64 reference run")
+    ap.add_argument("--full-stack", action="store_true",
+                    help="also run the full stack: the 4096-replica uneven batch with one learned proposal per "
+                         "slab class, per-class reweighting maps and an FP64 oracle check on a 64-replica subset")
+    ap.add_argument("--fs-capture", type=int, default=500, help="full stack: captured sweeps for training")
+    ap.add_argument("--fs-train-steps", type=int, default=5000, help="full stack: Adam steps per class network")
+    ap.add_argument("--fs-sweeps", type=int, default=2000, help="full stack: production sweeps (sampled every 2)")
+    ap.add_argument("--fs-oracle-sweeps", type=int, default=3000, help="full stack: oracle sweeps on the subset")
+    ap.add_argument("--fs-tmin", type=float, default=0.88,
+                    help="full stack: lowest temperature of the restricted reweighting (below it the states "
+                         "on either side of the condensation do not exchange configurations)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
@@ -271,6 +284,8 @@ def main():
         gm.close()
     if args.learned_seconds > 0:
         result["learned"] = learned_leg(args)
+    if args.full_stack:
+        result["full_stack"] = full_stack_leg(args)
     print(json.dumps(result))
 
 
@@ -357,6 +372,169 @@ def learned_leg(args):
         out["speedup_t_acc"] = plain["t_acc_s"] / learned["t_acc_s"]
     elif plain["reached"]:
         out["speedup_t_acc"] = f"< {plain['t_acc_s'] / learned['t_acc_s']:.4f} (learned not reached in the cap)"
+    return out
+
+
+def full_stack_leg(args):
+    """4096 uneven replicas (four slab classes 6x6 .. 12x12 x 3, N <= 500) with one
+    learned insertion proposal per class fused into the sweep, FP32 pairs; the
+    reweighting of each class (1024 states) into <N>, coverage and heat-capacity
+    maps; the maps checked against the FP64 oracle run as its own REGC on an 8 x 8
+    sub-grid of the 6x6 class, started from the GPU's configurations."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1908_11118_amd import proposal as P
+    from paper_1908_11118_amd import regc
+    from paper_1908_11118_amd import workloads as W
+
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    classes = W.config3_classes()
+    out = {"workload": "4 slab classes {6,8,10,12}^2 x 3, box 1.5n x 1.5n x 12, N <= 500, 4 x 32 x 32 replicas",
+           "alpha": args.learned_alpha}
+    t = time.perf_counter()
+    data, blob = P.capture_batch(classes, burnin=2000, sweeps=args.fs_capture)
+    torch.cuda.synchronize()
+    out["capture"] = {"sweeps": args.fs_capture, "examples_per_class": int(data[0][0].shape[0]),
+                      "seconds": time.perf_counter() - t}
+    say(f"[full stack] captured {args.fs_capture} sweeps in {out['capture']['seconds']:.1f} s")
+    nets = []
+    t = time.perf_counter()
+    for c, (vox, n) in enumerate(data):
+        nets.append(P.train(vox, n, steps=args.fs_train_steps, batch=256, lr=1e-3, seed=100 + 17 * c))
+    torch.cuda.synchronize()
+    out["train"] = {"steps_per_class": args.fs_train_steps, "seconds": time.perf_counter() - t}
+    del data
+    say(f"[full stack] trained {len(nets)} networks in {out['train']['seconds']:.1f} s")
+
+    wl = [w.replace(sample_every=2) for w in classes]
+    n_rec = args.fs_sweeps // 2
+    Wa = sum(w.n_states for w in wl)
+    rates = {}
+    with regc.Regc(wl, precision=regc.FP32PAIR, sample_capacity=n_rec * Wa, graph_intervals=10) as g:
+        for mode in ("plain", "learned"):
+            g.restore(blob)
+            for c, net in enumerate(nets):
+                g.set_proposal(net if mode == "learned" else None, args.learned_alpha, cls=c)
+            g.run(20)
+            g.sync()
+            t0 = time.perf_counter()
+            g.run(40)
+            g.sync()
+            dt = time.perf_counter() - t0
+            rates[mode] = 40 * sum(w.n_states * w.trials for w in wl) / dt
+            say(f"[full stack] {mode}: {rates[mode]:.3g} trial moves/s")
+        g.clear_samples()
+        t0 = time.perf_counter()
+        g.run(args.fs_sweeps)
+        g.sync()
+        t_prod = time.perf_counter() - t0
+        ps = g.proposal_stats()
+        smp = g.samples()
+        wk = g.walkers()
+        offs, cnts = g.offsets, g.counts
+        out["rates"] = {"plain_trial_moves_per_s": rates["plain"], "learned_trial_moves_per_s": rates["learned"],
+                        "production_sweeps": args.fs_sweeps, "production_s": t_prod, "proposal": ps}
+        # per-class reweighting over the class's own states: all states, and the states with
+        # T >= fs_tmin only (the low-T rows cannot exchange configurations across the
+        # condensation, so their samples are not all from equilibrium and bias a joint solve)
+        skip = n_rec // 10
+        maps, maps_hi = [], []
+        for c, w in enumerate(wl):
+            mb = regc.Mbar(w.t, w.mu, w.n_max)
+            mb.load_run(g, c, skip)
+            t0 = time.perf_counter()
+            f, conv, iters, delta = mb.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
+            tr = mb.targets(w.t, w.mu)
+            dt = time.perf_counter() - t0
+            mb.close()
+            o, cn = offs[c], cnts[c]
+            E = smp["e"].reshape(-1, Wa)[skip:, o:o + cn].ravel()
+            Nn = smp["n"].reshape(-1, Wa)[skip:, o:o + cn].ravel()
+            St = smp["state"].reshape(-1, Wa)[skip:, o:o + cn].ravel()
+            l0 = int(np.searchsorted(w.t, args.fs_tmin))
+            keep = St // len(w.mu) >= l0
+            mh = regc.Mbar(w.t[l0:], w.mu, w.n_max)
+            mh.set_samples(E[keep], Nn[keep], St[keep] - l0 * len(w.mu))
+            _, conv_h, it_h, _ = mh.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
+            trh = mh.targets(w.t[l0:], w.mu)
+            mh.close()
+            beta = np.repeat(1.0 / w.t, len(w.mu))
+            heat = beta ** 2 * (tr["mean_e2"] - tr["mean_e"] ** 2)
+            n_sites = int(round(w.lx / 1.5)) ** 2
+            cov = tr["mean_n"] / n_sites
+            maps.append(tr)
+            maps_hi.append((l0, trh))
+            out.setdefault("reweighting", []).append(
+                {"class": w.name, "samples": int(len(E)), "iterations": iters, "converged": bool(conv),
+                 "seconds": dt, "coverage_range": [float(cov.min()), float(cov.max())],
+                 "heat_capacity_max": float(heat.max()), "phases": int(len(set(tr["phase"].tolist()))),
+                 "restricted_t_min": float(w.t[l0]), "restricted_iterations": it_h,
+                 "restricted_converged": bool(conv_h)})
+            say(f"[full stack] class {c}: reweighting {iters} iterations, {dt:.2f} s")
+    for net in nets:
+        net.close()
+
+    # FP64 oracle on the 8 x 8 sub-grid (every fourth T and mu) of the 6x6 class, run as
+    # its own REGC from the GPU's configurations of those states
+    w0 = wl[0]
+    sub_t, sub_mu = w0.t[::4], w0.mu[::4]
+    ws = w0.replace(t=sub_t, mu=sub_mu, sample_every=1, seed=5)
+    lab = wk["label"][offs[0]:offs[0] + cnts[0]]
+    li, mi = lab // len(w0.mu), lab % len(w0.mu)
+    pick = np.nonzero((li % 4 == 0) & (mi % 4 == 0))[0]
+    sub_label = (li[pick] // 4) * len(sub_mu) + mi[pick] // 4
+    oracle.build(force=False)
+    ch = oracle.Chain(ws, n_threads=oracle.default_threads())
+    ch.set_walkers(wk["n"][offs[0] + pick], wk["xyz"][offs[0] + pick], label=sub_label)
+    t0 = time.perf_counter()
+    ch.run(200)
+    r = ch.run(args.fs_oracle_sweeps)
+    t_or = time.perf_counter() - t0
+    S = ws.n_states
+    order = np.argsort(r["state"].reshape(-1, S), axis=1)
+    n_or = np.take_along_axis(r["n"].reshape(-1, S), order, axis=1).astype(np.float64)
+    e_or = np.take_along_axis(r["e"].reshape(-1, S), order, axis=1)
+    m_or, se_or = P.mean_se(list(n_or.T))
+    sm_n = smp["n"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]]
+    sm_s = smp["state"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]]
+    n_gpu = np.take_along_axis(sm_n, np.argsort(sm_s, axis=1), axis=1).astype(np.float64)
+    m_gpu, se_gpu = P.mean_se(list(n_gpu.T))
+    sub_states = np.array([(4 * a) * len(w0.mu) + 4 * b for a in range(len(sub_t)) for b in range(len(sub_mu))])
+    se_c = np.maximum(np.sqrt(se_or ** 2 + se_gpu[sub_states] ** 2), 0.02)     # floor: states pinned at the cap
+    hi = np.repeat(sub_t >= args.fs_tmin, len(sub_mu))
+
+    def compare(est, sel):
+        z = (est[sel] - m_or[sel]) / se_c[sel]
+        return {"states": int(sel.sum()), "frac_within_3se": float(np.mean(np.abs(z) <= 3.0)),
+                "chi2_per_state": float(np.mean(z ** 2)), "max_abs_dn": float(np.max(np.abs(est[sel] - m_or[sel])))}
+
+    l0, trh = maps_hi[0]
+    mbar_all = maps[0]["mean_n"][sub_states]
+    mbar_hi = np.full(len(sub_states), np.nan)
+    mbar_hi[hi] = trh["mean_n"][sub_states[hi] - l0 * len(w0.mu)]
+    beta_s = np.repeat(1.0 / sub_t, len(sub_mu))
+    heat_or = beta_s ** 2 * e_or.var(axis=0)
+    heat_hi = np.full(len(sub_states), np.nan)
+    heat_hi[hi] = (beta_s[hi] ** 2 * (trh["mean_e2"] - trh["mean_e"] ** 2)[sub_states[hi] - l0 * len(w0.mu)])
+    out["oracle_subset"] = {
+        "grid": "8 x 8 (every fourth T and mu of the 6x6 class), its own REGC from the GPU's configurations",
+        "sweeps": args.fs_oracle_sweeps, "seconds": t_or, "threads": oracle.default_threads(),
+        "gpu_direct_means_all_states": compare(m_gpu[sub_states], np.ones(len(sub_states), bool)),
+        "reweighted_all_states_solve_at_t_ge_tmin": compare(mbar_all, hi),
+        "reweighted_restricted_solve_at_t_ge_tmin": compare(mbar_hi, hi),
+        "heat_capacity_restricted_median_rel_diff": float(np.median(np.abs(heat_hi[hi] - heat_or[hi]) /
+                                                                    np.maximum(np.abs(heat_or[hi]), 1e-9))),
+        "t_min": args.fs_tmin}
+    out["oracle_subset_states"] = {"t": np.repeat(sub_t, len(sub_mu)).tolist(), "mu": np.tile(sub_mu, len(sub_t)).tolist(),
+                                   "oracle_mean_n": m_or.tolist(), "oracle_se": se_or.tolist(),
+                                   "gpu_direct_mean_n": m_gpu[sub_states].tolist(),
+                                   "gpu_se": se_gpu[sub_states].tolist(), "reweighted_all": mbar_all.tolist(),
+                                   "reweighted_restricted": [None if np.isnan(x) else float(x) for x in mbar_hi],
+                                   "heat_capacity_oracle": heat_or.tolist(),
+                                   "heat_capacity_restricted": [None if np.isnan(x) else float(x) for x in heat_hi]}
+    say(f"[full stack] oracle subset: {out['oracle_subset']}")
     return out
 
 

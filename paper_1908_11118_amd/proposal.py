@@ -52,6 +52,34 @@ def capture_dataset(workload, seeds=(1, 2), burnin: int = 2000, sweeps: int = 10
     return vox, n
 
 
+def capture_batch(classes, burnin: int = 2000, sweeps: int = 500, seed: int = 1, precision: int = regc.FP32PAIR,
+                  **opts):
+    """Per-class device data sets of sweep-end configurations of a plain uneven
+    batch: returns [(vox, n)] per class (torch tensors as in capture_dataset, rows of
+    the class's walkers only, n_max the largest over the batch) and the checkpoint
+    of the batch after burn-in."""
+    import torch
+    wl = [w.replace(sample_every=0, seed=seed) for w in classes]
+    with regc.Regc(wl, precision=precision, sample_capacity=0, **opts) as g:
+        g.run(burnin)
+        blob = g.checkpoint()
+        Wa, nmax = g.W, max(w.n_max for w in wl)
+        vox = torch.zeros((sweeps * Wa, nmax), dtype=torch.int16, device="cuda")
+        n = torch.zeros((sweeps * Wa,), dtype=torch.int32, device="cuda")
+        for s in range(sweeps):
+            g.run(1)
+            g.capture_voxels(vox[s * Wa].data_ptr(), n[s * Wa].data_ptr())
+        g.sync()
+        offs, cnts = g.offsets, g.counts
+    out = []
+    for o, c in zip(offs, cnts):
+        rows = (torch.arange(sweeps, device="cuda")[:, None] * Wa + o + torch.arange(c, device="cuda")[None, :])
+        rows = rows.reshape(-1)
+        out.append((vox[rows].contiguous(), n[rows].contiguous()))
+    del vox, n
+    return out, blob
+
+
 def train(vox, n, steps: int = 10000, batch: int = 256, lr: float = 1e-3, seed: int = 100, init_seed: int = 0,
           report_every: int = 500, log=None) -> "regc.Mlp":
     """Trains a fresh network on the device data set; returns it (regc.Mlp)."""
