@@ -1,0 +1,43 @@
+"""Host-side statistics of the time-to-accuracy measurement (CPU only): the running
+per-state series gives the same mean and batch-means error as the direct
+computation over all samples, whatever the chunking."""
+import numpy as np
+
+from paper_1908_11118_amd.proposal import _Series, _per_state, efficiency_ratio, mean_se
+
+
+def _records(seed, recs, S):
+    rng = np.random.default_rng(seed)
+    state = np.array([rng.permutation(S) for _ in range(recs)]).ravel()
+    n = rng.integers(0, 50, recs * S)
+    return state, n
+
+
+def test_running_series_equals_direct_batch_means():
+    S, recs = 8, 1013
+    state, n = _records(0, recs, S)
+    m_ref, se_ref = mean_se(_per_state(state, n, S))
+    for chunk in (1, 37, 100, recs):
+        ser = _Series(S)
+        for k in range(0, recs, chunk):
+            ser.add(state[k * S:(k + chunk) * S], n[k * S:(k + chunk) * S])
+        m, se = ser.mean_se()
+        assert np.allclose(m, m_ref, rtol=0, atol=1e-12)
+        assert np.allclose(se, se_ref, rtol=1e-12, atol=1e-12)
+
+
+def test_series_before_enough_batches_reports_infinite_error():
+    ser = _Series(3, n_batches=20)
+    state, n = _records(1, 10, 3)
+    ser.add(state, n)
+    m, se = ser.mean_se()
+    assert np.all(np.isinf(se)) and np.all(np.isfinite(m))
+
+
+def test_efficiency_ratio():
+    a = {"se_by_state": [0.2, 0.4, 0.0], "t_acc_s": 10.0}
+    b = {"se_by_state": [0.1, 0.4, 0.3], "t_acc_s": 20.0}
+    r = efficiency_ratio(a, b)
+    # 1/(SE^2 t): state 0 ratio (0.04*10)/(0.01*20) = 2, state 1 (0.16*10)/(0.16*20) = 0.5; state 2 frozen
+    assert r["states"] == 2
+    assert abs(r["max"] - 2.0) < 1e-12 and abs(r["min"] - 0.5) < 1e-12 and abs(r["geomean"] - 1.0) < 1e-12
