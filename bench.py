@@ -98,7 +98,7 @@ def main():
                          "on either side of the condensation do not exchange configurations)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is described in the "
                                    "design notes but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -45,7 +45,7 @@ extern "C" {
 #define REGC_EHIP (-3)         /* a HIP runtime call failed; message has hipGetErrorString */
 #define REGC_ECAPACITY (-4)    /* sample or trace buffer too small; nothing was run */
 #define REGC_ESTATE (-5)       /* call made in the wrong order */
-#define REGC_EUNSUPPORTED (-6) /* option not supported by this build */
+#define REGC_EUNSUPPORTED (-6) /* option or combination of options not supported */
 #define REGC_ENOCONV (-7)      /* reweighting did not converge; last iterate returned */
 
 /* ---- enumerations --------------------------------------------------------- */
