@@ -280,6 +280,31 @@ def main():
                           "fp64_exp_per_s": L * ns / (per_iter * 1e-3),
                           "sample_stream_GBps": 8.0 * ns / (per_iter * 1e-3) / 1e9,
                           "target_grid": "64 x 64", "phases_found": int(len(set(tr["phase"].tolist())))}
+        # consistency at the sampled states: reweighted <N> against the direct per-state
+        # means, for the solve over all states and for the solve over T >= 0.88 only (the
+        # low-T rows do not exchange configurations across the condensation)
+        from paper_1908_11118_amd import proposal as P
+        smp = gm.samples()
+        S = w.n_states
+        nn = np.take_along_axis(smp["n"].reshape(-1, S), np.argsort(smp["state"].reshape(-1, S), axis=1),
+                                axis=1).astype(np.float64)
+        m_dir, se_dir = P.mean_se(list(nn.T))
+        at = mb.targets(w.t, w.mu)["mean_n"]
+        l0 = int(np.searchsorted(w.t, 0.88))
+        keep = smp["state"] // len(w.mu) >= l0
+        mh = regc.Mbar(w.t[l0:], w.mu, w.n_max)
+        mh.set_samples(smp["e"][keep], smp["n"][keep], smp["state"][keep] - l0 * len(w.mu))
+        mh.solve(tol=1e-8, max_iter=2000, allow_noconv=True)
+        ah = mh.targets(w.t[l0:], w.mu)["mean_n"]
+        mh.close()
+        hi = np.arange(S) >= l0 * len(w.mu)
+        se_f = np.maximum(se_dir, 0.02)
+        z_all = (at - m_dir) / se_f
+        z_hi = (ah - m_dir[hi]) / se_f[hi]
+        result["mbar"]["consistency_at_sampled_states_t_ge_0.88"] = {
+            "states": int(hi.sum()),
+            "all_state_solve": {"mean_z": float(z_all[hi].mean()), "frac_abs_z_gt_3": float(np.mean(np.abs(z_all[hi]) > 3))},
+            "restricted_solve": {"mean_z": float(z_hi.mean()), "frac_abs_z_gt_3": float(np.mean(np.abs(z_hi) > 3))}}
         mb.close()
         gm.close()
     if args.learned_seconds > 0:

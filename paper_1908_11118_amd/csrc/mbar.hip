@@ -185,20 +185,20 @@ __global__ void mbar_gauge(int S, int g, const double *lnomega, double *fnew, do
         const double v = fnew[s] - f0;
         if (lnomega[s] != -INFINITY) {
             const double a = fabs(v - f[s]);
-            d = a > d ? a : d;
+            d = (a > d || a != a) ? a : d;           // a NaN propagates: the host must see it
         }
         f[s] = v;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double t = __shfl_xor(d, o);
-        d = t > d ? t : d;
+        d = (t > d || t != t) ? t : d;
     }
     if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = d;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = 0.0;
-        for (int k = 0; k < (int)(blockDim.x / 64); ++k) m = red[k] > m ? red[k] : m;
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) m = (red[k] > m || red[k] != red[k]) ? red[k] : m;
         *delta = m;
     }
 }
@@ -678,10 +678,13 @@ extern "C" int regc_mbar_set_solver(regc_mbar *mb, int method, int memory)
 
 // Fixed point f = g(f) of the self-consistent map (one device iteration = g plus the
 // gauge).  Plain: f <- g(f).  Anderson acceleration (Walker & Ni, SIAM J. Numer.
-// Anal. 49 (2011) 1715, type II, memory m) on the sampled states' components:
-// x_{k+1} = g_k - dG gamma, gamma = argmin || r_k - dR gamma ||, r = g(x) - x; a step
-// that raises the residual tenfold restarts the history.  Converged when
-// max |g(x) - x| over sampled states < tol.
+// Anal. 49 (2011) 1715, type II) on the sampled states' components:
+// x_{k+1} = g_k - dG gamma, gamma = argmin || r_k - dR gamma ||, r = g(x) - x, with
+// at most min(memory, n - 2) differences for n sampled states (one component is
+// fixed by the gauge, and more differences than free components make the least
+// squares ill-posed).  A step that raises the residual tenfold restarts the history;
+// a non-finite map value returns to the last finite one and takes plain steps for a
+// while.  Converged when max |g(x) - x| over sampled states < tol.
 extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters, double *delta)
 {
     REGC_CHECK(mb, REGC_EINVAL, "null handle");
@@ -697,12 +700,13 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     for (int k = 0; k < mb->S; ++k)
         if (mb->lnomega[k] != -INFINITY) idx.push_back(k);
     const int n = (int)idx.size();
-    const int m = mb->memory;
+    const int m = std::min(mb->memory, std::max(n - 2, 0));
     std::vector<double> x(mb->S, 0.0), gx(mb->S), xs(n), gs(n), r(n);
     std::deque<std::vector<double>> hist_r, hist_g;   // last residuals and map values (sampled part)
     double d = INFINITY, d_prev = INFINITY;
-    int it = 0;
+    int it = 0, plain_left = 0;
     bool conv = false;
+    std::vector<double> good(mb->S, 0.0);            // the last finite map value
     const int check = mb->method == 0 ? 10 : 1;
     for (it = 0; it < max_iter;) {
         REGC_HIP(mbar_iteration(mb));   // f_d <- gauge(map(f_d)), delta_d <- max |new - old|
@@ -711,9 +715,19 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
         REGC_HIP(hipMemcpyAsync(&d, mb->delta_d.p, sizeof(double), hipMemcpyDeviceToHost, s));
         if (mb->method == 1) REGC_HIP(hipMemcpyAsync(gx.data(), mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost, s));
         REGC_HIP(hipStreamSynchronize(s));
-        if (!(d == d)) break;                       // NaN: give up, report the last state
+        if (!(d <= 1e300)) {                        // NaN or inf
+            if (mb->method == 0 || it == 1) break;  // nothing to return to: report it
+            hist_r.clear();
+            hist_g.clear();
+            x = good;
+            plain_left = 5;
+            d_prev = INFINITY;
+            REGC_HIP(hipMemcpyAsync(mb->f_d.p, x.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
+            continue;
+        }
         if (d < tol) { conv = true; break; }
         if (mb->method == 0) continue;
+        good = gx;
         for (int q = 0; q < n; ++q) {
             gs[q] = gx[idx[q]];
             r[q] = gx[idx[q]] - x[idx[q]];
@@ -725,7 +739,9 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
         if ((int)hist_r.size() > m + 1) { hist_r.pop_front(); hist_g.pop_front(); }
         const int mk = (int)hist_r.size() - 1;
         std::vector<double> xn(gx);
-        if (mk > 0) {
+        if (plain_left > 0) {
+            --plain_left;
+        } else if (mk > 0) {
             std::vector<double> dR((size_t)n * mk), gamma;
             for (int j = 0; j < mk; ++j)
                 for (int q = 0; q < n; ++q) dR[(size_t)j * n + q] = hist_r[j + 1][q] - hist_r[j][q];

@@ -251,6 +251,26 @@ def test_fp32_long_run_mean_n_within_3se():
 # ---------------------------------------------------------------------------
 # Reweighting
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t_mu,sweeps", [((2, 2), 40), ((1, 3), 60), ((2, 1), 30)])
+def test_mbar_few_states_short_runs(t_mu, sweeps):
+    """Anderson-accelerated solve on grids of 2-4 states and a few hundred correlated
+    samples (where more history than free components would make the least squares
+    ill-posed): converges to the naive oracle's free energies."""
+    w = W.small_lj(n_t=t_mu[0], n_mu=t_mu[1], n_max=12, n_sweeps=sweeps)
+    _say(f"[mbar small] {t_mu} {sweeps} sweeps")
+    ref = oracle.Chain(w)
+    r = ref.run(sweeps)
+    beta, lnz = oracle.state_arrays(w)
+    omega = np.bincount(r["state"], minlength=len(beta))
+    f_ref, _, ok, _, _ = oracle.mbar_solve(beta, lnz, omega, r["e"], r["n"], tol=1e-11, max_iter=20000)
+    mb = regc.Mbar(w.t, w.mu, w.n_max)
+    mb.set_samples(r["e"], r["n"], r["state"])
+    f_gpu, conv, _, _ = mb.solve(tol=1e-10, max_iter=5000)
+    mb.close()
+    assert ok and conv and np.all(np.isfinite(f_gpu))
+    assert np.max(np.abs(f_gpu - f_ref)) < 1e-7, (f_gpu, f_ref)
+
+
 @pytest.mark.parametrize("method", [1, 0])
 def test_mbar_matches_oracle(method):
     """GPU reweighting (factorised over temperatures, plain or Anderson-accelerated
