@@ -41,3 +41,17 @@ def test_efficiency_ratio():
     # 1/(SE^2 t): state 0 ratio (0.04*10)/(0.01*20) = 2, state 1 (0.16*10)/(0.16*20) = 0.5; state 2 frozen
     assert r["states"] == 2
     assert abs(r["max"] - 2.0) < 1e-12 and abs(r["min"] - 0.5) < 1e-12 and abs(r["geomean"] - 1.0) < 1e-12
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 prints one JSON line saying the run is single-GPU and exits 2."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
