@@ -88,6 +88,7 @@ struct regc_ctx {
     // learned insertion proposal, per class (any alpha > 0: the learned kernel runs the sweeps);
     // net_w / net_b hold one network per class, allocated at the first proposal
     std::vector<double> alpha;
+    DevBuf<int> learn_order_d;              // walker of each learned-kernel workgroup
     DevBuf<uint16_t> net_w;                 // w1 | w2p | w3p | w4p (bfloat16)
     DevBuf<float> net_b;                    // b1 | b2 | b3 | b4
     DevBuf<unsigned long long> net_ev_d;    // proposal counters [4]
@@ -622,6 +623,7 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
             d.b4 = bb + 3 * kNetH;
         }
         l.walker_class = c->walker_class_d.p;
+        l.block_walker = c->learn_order_d.p;
         l.evals = c->net_ev_d.p;
         if (c->opts.precision == REGC_FP64)
             REGC_HIP(launch_learned_f64(a, l, c->learn_smem, stream));
@@ -853,6 +855,54 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
     return REGC_OK;
 }
 
+// Workgroup order of the learned kernel.  Workgroups are dispatched round-robin over
+// the XCDs (workgroup b on XCD b mod n_xcd), each XCD with its own L2; a network pass
+// streams the class's output layer (1 MB) from L2, and a batch's networks together
+// exceed one XCD's L2.  So each class gets a set of XCDs in proportion to its walkers
+// and its walkers go to workgroups on those XCDs: every XCD then streams (nearly) one
+// network.  Single-class contexts keep the identity order.
+static std::vector<int> xcd_walker_order(const std::vector<int> &walker_class, int n_class, int n_xcd)
+{
+    const int W = (int)walker_class.size();
+    std::vector<int> order(W);
+    for (int w = 0; w < W; ++w) order[w] = w;
+    if (n_class <= 1 || n_xcd <= 1 || n_class > n_xcd) return order;
+    std::vector<std::vector<int>> queue(n_class);
+    for (int w = W - 1; w >= 0; --w) queue[walker_class[w]].push_back(w);     // popped from the back
+    // XCDs per class: largest remainder, at least one each
+    std::vector<int> share(n_class, 1);
+    std::vector<double> rem(n_class);
+    int left = n_xcd - n_class;
+    for (int k = 0; k < n_class; ++k) {
+        const double want = (double)queue[k].size() * n_xcd / W - 1.0;
+        const int whole = want > 0 ? std::min((int)want, left) : 0;
+        share[k] += whole;
+        left -= whole;
+        rem[k] = want - whole;
+    }
+    while (left > 0) {
+        int best = 0;
+        for (int k = 1; k < n_class; ++k)
+            if (rem[k] > rem[best]) best = k;
+        share[best] += 1;
+        rem[best] -= 1.0;
+        --left;
+    }
+    std::vector<int> xcd_class(n_xcd);
+    for (int k = 0, x = 0; k < n_class; ++k)
+        for (int j = 0; j < share[k]; ++j) xcd_class[x++] = k;
+    for (int b = 0; b < W; ++b) {
+        int k = xcd_class[b % n_xcd];
+        if (queue[k].empty()) {                 // this class is done: the fullest other one
+            for (int q = 0; q < n_class; ++q)
+                if (queue[q].size() > queue[k].size()) k = q;
+        }
+        order[b] = queue[k].back();
+        queue[k].pop_back();
+    }
+    return order;
+}
+
 // Installs (mlp, alpha) as the insertion proposal of class cls, or of every class
 // when cls < 0; mlp = NULL or alpha = 0 removes it.
 static int set_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
@@ -885,6 +935,15 @@ static int set_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
     if (!c->net_ev_d.p) {
         if ((rc = c->net_ev_d.alloc(4))) return rc;
         REGC_HIP(hipMemset(c->net_ev_d.p, 0, 4 * sizeof(unsigned long long)));
+    }
+    if (!c->learn_order_d.p) {
+        int n_cu = 0;
+        REGC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int n_xcd = n_cu % 32 == 0 ? std::max(1, n_cu / 32) : 1;      // 32 CUs per XCD on CDNA4
+        const std::vector<int> order = xcd_walker_order(c->walker_class, (int)ncls, n_xcd);
+        if ((rc = c->learn_order_d.alloc(order.size())) ||
+            (rc = upload(c->learn_order_d.p, order.data(), sizeof(int) * order.size())))
+            return rc;
     }
     for (int k = k0; k < k1; ++k) {
         uint16_t *w = c->net_w.p + (size_t)k * kNetWords;

@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int w = blockIdx.x;
+    const int w = l.block_walker[blockIdx.x];
     const int cid = l.walker_class[w];
     const ClassDev &C = a.cls[cid];
     const NetDev &net = l.net[cid];

@@ -204,6 +204,7 @@ struct LearnArgs {
     NetDev net[kMaxLearnClasses];    // per class (entries of classes without a network unused)
     double alpha[kMaxLearnClasses];  // per class mixture weight of the network branch (0: uniform insertion)
     const int *walker_class;         // class of every walker
+    const int *block_walker;         // walker of each workgroup (XCD-aware order)
     unsigned long long *evals;       // [0] network passes, [1] insertions served from the cached pass,
                                      // [2] network-branch insertions, [3] of them accepted
 };
