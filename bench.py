@@ -301,6 +301,22 @@ def main():
         se_f = np.maximum(se_dir, 0.02)
         z_all = (at - m_dir) / se_f
         z_hi = (ah - m_dir[hi]) / se_f[hi]
+        if args.cpu_sweeps > 0:
+            # the oracle's naive reweighting iteration (every state x every sample) on the host
+            # cores, timed on the first 1e5 samples and scaled to the full set
+            import oracle
+            oracle.build(force=False)
+            sub = min(ns, 100000)
+            beta_s, lnz_s = oracle.state_arrays(w)
+            om = np.bincount(smp["state"][:sub], minlength=S)
+            t_c = time.perf_counter()
+            oracle.mbar_iterate(beta_s, lnz_s, om, smp["e"][:sub], smp["n"][:sub], np.zeros(S))
+            t_c = time.perf_counter() - t_c
+            result["mbar"]["cpu_baseline"] = {
+                "kind": "oracle", "cores": oracle.default_threads(),
+                "sample": f"one naive iteration over {S} states x the first {sub} samples, {t_c:.2f} s",
+                "seconds_per_iteration_full_set": t_c * ns / sub,
+                "gpu_over_cpu_per_iteration": (t_c * ns / sub) / (per_iter * 1e-3)}
         result["mbar"]["consistency_at_sampled_states_t_ge_0.88"] = {
             "states": int(hi.sum()),
             "all_state_solve": {"mean_z": float(z_all[hi].mean()), "frac_abs_z_gt_3": float(np.mean(np.abs(z_all[hi]) > 3))},
