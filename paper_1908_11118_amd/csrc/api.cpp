@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "host_util.h"
-#include "regc_dev.h"
+#include "learn_dev.h"
 
 namespace regc {
 

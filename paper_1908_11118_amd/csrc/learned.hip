@@ -27,6 +27,7 @@
 // later insertions until the occupancy changes.  The energy change is split over
 // the four waves and combined through LDS in a fixed order.
 #include "sweep_dev.h"
+#include "learn_dev.h"
 #include "mlp_dev.h"
 
 #if defined(REGC_FP64)

@@ -24,7 +24,7 @@
 #include "host_util.h"
 #include "mlp_dev.h"
 #include "philox_dev.h"
-#include "regc_dev.h"
+#include "learn_dev.h"
 
 namespace regc {
 namespace mlpk {

@@ -209,9 +209,9 @@ def test_fp32_configuration_energies_config2_scale():
     """1024 replicas, 192-atom slab, N <= 200, the benchmark's launch shape: the
     oracle re-evaluates sampled walkers' configurations in FP64."""
     w = W.config2()
-    _say("[fp32 energies] config2 1024 walkers, 30 sweeps")
+    _say("[fp32 energies] config2 1024 walkers, 1000 sweeps")
     with regc.Regc(w, precision=regc.FP32PAIR, sample_capacity=0) as g:
-        g.run(30)
+        g.run(1000)
         wk = g.walkers()
         e_re = g.energies()
     ch = oracle.Chain(w.replace(t=w.t[:1], mu=w.mu[:1]))
@@ -223,6 +223,31 @@ def test_fp32_configuration_energies_config2_scale():
         tol = 1e-5 * max(1.0, abs(ref))
         assert abs(e_re[k] - ref) <= tol, (k, e_re[k], ref)
         assert abs(wk["e"][k] - ref) <= tol, (k, wk["e"][k], ref)
+
+
+def test_fp32_configuration_energies_config3_batch():
+    """4096 replicas in four slab classes (N <= 500) in the benchmark's launch shape
+    (graph-replayed exchange intervals): after 600 sweeps the running and recomputed
+    energies of sampled walkers of every class agree with the oracle's FP64 energy of
+    the same configuration to 1e-5 relative."""
+    classes = W.config3_classes()
+    _say("[fp32 energies] config3 4096 walkers, 600 sweeps")
+    with regc.Regc(classes, precision=regc.FP32PAIR, sample_capacity=0, graph_intervals=10) as g:
+        g.run(600)
+        wk = g.walkers()
+        e_re = g.energies()
+        offs, cnts = g.offsets, g.counts
+    rng = np.random.default_rng(1)
+    assert wk["n"].max() > 400
+    for c, w in enumerate(classes):
+        ch = oracle.Chain(w.replace(t=w.t[:1], mu=w.mu[:1]))
+        n_c = wk["n"][offs[c]:offs[c] + cnts[c]]
+        idx = offs[c] + np.concatenate([np.argsort(n_c)[-4:], rng.choice(cnts[c], 6, replace=False)])
+        for k in idx:
+            ref = ch.energy(wk["xyz"][k, : wk["n"][k]])
+            tol = 1e-5 * max(1.0, abs(ref))
+            assert abs(e_re[k] - ref) <= tol, (c, k, e_re[k], ref)
+            assert abs(wk["e"][k] - ref) <= tol, (c, k, wk["e"][k], ref)
 
 
 def test_fp32_long_run_mean_n_within_3se():
