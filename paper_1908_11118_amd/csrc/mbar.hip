@@ -371,9 +371,12 @@ __global__ void __launch_bounds__(kMbarThreads) mbar_obs_chunk(int nT, int n_obs
 __global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *part, const int *seg_c0,
                               const int *seg_c1, const double *tlnz, double *cond, double *mean)
 {
-    extern __shared__ double G[];     // [nN]
+    extern __shared__ double sh[];    // G [nN] | p(N) of one mu [nN]
+    double *G = sh, *P = sh + nN;
     const int t = blockIdx.x;
     const size_t stride = (size_t)n_obs + 2;
+    double *ct = cond + (size_t)t * nN * n_obs;
+    // the average conditional on N: chunk partials of one N combined in chunk order
     for (int N = 0; N < nN; ++N) {
         double M = -INFINITY;
         for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
@@ -394,38 +397,32 @@ __global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *
                     const double *o = part + ((size_t)c * nT + t) * stride;
                     if (o[0] != -INFINITY) a += o[2 + k] * exp(o[0] - M);
                 }
-            const double v = s0 > 0.0 ? a / s0 : 0.0;
-            if (cond) cond[((size_t)t * nN + N) * n_obs + k] = v;
+            ct[(size_t)N * n_obs + k] = s0 > 0.0 ? a / s0 : 0.0;
         }
     }
     __syncthreads();
     if (!mean) return;
+    // mean at every mu: sum over N of p(N) times the conditional average
     for (int m = 0; m < nMu; ++m) {
         const double lz = tlnz[t * nMu + m];
-        double mx = -INFINITY;
-        for (int N = 0; N < nN; ++N)
-            if (G[N] != -INFINITY) mx = fmax(mx, (double)N * lz + G[N]);
-        double sum = 0.0;
-        for (int N = 0; N < nN; ++N)
-            if (G[N] != -INFINITY) sum += exp((double)N * lz + G[N] - mx);
-        const double lse = mx + log(sum);
+        if (threadIdx.x == 0) {
+            double mx = -INFINITY;
+            for (int N = 0; N < nN; ++N)
+                if (G[N] != -INFINITY) mx = fmax(mx, (double)N * lz + G[N]);
+            double sum = 0.0;
+            for (int N = 0; N < nN; ++N)
+                if (G[N] != -INFINITY) sum += exp((double)N * lz + G[N] - mx);
+            const double lse = mx + log(sum);
+            for (int N = 0; N < nN; ++N) P[N] = G[N] == -INFINITY ? 0.0 : exp((double)N * lz + G[N] - lse);
+        }
+        __syncthreads();
         for (int k = threadIdx.x; k < n_obs; k += blockDim.x) {
             double acc = 0.0;
-            for (int N = 0; N < nN; ++N) {
-                if (G[N] == -INFINITY) continue;
-                double a = 0.0, s0 = 0.0, M = -INFINITY;
-                for (int c = seg_c0[N]; c < seg_c1[N]; ++c) M = fmax(M, part[((size_t)c * nT + t) * stride]);
-                for (int c = seg_c0[N]; c < seg_c1[N]; ++c) {
-                    const double *o = part + ((size_t)c * nT + t) * stride;
-                    if (o[0] == -INFINITY) continue;
-                    const double sc = exp(o[0] - M);
-                    s0 += o[1] * sc;
-                    a += o[2 + k] * sc;
-                }
-                acc += exp((double)N * lz + G[N] - lse) * (a / s0);
-            }
+            for (int N = 0; N < nN; ++N)
+                if (P[N] != 0.0) acc += P[N] * ct[(size_t)N * n_obs + k];
             mean[((size_t)t * nMu + m) * n_obs + k] = acc;
         }
+        __syncthreads();
     }
 }
 
@@ -857,15 +854,15 @@ extern "C" int regc_mbar_observables(regc_mbar *mb, const regc_grid *targets, do
     DevBuf<double> tb_d, tz_d, part, cond_d, mean_d;
     int rc;
     if ((rc = tb_d.alloc(nT)) || (rc = tz_d.alloc(nK)) || (rc = part.alloc((size_t)mb->nchunks * nT * (no + 2))) ||
-        (rc = cond_d.alloc(cond ? (size_t)nT * mb->nN * no : 1)) || (rc = mean_d.alloc(mean ? (size_t)nK * no : 1)))
+        (rc = cond_d.alloc((size_t)nT * mb->nN * no)) || (rc = mean_d.alloc(mean ? (size_t)nK * no : 1)))
         return rc;
     REGC_HIP(hipMemcpyAsync(tb_d.p, tb.data(), sizeof(double) * nT, hipMemcpyHostToDevice, s));
     REGC_HIP(hipMemcpyAsync(tz_d.p, tz.data(), sizeof(double) * nK, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(mbar_obs_chunk, dim3(mb->nchunks, nT), dim3(kMbarThreads), 0, s, nT, no, tb_d.p, mb->e_d.p,
                        mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, mb->obs_d.p, part.p);
     REGC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mbar_obs_eval, dim3(nT), dim3(256), sizeof(double) * mb->nN, s, nT, nMu, mb->nN, no, part.p,
-                       mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d.p, cond ? cond_d.p : nullptr, mean ? mean_d.p : nullptr);
+    hipLaunchKernelGGL(mbar_obs_eval, dim3(nT), dim3(256), 2 * sizeof(double) * mb->nN, s, nT, nMu, mb->nN, no,
+                       part.p, mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d.p, cond_d.p, mean ? mean_d.p : nullptr);
     REGC_HIP(hipGetLastError());
     REGC_HIP(hipStreamSynchronize(s));
     if (cond) REGC_HIP(hipMemcpy(cond, cond_d.p, sizeof(double) * (size_t)nT * mb->nN * no, hipMemcpyDeviceToHost));
