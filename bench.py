@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--burnin", type=int, default=3000, help="untimed equilibration sweeps")
     ap.add_argument("--cpu-sweeps", type=int, default=500, help="oracle sweeps timed for cpu_baseline (0: skip)")
     ap.add_argument("--mbar-records", type=int, default=1000, help="records for the reweighting leg (0: skip)")
+    ap.add_argument("--production-sweeps", type=int, default=100000,
+                    help="sweeps of the production leg: the 1024-replica run sampled every 100 sweeps and "
+                         "reweighted over all its samples (0: skip)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
@@ -230,6 +233,10 @@ def main():
                                             f"workload from the GPU's equilibrated configurations (FP64), "
                                             f"{csec:.1f} s"}
 
+    # ---- production leg: the configuration the metric is quoted on, end to end ----
+    if args.production_sweeps > 0 and args.workload == "c2":
+        result["production"] = production_leg(args, w, wk, prec)
+
     # ---- reweighting leg: 1024 states x mbar-records records ----
     if args.mbar_records > 0 and args.workload == "c2":
         g.close()
@@ -328,6 +335,52 @@ def main():
     if args.full_stack:
         result["full_stack"] = full_stack_leg(args)
     print(json.dumps(result))
+
+
+def production_leg(args, w, wk, prec):
+    """The 1024-replica run at its stated length: production_sweeps sweeps from the
+    benchmark's equilibrated walkers, samples every 100 sweeps (1.024e6 for 1e5
+    sweeps), graph-replayed exchange intervals; then the reweighting of every sample
+    into <N>, the coverage and the phase map on a 64 x 64 grid."""
+    import numpy as np
+    import torch
+
+    from paper_1908_11118_amd import regc
+    from paper_1908_11118_amd import workloads as W
+
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    n_rec = args.production_sweeps // w.sample_every
+    out = {"sweeps": args.production_sweeps, "sample_every": w.sample_every, "records": n_rec}
+    with regc.Regc(w, precision=prec, sample_capacity=max(n_rec, 1) * w.n_states, graph_intervals=10) as g:
+        g.set_walkers(wk["n"], wk["xyz"], label=wk["label"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, chunk = 0, 10000
+        while done < args.production_sweeps:
+            k = min(chunk, args.production_sweeps - done)
+            g.run(k)
+            g.sync()
+            done += k
+            say(f"[production] {done}/{args.production_sweeps} sweeps, {time.perf_counter() - t0:.1f} s")
+        t_run = time.perf_counter() - t0
+        out["seconds"] = t_run
+        out["trial_moves_per_s"] = args.production_sweeps * w.n_states * w.trials / t_run
+        mb = regc.Mbar(w.t, w.mu, w.n_max)
+        skip = n_rec // 10
+        mb.load_run(g, 0, skip)
+        t0 = time.perf_counter()
+        f, conv, iters, delta = mb.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
+        tg = W.linear_grid(0.5, 2.0, 64), W.linear_grid(-8.0, -2.0, 64)
+        tr = mb.targets(*tg)
+        t_mb = time.perf_counter() - t0
+        mb.close()
+    cov = tr["mean_n"] / 64.0                       # 8 x 8 hollow sites of the slab's top layer
+    out["reweighting"] = {"samples": (n_rec - skip) * w.n_states, "iterations": iters, "converged": bool(conv),
+                          "seconds": t_mb, "target_grid": "64 T x 64 mu",
+                          "phases": int(len(set(tr["phase"].tolist()))),
+                          "coverage_range": [float(cov.min()), float(cov.max())]}
+    say(f"[production] {out}")
+    return out
 
 
 def learned_leg(args):
