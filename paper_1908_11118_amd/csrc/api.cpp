@@ -30,7 +30,6 @@ struct ClassHost {
     int S = 0, off = 0, K = 0;
     int bins = 0, ncx = 1, ncy = 1, cap = 0;
     std::vector<double> packed;   // xyz of the packed (binned or plain) slab, 3 per entry
-    std::vector<int16_t> stencil;
 };
 
 struct TimingPair {
@@ -48,7 +47,7 @@ struct regc_ctx {
     int W = 0, nmax_all = 0, kmax = 0, words = 1;
     PotDev potd{};
     hipStream_t stream = nullptr;
-    int wpb = 1, split = 1, nblocks = 0, max_slab_len = 0, max_stencil = 0, max_slab_scan = 0;
+    int wpb = 1, split = 1, nblocks = 0, max_slab_len = 0, max_slab_scan = 0;
     bool cull = false;
     size_t smem = 0;
 
@@ -57,7 +56,6 @@ struct regc_ctx {
     DevBuf<int32_t> n_d, label_d, wos_d;
     DevBuf<double> e_d, xyz_d, beta_d, lnz_d, lnk_d, slab4_d, unb_d;
     DevBuf<float> slab4f_d;
-    DevBuf<int16_t> stencil_d;
     DevBuf<double> samp_e;
     DevBuf<int32_t> samp_n, samp_s;
     int64_t rec_cap = 0, rec_base = 0, n_rec = 0;
@@ -203,7 +201,6 @@ static void pack_slab(ClassHost &c, const regc_potential *pot, const regc_opts *
     const bool bins = ns > 0 && ncx >= 3 && ncy >= 3 && o->slab_bins >= 0;
     c.bins = bins ? 1 : 0;
     c.packed.clear();
-    c.stencil.clear();
     if (!bins) {
         c.ncx = c.ncy = 1;
         c.cap = ns;
@@ -236,11 +233,6 @@ static void pack_slab(ClassHost &c, const regc_potential *pot, const regc_opts *
                 d[0] = 0.0; d[1] = 0.0; d[2] = -1.0e4;   // padding, beyond any cutoff
             }
         }
-    for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
-                    c.stencil.push_back((int16_t)(((cy + dy + ncy) % ncy) * ncx + (cx + dx + ncx) % ncx));
 }
 
 static int upload(void *dst, const void *src, size_t bytes)
@@ -286,13 +278,12 @@ static int ctx_alloc_and_init(regc_ctx *c)
     pd.hc2_gs = (p.hc_frac * p.sig_gs) * (p.hc_frac * p.sig_gs);
     pd.ideal = p.mode == REGC_MODE_IDEAL;
 
-    // per-class device constants, packed slabs, stencils
+    // per-class device constants, packed slabs
     std::vector<ClassDev> cd(n_class);
     std::vector<double> slab4, unb4;
     std::vector<float> slab4f;
-    std::vector<int16_t> stencil;
     std::vector<int> unb_off(n_class), unb_len(n_class);
-    int max_slab_len = 0, max_stencil = 0;
+    int max_slab_len = 0;
     for (int k = 0; k < n_class; ++k) {
         ClassHost &h = c->cls[k];
         ClassDev &d = cd[k];
@@ -324,14 +315,10 @@ static int ctx_alloc_and_init(regc_ctx *c)
         d.bins = h.bins; d.ncx = h.ncx; d.ncy = h.ncy; d.cap = h.cap;
         d.inv_cw_x = h.bins ? h.ncx / h.sys.lx : 0.0;
         d.inv_cw_y = h.bins ? h.ncy / h.sys.ly : 0.0;
-        d.stencil_off = (int)stencil.size();
-        stencil.insert(stencil.end(), h.stencil.begin(), h.stencil.end());
         max_slab_len = std::max(max_slab_len, len);
         c->max_slab_scan = std::max(c->max_slab_scan, h.bins ? 9 * h.cap : len);
-        max_stencil = std::max(max_stencil, (int)h.stencil.size());
     }
     c->max_slab_len = max_slab_len;
-    c->max_stencil = max_stencil;
 
     // launch shape: walkers per block, waves per walker, LDS
     int dev = 0;
@@ -346,7 +333,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
     (void)n_cu;
     const bool cull = o.cull > 0;
     auto smem_for = [&](int wpb) {
-        return lds_layout(max_slab_len, max_stencil, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
+        return lds_layout(max_slab_len, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
     };
     int wpb = split == 2 ? 1 : o.walkers_per_block;
     if (wpb == 0) wpb = W >= 1024 ? 4 : 1;
@@ -413,7 +400,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->xyz_d.alloc((size_t)W * nmax * 3)) || (rc = c->beta_d.alloc(W)) || (rc = c->lnz_d.alloc(W)) ||
         (rc = c->lnk_d.alloc(nmax + 2)) || (rc = c->slab4_d.alloc(slab4.size())) ||
         (rc = c->slab4f_d.alloc(slab4f.size())) || (rc = c->unb_d.alloc(unb4.size())) ||
-        (rc = c->stencil_d.alloc(stencil.size())) || (rc = c->samp_e.alloc((size_t)rec_cap * W)) ||
+        (rc = c->samp_e.alloc((size_t)rec_cap * W)) ||
         (rc = c->samp_n.alloc((size_t)rec_cap * W)) || (rc = c->samp_s.alloc((size_t)rec_cap * W)) ||
         (rc = c->hist_d.alloc((size_t)W * (nmax + 1))) || (rc = c->stats_d.alloc((size_t)W * kNStat)) ||
         (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) || (rc = c->pairs_d.alloc(2)) ||
@@ -439,8 +426,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = upload(c->lnk_d.p, lnk.data(), sizeof(double) * lnk.size())) ||
         (rc = upload(c->slab4_d.p, slab4.data(), sizeof(double) * slab4.size())) ||
         (rc = upload(c->slab4f_d.p, slab4f.data(), sizeof(float) * slab4f.size())) ||
-        (rc = upload(c->unb_d.p, unb4.data(), sizeof(double) * unb4.size())) ||
-        (rc = upload(c->stencil_d.p, stencil.data(), sizeof(int16_t) * stencil.size())))
+        (rc = upload(c->unb_d.p, unb4.data(), sizeof(double) * unb4.size())))
         return rc;
     REGC_HIP(hipMemset(c->n_d.p, 0, sizeof(int32_t) * W));
     REGC_HIP(hipMemset(c->e_d.p, 0, sizeof(double) * W));
@@ -562,7 +548,6 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     a.lnk = c->lnk_d.p;
     a.slab4 = c->slab4_d.p;
     a.slab4f = c->slab4f_d.p;
-    a.stencil = c->stencil_d.p;
     a.key0 = (uint32_t)c->opts.seed;
     a.key1 = (uint32_t)(c->opts.seed >> 32);
     a.th_disp = (uint64_t)std::llround(c->opts.p_disp * 4294967296.0);
@@ -586,7 +571,6 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     a.trace_cap = c->trace_cap;
     a.trace_words = c->words;
     a.max_slab_len = c->max_slab_len;
-    a.max_stencil = c->max_stencil;
     a.gas_stride = c->nmax_all;
     a.max_slab_scan = c->max_slab_scan;
     int rc;
@@ -925,7 +909,7 @@ static int set_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
     REGC_HIP(hipGetDevice(&dev));
     REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int real = c->opts.precision == REGC_FP64 ? 8 : 4;
-    const size_t smem = learn_lds(c->max_slab_len, c->max_stencil, c->nmax_all, real).total;
+    const size_t smem = learn_lds(c->max_slab_len, c->nmax_all, real).total;
     REGC_CHECK(smem <= (size_t)lds_max, REGC_EUNSUPPORTED, "a walker needs %zu bytes of LDS, the device allows %d",
                smem, lds_max);
     int rc;

@@ -40,16 +40,15 @@ struct LearnArgs {
 // LDS carve of the learned-proposal kernel (one walker per workgroup of kLearnWaves waves).
 constexpr int kLearnWaves = 4;
 struct LearnLds {
-    size_t slab, stencil, lnk, xch, gas, vox, occ, list, part, hid, logit, bias, red, total;
+    size_t slab, lnk, xch, gas, vox, occ, list, part, hid, logit, bias, red, total;
 };
 
-__host__ __device__ inline LearnLds learn_lds(int max_slab_len, int max_stencil, int gas_stride, int real_size)
+__host__ __device__ inline LearnLds learn_lds(int max_slab_len, int gas_stride, int real_size)
 {
     LearnLds L;
     const size_t r4 = 4 * (size_t)real_size;
     size_t off = 0;
     L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
-    L.stencil = off; off = lds_round(off + (size_t)max_stencil * 2);
     L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
     L.xch = off;     off = lds_round(off + (size_t)2 * kLearnWaves * 2 * 8);
     L.gas = off;     off = lds_round(off + (size_t)gas_stride * r4);

@@ -469,9 +469,8 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     const ClassDev &C = a.cls[cid];
     const NetDev &net = l.net[cid];
     const double alpha = l.alpha[cid];
-    const LearnLds L = learn_lds(a.max_slab_len, a.max_stencil, a.gas_stride, (int)sizeof(Real));
+    const LearnLds L = learn_lds(a.max_slab_len, a.gas_stride, (int)sizeof(Real));
     Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
-    int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
     double *lnk = reinterpret_cast<double *>(smem + L.lnk);
     double *xch = reinterpret_cast<double *>(smem + L.xch);          // [parity][wave][value, core]
     Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas);
@@ -512,8 +511,6 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
         v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
         slab[k] = v;
     }
-    const int n_st = C.bins ? C.ncx * C.ncy * 9 : 0;
-    for (int k = tid; k < n_st; k += kLT) stencil[k] = a.stencil[C.stencil_off + k];
     for (int k = tid; k < a.gas_stride + 2; k += kLT) lnk[k] = a.lnk[k];
     for (int k = tid; k < kNetNV; k += kLT) occ[k] = 0u;
 
@@ -559,7 +556,7 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     gs.rc2 = gg.rc2; gs.hc2 = (Real)a.pot.hc2_gs;
     const bool ideal = a.pot.ideal != 0;
     SlabView sv;
-    sv.atoms = slab; sv.stencil = stencil; sv.len = slab_len; sv.bins = C.bins;
+    sv.atoms = slab; sv.len = slab_len; sv.bins = C.bins;
     sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
     sv.inv_cap = C.bins ? 1.0f / (float)C.cap : 0.f;
     sv.inv_cw_x = (Real)C.inv_cw_x; sv.inv_cw_y = (Real)C.inv_cw_y;

@@ -28,7 +28,6 @@ struct ClassDev {
     int bins;                // 0/1
     int ncx, ncy, cap;
     double inv_cw_x, inv_cw_y;
-    int stencil_off;         // offset into the stencil table: ncx*ncy*9 column ids
 };
 
 // Pair-potential constants, precomputed on the host.
@@ -56,7 +55,6 @@ struct SweepArgs {
     const double *lnk;           // log(k), k = 0 .. max n_max + 1
     const double *slab4;         // packed slab as double4 (FP64 kernels)
     const float *slab4f;         // packed slab as float4 (FP32 kernels)
-    const int16_t *stencil;      // column stencil tables
     uint32_t key0, key1;
     uint64_t th_disp, th_ins;
     double max_disp;
@@ -75,7 +73,7 @@ struct SweepArgs {
     int32_t *trace_n;
     int64_t trace_sweep0, trace_cap;
     int trace_words;
-    int max_slab_len, max_stencil;  // LDS carve sizes of this launch
+    int max_slab_len;               // LDS carve sizes of this launch
     int gas_stride;                 // LDS entries per walker (max n_max over classes)
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
 };
@@ -155,22 +153,21 @@ struct EnergyArgs {
 };
 
 // LDS carve of the sweep kernel (byte offsets, 32-byte aligned), shared by the
-// kernel and the host launch code: class slab, stencil table, ln k table, the
+// kernel and the host launch code: class slab, ln k table, the
 // split-walker exchange slots, the walkers' gas coordinates, the pair queues.
 struct LdsLayout {
-    size_t slab, stencil, lnk, xch, gas, queue, total;
+    size_t slab, lnk, xch, gas, queue, total;
 };
 
 __host__ __device__ inline size_t lds_round(size_t x) { return (x + 31) & ~(size_t)31; }
 
-__host__ __device__ inline LdsLayout lds_layout(int max_slab_len, int max_stencil, int gas_stride, int max_slab_scan,
-                                                int walkers, int queue_waves, int real_size)
+__host__ __device__ inline LdsLayout lds_layout(int max_slab_len, int gas_stride, int max_slab_scan, int walkers,
+                                                int queue_waves, int real_size)
 {
     LdsLayout L;
     const size_t r4 = 4 * (size_t)real_size;
     size_t off = 0;
     L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
-    L.stencil = off; off = lds_round(off + (size_t)max_stencil * 2);
     L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
     L.xch = off;     off = lds_round(off + (size_t)walkers * 8 * 8);
     L.gas = off;     off = lds_round(off + (size_t)walkers * gas_stride * r4);

@@ -19,8 +19,8 @@
 //   removal, Eq. (2): ln A = ln N - ln z - ln V - beta dE;
 //   accept when U53 <= min(1, A), evaluated as dE <= (ln prefactor - ln U) / beta.
 // dE sums LJ pair terms of the moved particle over the other gas atoms and over
-// the slab atoms (all of them, or the 3x3 stencil of x-y columns around the
-// particle).  Storage rule: insertion appends, removal moves the last particle
+// the slab atoms (all of them, or those of the 3x3 block of x-y columns around
+// the particle).  Storage rule: insertion appends, removal moves the last particle
 // into the freed slot.
 //
 // Launch variants (template parameters):
@@ -64,17 +64,16 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     const ClassDev &C = a.cls[cid];
     const int nw = a.block_nw[blk];
 
-    const LdsLayout L = lds_layout(a.max_slab_len, a.max_stencil, a.gas_stride, a.max_slab_scan, waves / SPLIT,
+    const LdsLayout L = lds_layout(a.max_slab_len, a.gas_stride, a.max_slab_scan, waves / SPLIT,
                                    CULL ? waves : 0, (int)sizeof(Real));
     Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
-    int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
     double *lnk = reinterpret_cast<double *>(smem + L.lnk);
     double *xch = reinterpret_cast<double *>(smem + L.xch) + slot * 8;     // [parity][part][value, core]
     Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)slot * a.gas_stride;
     Real *qgas = reinterpret_cast<Real *>(smem + L.queue) + (size_t)wave * (2 * a.gas_stride + 2 * a.max_slab_scan);
     Real *qslab = qgas + 2 * a.gas_stride;
 
-    // ---- class slab, stencil and log table into LDS (shared by the block) ----
+    // ---- class slab and log table into LDS (shared by the block) ----
     const int slab_len = C.slab_len;
     for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
 #if defined(REGC_FP64)
@@ -86,8 +85,6 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
         v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
         slab[k] = v;
     }
-    const int n_st = C.bins ? C.ncx * C.ncy * 9 : 0;
-    for (int k = threadIdx.x; k < n_st; k += blockDim.x) stencil[k] = a.stencil[C.stencil_off + k];
     for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
     __syncthreads();
     if (slot >= nw) return;    // (SPLIT == 2 blocks always hold one walker)
@@ -125,7 +122,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     gs.shift = in_vgpr((Real)a.pot.shift_gs); gs.rc2 = gg.rc2; gs.hc2 = in_vgpr((Real)a.pot.hc2_gs);
     const bool ideal = a.pot.ideal != 0;
     SlabView sv;
-    sv.atoms = slab; sv.stencil = stencil; sv.len = slab_len; sv.bins = C.bins;
+    sv.atoms = slab; sv.len = slab_len; sv.bins = C.bins;
     sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
     sv.inv_cap = in_vgpr(C.bins ? 1.0f / (float)C.cap : 0.f);
     sv.inv_cw_x = in_vgpr((Real)C.inv_cw_x); sv.inv_cw_y = in_vgpr((Real)C.inv_cw_y);
@@ -447,10 +444,9 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
     const ClassDev &C = a.cls[0];
     const int nw = a.block_nw[blk];
 
-    const LdsLayout L = lds_layout(a.max_slab_len, a.max_stencil, a.gas_stride, a.max_slab_scan, waves, 0,
+    const LdsLayout L = lds_layout(a.max_slab_len, a.gas_stride, a.max_slab_scan, waves, 0,
                                    (int)sizeof(Real));
     Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
-    int16_t *stencil = reinterpret_cast<int16_t *>(smem + L.stencil);
     double *lnk = reinterpret_cast<double *>(smem + L.lnk);
     Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)wave * a.gas_stride;
     const bool use_md = pa.md_steps > 0;
@@ -468,8 +464,6 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
         v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
         slab[k] = v;
     }
-    const int n_st = C.bins ? C.ncx * C.ncy * 9 : 0;
-    for (int k = threadIdx.x; k < n_st; k += blockDim.x) stencil[k] = a.stencil[C.stencil_off + k];
     for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
     __syncthreads();
     if (wave >= nw) return;
@@ -506,7 +500,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) paper_kernel(Swee
     gs.rc2 = gg.rc2; gs.hc2 = (Real)a.pot.hc2_gs;
     const bool ideal = a.pot.ideal != 0;
     SlabView sv;
-    sv.atoms = slab; sv.stencil = stencil; sv.len = slab_len; sv.bins = C.bins;
+    sv.atoms = slab; sv.len = slab_len; sv.bins = C.bins;
     sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
     sv.inv_cap = C.bins ? 1.0f / (float)C.cap : 0.f;
     sv.inv_cw_x = (Real)C.inv_cw_x; sv.inv_cw_y = (Real)C.inv_cw_y;

@@ -143,10 +143,10 @@ __device__ __forceinline__ double bcast(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// Slab access: all atoms, or the 3x3 column stencil around a column.
+// Slab access: all atoms, or the 3x3 block of x-y columns around a column
+// (periodic in x and y; column ids row-major, y outer).
 struct SlabView {
     const Real4 *atoms;
-    const int16_t *stencil;   // [ncol][9]
     int len;                  // entries when unbinned
     int bins, ncx, ncy, cap;
     float inv_cap;
@@ -154,13 +154,24 @@ struct SlabView {
     Real top_plus_rc;
 };
 
-__device__ __forceinline__ int column_of(const SlabView &sv, Real x, Real y)
+// Column (cx, cy) of a position, clamped to the grid; the caller's position is
+// wave-uniform, so the result is moved to scalar registers.
+__device__ __forceinline__ void column_of(const SlabView &sv, Real x, Real y, int &cx, int &cy)
 {
-    int cx = (int)(x * sv.inv_cw_x);
-    int cy = (int)(y * sv.inv_cw_y);
-    cx = cx < 0 ? 0 : (cx >= sv.ncx ? sv.ncx - 1 : cx);
-    cy = cy < 0 ? 0 : (cy >= sv.ncy ? sv.ncy - 1 : cy);
-    return cy * sv.ncx + cx;
+    const int ix = (int)(x * sv.inv_cw_x);
+    const int iy = (int)(y * sv.inv_cw_y);
+    cx = __builtin_amdgcn_readfirstlane(ix < 0 ? 0 : (ix >= sv.ncx ? sv.ncx - 1 : ix));
+    cy = __builtin_amdgcn_readfirstlane(iy < 0 ? 0 : (iy >= sv.ncy ? sv.ncy - 1 : iy));
+}
+
+// Periodic neighbour c + d (d in -1..1) of a column index in [0, nc): as an
+// unsigned value, -1 wraps to the largest integer and min() picks nc - 1, and
+// nc becomes 0 the same way.
+__device__ __forceinline__ uint32_t wrap_col(int c, int d, int nc)
+{
+    uint32_t u = (uint32_t)(c + d);
+    u = min(u, u + (uint32_t)nc);
+    return min(u, u - (uint32_t)nc);
 }
 
 // Appends the lanes' values whose predicate holds to an LDS queue (wave-wide
@@ -237,22 +248,33 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
     const Real zmin = (NEW && OLD) ? (pz < qz ? pz : qz) : (NEW ? pz : qz);
     if (zmin < sv.top_plus_rc) {
         const bool bins = sv.bins != 0;
-        const int16_t *st = sv.stencil + (bins ? column_of(sv, OLD ? qx : px, OLD ? qy : py) * 9 : 0);
         const int total = bins ? 9 * sv.cap : sv.len;
+        int cx = 0, cy = 0;
+        if (bins) column_of(sv, OLD ? qx : px, OLD ? qy : py, cx, cy);
+        // All U loads of a step are issued before the pair terms; entry kk of
+        // the 9 * cap scanned is slot kk % cap of the block's column sp = kk / cap,
+        // sp = 3 * (dy + 1) + (dx + 1).
         for (int k0 = part * U * kWave; k0 < total; k0 += STEP) {
+            Real4 g[U];
+            bool vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = k0 + u * kWave + lane;
-                const bool v = k < total;
-                const int kk = v ? k : 0;
+                vv[u] = k < total;
+                const int kk = vv[u] ? k : 0;
                 int idx = kk;
                 if (bins) {
                     const int sp = (int)(((float)kk + 0.5f) * sv.inv_cap);
-                    idx = (int)st[sp] * sv.cap + (kk - sp * sv.cap);
+                    const int q = (sp * 11) >> 5;   // sp / 3 for sp in 0..8
+                    const uint32_t ux = wrap_col(cx, sp - 3 * q - 1, sv.ncx);
+                    const uint32_t uy = wrap_col(cy, q - 1, sv.ncy);
+                    idx = (int)((uy * (uint32_t)sv.ncx + ux) * (uint32_t)sv.cap) + (kk - sp * sv.cap);
                 }
-                const Real4 g = sv.atoms[idx];
-                candidate<NEW, OLD, CULL>(b, gs, v, g, px, py, pz, qx, qy, qz, acc, core, useful, qslab, ns);
+                g[u] = sv.atoms[idx];
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                candidate<NEW, OLD, CULL>(b, gs, vv[u], g[u], px, py, pz, qx, qy, qz, acc, core, useful, qslab, ns);
         }
     }
     core_out = __any(core);
