@@ -182,8 +182,9 @@ void regc_default_opts(regc_opts *o);
 
 /* Creates a context for one REGC simulation on the current HIP device: all
  * walkers start empty (N = 0, E = 0) with label[w] = w (a reading; the paper
- * does not state the initial state).  EINVAL on bad sizes, T <= 0, lx or ly
- * below 2 rcut, p_ins != removal probability, z_hi <= z_lo.
+ * does not state the initial state).  EINVAL on bad sizes, T <= 0, a T or mu
+ * that is not finite, lx or ly below 2 rcut, p_ins != removal probability,
+ * z_hi <= z_lo.
  * EUNSUPPORTED for an unknown mode or precision. */
 int regc_create(const regc_potential *pot, const regc_system *sys, const regc_grid *grid,
                 const regc_opts *opts, regc_ctx **out);

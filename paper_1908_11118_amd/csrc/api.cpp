@@ -164,7 +164,9 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(pot->rcut > 0 && pot->sig_gg > 0 && pot->sig_gs > 0 && pot->hc_frac >= 0, REGC_EINVAL,
                "rcut and sigmas must be positive");
     REGC_CHECK(grid->n_t > 0 && grid->n_mu > 0 && grid->t && grid->mu, REGC_EINVAL, "empty state grid");
-    for (int l = 0; l < grid->n_t; ++l) REGC_CHECK(grid->t[l] > 0, REGC_EINVAL, "T must be positive");
+    for (int l = 0; l < grid->n_t; ++l)
+        REGC_CHECK(std::isfinite(grid->t[l]) && grid->t[l] > 0, REGC_EINVAL, "T must be positive and finite");
+    for (int m = 0; m < grid->n_mu; ++m) REGC_CHECK(std::isfinite(grid->mu[m]), REGC_EINVAL, "mu must be finite");
     REGC_CHECK(sys->n_max >= 1 && sys->n_max <= 4095, REGC_EINVAL, "n_max must be in 1..4095");
     REGC_CHECK(sys->lx >= 2 * pot->rcut && sys->ly >= 2 * pot->rcut, REGC_EINVAL, "lx, ly must be >= 2 rcut");
     REGC_CHECK(sys->z_hi > sys->z_lo, REGC_EINVAL, "z_hi must exceed z_lo");

@@ -53,6 +53,15 @@ def test_default_opts_and_errors_without_gpu():
     assert L.regc_create(ctypes.byref(pot), ctypes.byref(sys_), ctypes.byref(g), ctypes.byref(o),
                          ctypes.byref(h)) == regc.EINVAL
     L.regc_default_opts(ctypes.byref(o))
+    mu_nan = (ctypes.c_double * 1)(float("nan"))                 # non-finite mu, then T
+    g_bad = regc.Grid(1, 1, t, mu_nan)
+    assert L.regc_create(ctypes.byref(pot), ctypes.byref(sys_), ctypes.byref(g_bad), ctypes.byref(o),
+                         ctypes.byref(h)) == regc.EINVAL
+    assert b"mu" in L.regc_last_error()
+    t_inf = (ctypes.c_double * 1)(float("inf"))
+    g_bad = regc.Grid(1, 1, t_inf, t)
+    assert L.regc_create(ctypes.byref(pot), ctypes.byref(sys_), ctypes.byref(g_bad), ctypes.byref(o),
+                         ctypes.byref(h)) == regc.EINVAL
     pot.mode = 2                                                 # site lattice: oracle only
     assert L.regc_create(ctypes.byref(pot), ctypes.byref(sys_), ctypes.byref(g), ctypes.byref(o),
                          ctypes.byref(h)) == regc.EUNSUPPORTED
