@@ -291,7 +291,9 @@ int regc_mbar_set_stream(regc_mbar *mb, void *stream);
 
 /* Loads ns samples (E, N, state).  With on_device != 0 the three pointers are
  * device addresses (read during the call); otherwise host.  N outside 0..n_max
- * or a state outside the grid gives EINVAL. */
+ * or a state outside the grid gives EINVAL.  The call replaces earlier samples,
+ * their solution and observables; after a failed call the handle holds none
+ * (regc_mbar_solve then returns ESTATE). */
 int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e, const int32_t *n,
                           const int32_t *state, int on_device);
 
@@ -353,7 +355,8 @@ int regc_observables_device(regc_ctx *ctx, const uint32_t **obs_dev, int *n_obs)
 int regc_get_observables(regc_ctx *ctx, uint32_t *obs, int64_t cap_records, int64_t *n_out);
 /* Observables of the samples given to regc_mbar_set_samples, same order, obs
  * [ns][n_obs] uint32 (host, or device when on_device).  regc_mbar_load_run loads
- * them with the samples when the run recorded observables. */
+ * them with the samples when the run recorded observables.  After a failed call
+ * the handle holds no observables. */
 int regc_mbar_set_observables(regc_mbar *mb, const uint32_t *obs, int n_obs, int on_device);
 /* Reweighted observables on a target grid (after regc_mbar_solve): mean
  * [nT*nMu][n_obs] = sum_n w_n(t) obs_n; cond [nT][n_max+1][n_obs] = the average

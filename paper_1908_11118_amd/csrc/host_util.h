@@ -59,4 +59,17 @@ struct DevBuf {
     DevBuf &operator=(const DevBuf &) = delete;
 };
 
+// A HIP event destroyed with its scope (also on early error returns).
+struct ScopedEvent {
+    hipEvent_t e = nullptr;
+    hipError_t create() { return hipEventCreate(&e); }
+    ~ScopedEvent()
+    {
+        if (e) (void)hipEventDestroy(e);
+    }
+    ScopedEvent() = default;
+    ScopedEvent(const ScopedEvent &) = delete;
+    ScopedEvent &operator=(const ScopedEvent &) = delete;
+};
+
 }  // namespace regc

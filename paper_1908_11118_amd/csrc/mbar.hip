@@ -503,6 +503,11 @@ extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e,
     REGC_CHECK(mb, REGC_EINVAL, "null handle");
     REGC_CHECK(ns > 0 && e && n && state, REGC_EINVAL, "no samples");
     REGC_CHECK(ns < (int64_t)1 << 31, REGC_EUNSUPPORTED, "more than 2^31 - 1 samples");
+    // the handle's sample buffers are replaced below: until this call succeeds the
+    // handle holds no samples (a failed call leaves it empty, not half updated)
+    mb->have_samples = false;
+    mb->solved = false;
+    mb->n_obs = 0;
     hipStream_t s = mb->stream;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     DevBuf<double> e_in;
@@ -583,8 +588,6 @@ extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e,
     REGC_HIP(hipStreamSynchronize(s));
     mb->ns = ns;
     mb->have_samples = true;
-    mb->solved = false;
-    mb->n_obs = 0;
     return REGC_OK;
 }
 
@@ -689,10 +692,10 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     REGC_CHECK(max_iter > 0 && tol > 0, REGC_EINVAL, "max_iter and tol must be positive");
     hipStream_t s = mb->stream;
     REGC_HIP(hipMemsetAsync(mb->f_d.p, 0, sizeof(double) * mb->S, s));
-    hipEvent_t e0, e1;
-    REGC_HIP(hipEventCreate(&e0));
-    REGC_HIP(hipEventCreate(&e1));
-    REGC_HIP(hipEventRecord(e0, s));
+    ScopedEvent e0, e1;
+    REGC_HIP(e0.create());
+    REGC_HIP(e1.create());
+    REGC_HIP(hipEventRecord(e0.e, s));
     std::vector<int> idx;
     for (int k = 0; k < mb->S; ++k)
         if (mb->lnomega[k] != -INFINITY) idx.push_back(k);
@@ -752,7 +755,7 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
         x = xn;
         REGC_HIP(hipMemcpyAsync(mb->f_d.p, x.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
     }
-    REGC_HIP(hipEventRecord(e1, s));
+    REGC_HIP(hipEventRecord(e1.e, s));
     // f_d holds g of the last iterate; log D consistent with it
     hipLaunchKernelGGL(mbar_loga, dim3(mb->L), dim3(256), 0, s, mb->M, mb->nN, mb->lnomega_d.p, mb->f_d.p,
                        mb->lnz_d.p, mb->logA_d.p);
@@ -760,9 +763,7 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     REGC_HIP(launch_chunk(mb, mb->logd_d.p));
     REGC_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
-    REGC_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    REGC_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
     mb->ms_iter = ms;
     mb->n_iter = it;
     if (f_out) REGC_HIP(hipMemcpy(f_out, mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
@@ -821,6 +822,7 @@ extern "C" int regc_mbar_set_observables(regc_mbar *mb, const uint32_t *obs, int
     REGC_CHECK(mb && obs, REGC_EINVAL, "null argument");
     REGC_CHECK(mb->have_samples, REGC_ESTATE, "set the samples first");
     REGC_CHECK(n_obs > 0 && n_obs <= 4096, REGC_EINVAL, "n_obs must be 1..4096");
+    mb->n_obs = 0;     // no observables until this call succeeds
     hipStream_t s = mb->stream;
     const size_t count = (size_t)mb->ns * n_obs;
     DevBuf<uint32_t> in;

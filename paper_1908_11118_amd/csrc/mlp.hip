@@ -542,10 +542,10 @@ extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const u
     hipStream_t s = h->stream;
     DevBuf<float> lsum;
     if ((rc = lsum.alloc(batch))) return rc;
-    hipEvent_t e0, e1;
-    REGC_HIP(hipEventCreate(&e0));
-    REGC_HIP(hipEventCreate(&e1));
-    REGC_HIP(hipEventRecord(e0, s));
+    ScopedEvent e0, e1;
+    REGC_HIP(e0.create());
+    REGC_HIP(e1.create());
+    REGC_HIP(hipEventRecord(e0.e, s));
     const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
     double loss_acc = 0.0;
     std::vector<float> lh(batch);
@@ -567,12 +567,10 @@ extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const u
             loss_acc = a / batch;
         }
     }
-    REGC_HIP(hipEventRecord(e1, s));
-    REGC_HIP(hipEventSynchronize(e1));
+    REGC_HIP(hipEventRecord(e1.e, s));
+    REGC_HIP(hipEventSynchronize(e1.e));
     float ms = 0.f;
-    REGC_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    REGC_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
     h->ms_train += ms;
     h->steps_timed += steps;
     if (mean_loss) *mean_loss = loss_acc;

@@ -333,6 +333,35 @@ def test_mbar_matches_oracle(method):
     mb.close()
 
 
+def test_mbar_failed_reload_leaves_no_samples():
+    """A rejected sample set replaces the handle's earlier samples by none: the
+    solve then refuses (ESTATE) instead of running on half-replaced buffers, and a
+    valid reload gives the earlier solution again."""
+    w = W.small_lj(n_t=2, n_mu=2, n_max=10)
+    rng = np.random.default_rng(3)
+    ns = 400
+    e = rng.normal(size=ns)
+    n = rng.integers(0, w.n_max + 1, ns)
+    st = rng.integers(0, 4, ns)
+    _say("[mbar] failed reload")
+    mb = regc.Mbar(w.t, w.mu, w.n_max)
+    mb.set_samples(e, n, st)
+    f1, conv, _, _ = mb.solve(tol=1e-10)
+    assert conv
+    bad = st[:100].copy()
+    bad[-1] = 4                                   # outside the 2 x 2 grid
+    with pytest.raises(regc.RegcError) as ei:
+        mb.set_samples(e[:100], n[:100], bad)
+    assert ei.value.code == regc.EINVAL
+    with pytest.raises(regc.RegcError) as ei:
+        mb.solve(tol=1e-10)
+    assert ei.value.code == regc.ESTATE
+    mb.set_samples(e, n, st)
+    f2, conv, _, _ = mb.solve(tol=1e-10)
+    assert conv and np.allclose(f1, f2, atol=1e-12)
+    mb.close()
+
+
 def test_mbar_ideal_gas_iid_samples():
     """GPU reweighting of i.i.d. truncated-Poisson samples against the oracle on the
     same samples, with an unsampled state and an empty N segment."""
