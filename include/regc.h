@@ -276,7 +276,10 @@ int regc_timing_get(regc_ctx *ctx, double *ms_sweep, int64_t *n_sweep, double *m
 
 /* Serialises the complete sampling state (walkers, labels, sweep counter,
  * counters) into buf.  With buf == NULL only *size is set.  Samples and traces
- * are not included.  restore requires a context created with the same inputs. */
+ * are not included.  restore requires a context created with the same inputs
+ * (EINVAL otherwise) and rejects, before changing anything, a buffer whose N
+ * lie outside 0..n_max or whose labels are not a permutation of the class's
+ * states matching its walker-of-state table. */
 int regc_checkpoint(regc_ctx *ctx, void *buf, size_t cap, size_t *size);
 int regc_restore(regc_ctx *ctx, const void *buf, size_t size);
 

@@ -1368,8 +1368,24 @@ extern "C" int regc_restore(regc_ctx *c, const void *buf, size_t size)
     REGC_CHECK(h.magic == kMagic && h.version == 1 && h.W == (uint32_t)c->W && h.nmax == (uint32_t)c->nmax_all &&
                    h.n_class == (uint32_t)c->cls.size() && h.seed == c->opts.seed,
                REGC_EINVAL, "checkpoint was written by a different context");
-    REGC_HIP(hipStreamSynchronize(c->stream));
     const size_t W = c->W;
+    {
+        // the kernels index LDS by N and the state arrays by label: check both, and
+        // that walker-of-state inverts the labels, before anything reaches the device
+        std::vector<int32_t> nn(W), lab(W), wos(W);
+        std::memcpy(nn.data(), p, W * 4);
+        std::memcpy(lab.data(), p + W * 12, W * 4);
+        std::memcpy(wos.data(), p + W * 16, W * 4);
+        REGC_CHECK(h.sweep >= 0, REGC_EINVAL, "checkpoint holds a negative sweep count");
+        for (const ClassHost &k : c->cls)
+            for (int w = k.off; w < k.off + k.S; ++w) {
+                REGC_CHECK(nn[w] >= 0 && nn[w] <= k.sys.n_max, REGC_EINVAL, "checkpoint: N = %d of walker %d outside 0..%d",
+                           nn[w], w, k.sys.n_max);
+                REGC_CHECK(lab[w] >= 0 && lab[w] < k.S && wos[k.off + lab[w]] == w, REGC_EINVAL,
+                           "checkpoint: label %d of walker %d is not a state of its class held by it", lab[w], w);
+            }
+    }
+    REGC_HIP(hipStreamSynchronize(c->stream));
     REGC_HIP(hipMemcpy(c->n_d.p, p, W * 4, hipMemcpyHostToDevice)); p += W * 4;
     REGC_HIP(hipMemcpy(c->e_d.p, p, W * 8, hipMemcpyHostToDevice)); p += W * 8;
     REGC_HIP(hipMemcpy(c->label_d.p, p, W * 4, hipMemcpyHostToDevice)); p += W * 4;

@@ -6,6 +6,7 @@ per-configuration energies within 1e-5 relative of the FP64 oracle, long-run <N>
 within 3 standard errors.  Reweighting: free energies and reweighted averages
 against the naive FP64 oracle."""
 import math
+import struct
 import sys
 
 import numpy as np
@@ -177,6 +178,16 @@ def test_checkpoint_restore_continues_identically():
         ref = a.walkers()
         ref_st = a.stats()
     with regc.Regc(w) as b:
+        # corrupted buffers are rejected before anything changes: header of 40 bytes,
+        # then N (int32 per walker), E (float64), labels (int32), walker of state (int32)
+        nw = len(w.t) * len(w.mu)
+        for off, value in ((40, w.n_max + 1), (40 + 12 * nw, struct.unpack_from("<i", blob, 40 + 12 * nw + 4)[0])):
+            bad = bytearray(blob)
+            struct.pack_into("<i", bad, off, value)
+            with pytest.raises(regc.RegcError) as ei:
+                b.restore(bytes(bad))
+            assert ei.value.code == regc.EINVAL
+            assert b.sweep == 0
         b.restore(blob)
         assert b.sweep == 50
         b.run(70)
