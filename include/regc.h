@@ -415,7 +415,9 @@ int regc_mlp_loss_grads(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, con
  * n_dev [n_examples]): example and left-out particle from Philox keyed by seed;
  * an empty configuration is passed over for the next non-empty one (at most 256
  * further; a batch slot left empty adds nothing to the loss or its gradient).
- * mean_loss (may be NULL) receives the last batch's loss (mean over the batch). */
+ * mean_loss (may be NULL) receives the last batch's loss (mean over the batch).
+ * EINVAL, before any step, when an example's N lies outside 0..nmax or one of
+ * its first N voxel indices is 4096 or more (the set is scanned once per call). */
 int regc_mlp_train(regc_mlp *mlp, int64_t n_examples, int nmax, const uint16_t *vox_dev, const int32_t *n_dev,
                    int64_t steps, int batch, double lr, uint64_t seed, double *mean_loss);
 /* Accumulated training time in ms and steps. */

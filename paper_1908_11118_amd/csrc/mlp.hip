@@ -247,6 +247,22 @@ __global__ void make_batch(int B, int nmax, int64_t n_examples, const uint16_t *
     }
 }
 
+// Flags a training set with an N outside 0..nmax or a voxel index >= NV among an
+// example's first N entries (block per example, grid-stride over examples).
+__global__ void check_set(int64_t n_examples, int nmax, const uint16_t *set_vox, const int32_t *set_n, int *bad)
+{
+    for (int64_t ex = blockIdx.x; ex < n_examples; ex += gridDim.x) {
+        const int nb = set_n[ex];
+        if (nb < 0 || nb > nmax) {
+            if (threadIdx.x == 0) *bad = 1;
+            continue;
+        }
+        bool out = false;
+        for (int j = threadIdx.x; j < nb; j += blockDim.x) out |= set_vox[ex * nmax + j] >= NV;
+        if (out) *bad = 1;
+    }
+}
+
 // MFMA B-operand tiles of a [n_out][128] weight matrix (the layout of NetDev):
 // P[((tile*4 + kp)*64 + lane)*8 + j] = W[16 tile + lane%16][32 kp + 16 (j/4) + 4 (lane/16) + j%4]
 __global__ void pack_b_tiles(int n_out, const bf16 *W, bf16 *P)
@@ -537,11 +553,24 @@ extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const u
     REGC_CHECK(h && vox_dev && n_dev, REGC_EINVAL, "null argument");
     REGC_CHECK(n_examples > 0 && steps > 0 && lr > 0, REGC_EINVAL, "bad training size");
     REGC_CHECK(batch > 0 && batch % 64 == 0, REGC_EINVAL, "batch must be a positive multiple of 64");
+    REGC_CHECK(nmax > 0 && nmax <= 65535, REGC_EINVAL, "bad nmax");
     int rc;
     if ((rc = mlp_workspace(h, batch, nmax))) return rc;
     hipStream_t s = h->stream;
     DevBuf<float> lsum;
-    if ((rc = lsum.alloc(batch))) return rc;
+    DevBuf<int> bad;
+    if ((rc = lsum.alloc(batch)) || (rc = bad.alloc(1))) return rc;
+    {
+        // the batch kernels index by N and gather W1 rows by voxel: check the set first
+        int h_bad = 0;
+        REGC_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(check_set, dim3((unsigned)std::min<int64_t>(n_examples, 4096)), dim3(64), 0, s, n_examples,
+                           nmax, vox_dev, n_dev, bad.p);
+        REGC_HIP(hipGetLastError());
+        REGC_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        REGC_HIP(hipStreamSynchronize(s));
+        REGC_CHECK(!h_bad, REGC_EINVAL, "training set: an N outside 0..%d or a voxel index >= %d", nmax, NV);
+    }
     ScopedEvent e0, e1;
     REGC_HIP(e0.create());
     REGC_HIP(e1.create());

@@ -107,3 +107,33 @@ def test_training_lowers_the_loss():
     ms, steps = net.timing()
     _say(f"[mlp] {steps} steps in {ms:.1f} ms")
     net.close()
+
+
+def test_training_rejects_a_bad_set():
+    """A device training set with an N above nmax or a voxel index of 4096 or more
+    among an example's first N entries is refused before any step; entries past N
+    are not looked at."""
+    import torch
+    _say("[mlp] training set checks")
+    rng = np.random.default_rng(6)
+    nmax, ns = 8, 256
+    vox = rng.integers(0, 4096, (ns, nmax)).astype(np.int16)
+    n = np.full(ns, 4, dtype=np.int32)
+    vox[5, 6] = 5000                       # past N = 4: ignored
+    net = regc.Mlp(W.mlp_pack(W.mlp_init(5)))
+    p0 = net.params()
+    for bad_vox, bad_n in ((True, False), (False, True)):
+        v, m = vox.copy(), n.copy()
+        if bad_vox:
+            v[100, 2] = 5000
+        if bad_n:
+            m[7] = nmax + 1
+        vdev, ndev = torch.from_numpy(v).cuda(), torch.from_numpy(m).cuda()
+        with pytest.raises(regc.RegcError) as ei:
+            net.train(ns, nmax, vdev.data_ptr(), ndev.data_ptr(), steps=1, batch=64, lr=1e-3, seed=1)
+        assert ei.value.code == regc.EINVAL
+        assert np.array_equal(net.params(), p0)
+    vdev, ndev = torch.from_numpy(vox).cuda(), torch.from_numpy(n).cuda()
+    net.train(ns, nmax, vdev.data_ptr(), ndev.data_ptr(), steps=1, batch=64, lr=1e-3, seed=1)
+    assert not np.array_equal(net.params(), p0)
+    net.close()
