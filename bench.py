@@ -83,7 +83,8 @@ def main():
     ap.add_argument("--learned-seconds", type=float, default=60.0,
                     help="GPU-time cap of the plain and learned runs of the time-to-accuracy leg (0: skip the leg)")
     ap.add_argument("--schedule-seconds", type=float, default=30.0,
-                    help="GPU-time cap of the runs of that leg with the paper's REGC step (MC and MD forms)")
+                    help="GPU-time cap of the runs of that leg with the paper's REGC step (MC and MD forms; "
+                         "0: skip them)")
     ap.add_argument("--learned-tau", type=float, default=0.5, help="standard-error target (particles) of that leg")
     ap.add_argument("--learned-alpha", type=float, default=0.9, help="mixture weight of the network branch")
     ap.add_argument("--learned-capture", type=int, default=10000, help="plain sweeps per seed captured for training")
@@ -436,32 +437,34 @@ def learned_leg(args):
     say(f"[learned] learned: reached={learned['reached']} t={learned['t_acc_s']:.2f} s sweeps={learned['sweeps']}")
     net.close()
     keep = ("reached", "t_acc_s", "sweeps", "max_se", "frac_within", "chi2", "ins_acc", "ms_per_sweep")
-    # the paper's REGC step (x0 = 0.99, 10 MC cycles of N displacements) from the same state
-    wp = W.paper_schedule(w, x0=0.99, mc_cycles=10, sample_every=1)
-    paper = P.time_to_accuracy(wp, blob, ref_m, ref_se, tau=args.learned_tau, chunk=50,
-                               max_seconds=args.schedule_seconds, log=say)
-    say(f"[learned] paper schedule: reached={paper['reached']} t={paper['t_acc_s']:.2f} s steps={paper['sweeps']}")
-    # the same step with molecular dynamics as the canonical part (REGCMD)
-    wmd = W.paper_schedule_md(w, x0=0.99, md_steps=10, md_dt=0.005, md_tau=0.1, sample_every=1)
-    pmd = P.time_to_accuracy(wmd, blob, ref_m, ref_se, tau=args.learned_tau, chunk=50,
-                             max_seconds=args.schedule_seconds, log=say)
-    say(f"[learned] paper schedule, MD: reached={pmd['reached']} t={pmd['t_acc_s']:.2f} s steps={pmd['sweeps']}")
     out["plain"] = {k: plain[k] for k in keep}
-    out["paper_schedule_md"] = {k: pmd[k] for k in keep}
-    out["paper_schedule_md"]["steps"] = out["paper_schedule_md"].pop("sweeps")
-    out["paper_schedule_md"]["ms_per_step"] = out["paper_schedule_md"].pop("ms_per_sweep")
-    out["paper_schedule_md"].update({"x0": 0.99, "md_steps": 10, "md_dt": 0.005, "md_tau": 0.1})
-    out["paper_schedule"] = {k: paper[k] for k in keep}
-    out["paper_schedule"]["steps"] = out["paper_schedule"].pop("sweeps")
-    out["paper_schedule"]["ms_per_step"] = out["paper_schedule"].pop("ms_per_sweep")
-    out["paper_schedule"]["x0"], out["paper_schedule"]["mc_cycles"] = 0.99, 10
+    if args.schedule_seconds > 0:
+        # the paper's REGC step (x0 = 0.99, 10 MC cycles of N displacements) from the same state
+        wp = W.paper_schedule(w, x0=0.99, mc_cycles=10, sample_every=1)
+        paper = P.time_to_accuracy(wp, blob, ref_m, ref_se, tau=args.learned_tau, chunk=50,
+                                   max_seconds=args.schedule_seconds, log=say)
+        say(f"[learned] paper schedule: reached={paper['reached']} t={paper['t_acc_s']:.2f} s "
+            f"steps={paper['sweeps']}")
+        # the same step with molecular dynamics as the canonical part (REGCMD)
+        wmd = W.paper_schedule_md(w, x0=0.99, md_steps=10, md_dt=0.005, md_tau=0.1, sample_every=1)
+        pmd = P.time_to_accuracy(wmd, blob, ref_m, ref_se, tau=args.learned_tau, chunk=50,
+                                 max_seconds=args.schedule_seconds, log=say)
+        say(f"[learned] paper schedule, MD: reached={pmd['reached']} t={pmd['t_acc_s']:.2f} s steps={pmd['sweeps']}")
+        out["paper_schedule_md"] = {k: pmd[k] for k in keep}
+        out["paper_schedule_md"]["steps"] = out["paper_schedule_md"].pop("sweeps")
+        out["paper_schedule_md"]["ms_per_step"] = out["paper_schedule_md"].pop("ms_per_sweep")
+        out["paper_schedule_md"].update({"x0": 0.99, "md_steps": 10, "md_dt": 0.005, "md_tau": 0.1})
+        out["paper_schedule"] = {k: paper[k] for k in keep}
+        out["paper_schedule"]["steps"] = out["paper_schedule"].pop("sweeps")
+        out["paper_schedule"]["ms_per_step"] = out["paper_schedule"].pop("ms_per_sweep")
+        out["paper_schedule"]["x0"], out["paper_schedule"]["mc_cycles"] = 0.99, 10
+        out["efficiency_ratio_paper_schedule_over_plain"] = P.efficiency_ratio(plain, paper)
+        out["efficiency_ratio_paper_schedule_md_over_plain"] = P.efficiency_ratio(plain, pmd)
+        if plain["reached"] and paper["reached"]:
+            out["paper_schedule"]["t_acc_ratio_plain_over_paper"] = plain["t_acc_s"] / paper["t_acc_s"]
     out["learned"] = {k: learned[k] for k in keep}
     out["learned"]["proposal"] = learned.get("proposal")
     out["efficiency_ratio_learned_over_plain"] = P.efficiency_ratio(plain, learned)
-    out["efficiency_ratio_paper_schedule_over_plain"] = P.efficiency_ratio(plain, paper)
-    out["efficiency_ratio_paper_schedule_md_over_plain"] = P.efficiency_ratio(plain, pmd)
-    if plain["reached"] and paper["reached"]:
-        out["paper_schedule"]["t_acc_ratio_plain_over_paper"] = plain["t_acc_s"] / paper["t_acc_s"]
     if plain["reached"] and learned["reached"]:
         out["speedup_t_acc"] = plain["t_acc_s"] / learned["t_acc_s"]
     elif plain["reached"]:

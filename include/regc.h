@@ -426,9 +426,11 @@ void regc_mlp_destroy(regc_mlp *mlp);
 
 /* Sampling with the learned proposal.  An insertion draws, with probability alpha
  * ((B3 + 1/2) / 2^32 < alpha, B3 the last word of the trial's second Philox
- * block), a voxel v from the network's categorical for the current occupancy by
- * Gumbel-max -- argmax_v logit_v - ln(-ln u_v), u_v the open uniform of word v%4
- * of Philox block (trial, sweep, walker, 16 + v/4) -- and a uniform point inside
+ * block), a voxel v from the network's categorical for the current occupancy --
+ * FP64: by Gumbel-max, argmax_v logit_v - ln(-ln u_v), u_v the open uniform of
+ * word v%4 of Philox block (trial, sweep, walker, 16 + v/4); FP32 pair mode: by
+ * inverse CDF over a fixed voxel order with one uniform from word x of block
+ * (trial, sweep, walker, 16) -- and a uniform point inside
  * it (the trial's uniforms A2, A3, B0); otherwise a uniform point of V as in the
  * plain method.  The proposal density
  *   q(r|X) = alpha P(v(r)|occ(X)) / V_vox + (1 - alpha) / V

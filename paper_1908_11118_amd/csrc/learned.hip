@@ -12,14 +12,17 @@
 //   insertion  ln A = ln z + ln V - ln(N+1) - Lq(r | X)        - beta dE,
 //   removal    ln A = ln N - ln z - ln V    + Lq(r_i | X \ i)  - beta dE,
 // which leaves Eq. (1) the stationary law for any network.  A voxel is drawn by
-// Gumbel-max: argmax_v logit_v - ln(-ln u_v), u_v from Philox block
-// (trial, sweep, walker, 16 + v/4), word v%4.
+// Gumbel-max (FP64 build: argmax_v logit_v - ln(-ln u_v), u_v from Philox block
+// (trial, sweep, walker, 16 + v/4), word v%4) or by inverse CDF with one uniform
+// from word x of block (trial, sweep, walker, 16) (FP32 build): both are exact
+// draws from the categorical.
 //
 // Per trial: the same Philox words as the plain sweep kernel (displacement and the
 // uniform branch give the plain trajectories); for insertions and removals the
 // network runs on the ascending list of occupied voxels (first layer: sum of
 // count x W1 row).  FP32 build: layers 2-4 on v_mfma_f32_16x16x16_bf16 with the
-// activation vector as every row of A, log-normaliser and Gumbel keys in FP32.
+// activation vector as every row of A, log-normaliser and the inverse-CDF draw in
+// FP32.
 // FP64 (parity) build: layers 2-4 as sequential FP32 sums of exact bfloat16
 // products, GELU's erf in FP64, log-normaliser and Gumbel keys in FP64, so the
 // network output is the oracle's bit for bit and trajectories can be compared
@@ -411,19 +414,17 @@ __device__ double net_forward(const NetDev &net, const NetLds &S, int ex, int ti
     }
 }
 
-// E = -ln u for the open uniform u = (w + 1/2) / 2^32, to FP32 relative accuracy
-// on both ends (log1p form near u = 1)
-__device__ __forceinline__ float neg_log_u(uint32_t w)
-{
-    const float scale = 2.3283064365386963e-10f;   // 2^-32
-    if (w < 0x80000000u) return -logf(((float)w + 0.5f) * scale);
-    return -log1pf(-(((float)(0xFFFFFFFFu - w) + 0.5f) * scale));
-}
-
-// Gumbel-max voxel draw from softmax(logit) (block-wide): thread t takes the Philox
-// blocks 16 + t + 256 r, r = 0..3, i.e. voxels 4 (t + 256 r) .. +3.
-__device__ int gumbel_argmax(const NetLds &S, uint32_t t, uint32_t sweep, uint32_t w, uint32_t k0, uint32_t k1,
-                             int tid)
+// Voxel draw from softmax(logit) (block-wide).
+// FP64 build (the oracle's draw): Gumbel-max, argmax_v logit_v - ln(-ln u_v); thread
+// t takes the Philox blocks 16 + t + 256 r, r = 0..3, i.e. voxels 4 (t + 256 r) .. +3.
+// FP32 build: inverse CDF with one uniform u = (k + 1/2) 2^-23, k the top 23 bits of
+// word x of Philox block 16.  Thread t owns voxels t + 256 j, j = 0..15, with weights
+// p_v = exp(logit_v - lse); a block-wide inclusive scan of the threads' sums (wave
+// scans, then the wave totals added in order) cuts [0, total) into contiguous
+// intervals [lo_t, hi_t), and the thread whose interval holds u total walks its
+// weights.  u <= 1 - 2^-24 keeps u total below total, so exactly one thread draws.
+__device__ int draw_voxel(const NetLds &S, double lse, uint32_t t, uint32_t sweep, uint32_t w, uint32_t k0,
+                          uint32_t k1, int tid)
 {
     if (kExact) {
         double best = -INFINITY;
@@ -442,21 +443,55 @@ __device__ int gumbel_argmax(const NetLds &S, uint32_t t, uint32_t sweep, uint32
         }
         return block_argmax(best, arg, S.redd, S.redi);
     } else {
-        float best = -INFINITY;
-        int arg = 0x7fffffff;
+        constexpr int P = kNetNV / kLT;
+        const int wave = tid / kWave, lane = tid % kWave;
+        const float shift = (float)lse;
+        float p[P];
+        float s = 0.f;
 #pragma unroll
-        for (int r = 0; r < kNetNV / (4 * kLT); ++r) {
-            const int b = tid + kLT * r;
-            const uint4 R = philox4x32_10(make_uint4(t, sweep, w, 16u + (uint32_t)b), k0, k1);
-            const uint32_t words[4] = {R.x, R.y, R.z, R.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int v = 4 * b + q;
-                const float key = S.logit[v] - logf(neg_log_u(words[q]));
-                if (key > best || (key == best && v < arg)) { best = key; arg = v; }
-            }
+        for (int j = 0; j < P; ++j) {
+            p[j] = expf(S.logit[tid + kLT * j] - shift);
+            s += p[j];
         }
-        return block_argmax(best, arg, S.redf, S.redi);
+        float x = s;                                  // inclusive scan over the wave
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const float y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        float ex = __shfl_up(x, 1);                   // exclusive: the previous lane's x
+        if (lane == 0) ex = 0.f;
+        __syncthreads();                              // earlier readers of redf, redi are done
+        if (lane == kWave - 1) S.redf[wave] = x;
+        if (tid == 0) S.redi[0] = 0;                  // (no interval holds a NaN target)
+        __syncthreads();
+        float base = 0.f, total = 0.f;
+#pragma unroll
+        for (int q = 0; q < kLearnWaves; ++q) {
+            if (q == wave) base = total;
+            total += S.redf[q];
+        }
+        const uint4 R = philox4x32_10(make_uint4(t, sweep, w, 16u), k0, k1);
+        const float u = ((float)(R.x >> 9) + 0.5f) * 1.1920928955078125e-7f;   // 2^-23
+        const float target = u * total;
+        const float lo = base + ex, hi = base + x;
+        if (lo <= target && target < hi) {
+            // the first voxel whose running sum passes the target; if rounding leaves
+            // the walk short of hi, the last voxel of positive weight
+            float c = lo;
+            int pick = -1, last = 0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                if (p[j] > 0.f) last = j;
+                c += p[j];
+                if (pick < 0 && target < c) pick = j;
+            }
+            S.redi[0] = tid + kLT * (pick >= 0 ? pick : last);
+        }
+        __syncthreads();
+        const int v = S.redi[0];
+        __syncthreads();
+        return v;
     }
 }
 
@@ -629,8 +664,8 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
                         int v;
                         if (kind == 1) {
                             if (bcast(fm, 2 * tt + 1) < alpha) {
-                                v = gumbel_argmax(S, (uint32_t)(t0 + tt), (uint32_t)sweep, (uint32_t)w, a.key0,
-                                                  a.key1, tid);
+                                v = draw_voxel(S, lse, (uint32_t)(t0 + tt), (uint32_t)sweep, (uint32_t)w, a.key0,
+                                               a.key1, tid);
                                 px = ((double)(v & (kNetGrid - 1)) + ux) * g.cx;
                                 py = ((double)((v >> 4) & (kNetGrid - 1)) + uy) * g.cy;
                                 pz = zlo + ((double)(v >> 8) + uz) * g.cz;
