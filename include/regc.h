@@ -119,7 +119,7 @@ typedef struct {
  *  walkers_per_block  waves (one walker each) per workgroup, 1..8; 0 -> auto.
  *  sweeps_per_launch  upper bound of sweeps per kernel launch; 0 -> swap_every.
  *  slab_bins       -1 off, 1 on, 0 auto: slab atoms sorted into x-y columns no
- *                  narrower than rcut + max_disp; each trial scans the 3x3 stencil.
+ *                  narrower than rcut + max_disp; each trial scans the 3x3 block of columns.
  *  split           wavefronts per walker: 1, 2, or 0 (auto: 1); with 2,
  *                  walkers_per_block is 1.
  *  cull            1: squared distances first, LJ terms only for pairs inside the
@@ -222,7 +222,9 @@ int regc_get_walkers(regc_ctx *ctx, int32_t *n, double *e, int32_t *label, doubl
 
 /* Replaces all walker configurations: n[W], xyz W x n_max x 3.  Energies are
  * recomputed on the device in the context's precision.  label may be NULL
- * (unchanged); otherwise it must be a permutation within each class. */
+ * (unchanged); otherwise it must be a permutation within each class.  EINVAL,
+ * before anything changes, for an N outside 0..n_max, a particle outside the
+ * gas region (or not finite), or labels that are not such a permutation. */
 int regc_set_walkers(regc_ctx *ctx, const int32_t *n, const double *xyz, const int32_t *label);
 
 /* Full recomputation of every walker's energy from its coordinates in the
@@ -444,8 +446,8 @@ void regc_mlp_destroy(regc_mlp *mlp);
  * restores the plain method.  Alpha outside [0, 1] is EINVAL; a context of more
  * than 8 classes or one run with the paper's REGC step (schedule 1) is
  * EUNSUPPORTED.  With a proposal set on any class, every walker runs in a
- * workgroup of its own (256 threads); the walkers_per_block, split, cull and
- * slab-binning options then have no effect. */
+ * workgroup of its own (256 threads); the walkers_per_block, split and cull
+ * options then have no effect (slab binning still applies). */
 int regc_set_proposal(regc_ctx *ctx, regc_mlp *mlp, double alpha);
 
 /* The same for class cls (0-based, in the order given to regc_create_batch) of a
