@@ -89,6 +89,25 @@ def test_fp64_trajectories_binned_slab_and_scheme1():
     _fp64_trajectory(w2, 200, slab_bins=-1)
 
 
+def test_fp64_trajectories_irregular_slab_rectangular_box():
+    """Binned slab columns on a rectangular box (14 x 8.5: 5 x 3 columns) with an
+    irregular slab: random atoms, a dense cluster in one corner column (the other
+    columns padded) and atoms within 0.05 of both periodic edges, so the column
+    block's wrap in x and in y and the padding are all exercised."""
+    rng = np.random.default_rng(11)
+    lx, ly = 14.0, 8.5
+    spread = np.column_stack([rng.uniform(0, lx, 40), rng.uniform(0, ly, 40), rng.uniform(-2.0, 0.0, 40)])
+    corner = np.column_stack([rng.uniform(0, 2.0, 20), rng.uniform(0, 2.0, 20), rng.uniform(-2.0, 0.0, 20)])
+    edges = np.array([[lx - 0.02, 0.3, -0.2], [0.01, ly - 0.05, -0.4], [lx - 0.01, ly - 0.01, -0.1],
+                      [7.0, 0.0, -0.3], [0.0, 4.0, -0.6]])
+    w = W.small_lj(n_t=3, n_mu=3, n_max=40).replace(
+        name="irregular-slab", slab=np.vstack([spread, corner, edges]), lx=lx, ly=ly, zlo=0.9, zhi=6.0,
+        t=W.linear_grid(0.8, 1.6, 3), mu=W.linear_grid(-4.0, -2.0, 3), sample_every=2)
+    assert math.floor(lx / (w.rc + w.max_disp)) == 5 and math.floor(ly / (w.rc + w.max_disp)) == 3
+    _, wk = _fp64_trajectory(w, 200)
+    assert wk["n"].max() > 10
+
+
 @pytest.mark.parametrize("wpb,spl,split,cull", [(1, 1, 1, 0), (4, 3, 1, 1), (8, 0, 1, 0), (1, 0, 2, 0), (1, 7, 2, 1)])
 def test_fp64_invariant_to_launch_shape(wpb, spl, split, cull):
     """Walkers per block, sweeps per launch, waves per walker and the cull pass
