@@ -41,7 +41,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_f32_1024rep_192slab_traffic.md")
-KERNEL_SOURCES = ["sweep.hip", "sweep_dev.h", "regc_dev.h", "philox_dev.h"]
+# the sweep kernel's sources and the host code that picks its launch shape
+KERNEL_SOURCES = ["sweep.hip", "sweep_dev.h", "regc_dev.h", "philox_dev.h", "api.cpp"]
 
 
 def measured_traffic():
@@ -74,7 +75,8 @@ def main():
                     help="sweeps of the production leg: the 1024-replica run sampled every 100 sweeps and "
                          "reweighted over all its samples (0: skip)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--wpb", type=int, default=0, help="walkers per workgroup (0: the library's choice)")
+    ap.add_argument("--split", type=int, default=0, help="waves per walker, 1 or 2 (0: the library's choice)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
                     help="c2: 1024 replicas at a 192-atom slab (the headline); c3: 4096 replicas in four "
                          "slab classes batched in one launch")
@@ -122,7 +124,7 @@ def main():
     prec = regc.FP32PAIR if args.precision == "fp32" else regc.FP64
     total_sweeps = args.burnin + (args.warmup + args.steps) * sweeps_per_step
     cap = (total_sweeps // w.sample_every + 2) * n_walkers
-    opts = {"walkers_per_block": args.wpb,
+    opts = {"walkers_per_block": args.wpb, "split": args.split,
             "graph_intervals": (0 if args.workload == "c2" else 10) if args.graph < 0 else args.graph}
     tuned = None
     if args.autotune:

@@ -120,8 +120,9 @@ typedef struct {
  *  sweeps_per_launch  upper bound of sweeps per kernel launch; 0 -> swap_every.
  *  slab_bins       -1 off, 1 on, 0 auto: slab atoms sorted into x-y columns no
  *                  narrower than rcut + max_disp; each trial scans the 3x3 block of columns.
- *  split           wavefronts per walker: 1, 2, or 0 (auto: 1); with 2,
- *                  walkers_per_block is 1.
+ *  split           wavefronts per walker: 1, 2, or 0 (auto: 2 when the sweep schedule
+ *                  runs at most 4 walkers per compute unit and walkers_per_block is 0,
+ *                  else 1); with 2, walkers_per_block is 1.
  *  cull            1: squared distances first, LJ terms only for pairs inside the
  *                  cutoff (compacted in LDS); 0 or -1: every candidate in full.
  *  graph_intervals 0: launch kernels one by one; R > 0: capture R exchange intervals

@@ -15,6 +15,7 @@ from __future__ import annotations
 import hashlib
 import json
 import os
+import sys
 import time
 from typing import Dict, List, Optional
 
@@ -76,7 +77,7 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
         rate = _measure(wl, precision, blob, opts, measure_sweeps)
         table.append({"options": dict(opts), "trials_per_s": rate})
         if verbose:
-            print(f"[autotune] {opts} -> {rate:.4g} trials/s", flush=True)
+            print(f"[autotune] {opts} -> {rate:.4g} trials/s", file=sys.stderr, flush=True)
         return rate
 
     best = {"walkers_per_block": 1, "split": 1, "cull": 0, "slab_bins": 0, "graph_intervals": 0}

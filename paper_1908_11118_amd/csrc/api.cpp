@@ -329,10 +329,13 @@ static int ctx_alloc_and_init(regc_ctx *c)
     REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     REGC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const int real = o.precision == REGC_FP64 ? 8 : 4;
-    // one wave per walker unless asked: two waves per walker measured within noise
-    // of one at 1024 walkers on 256 CUs (the barrier costs what the latency hiding gains)
-    int split = o.split > 0 ? o.split : 1;
-    (void)n_cu;
+    // waves per walker unless asked: two while one each would leave at most one wave
+    // per SIMD (W <= 4 x CUs: a walker's trial chain is latency-bound and the second
+    // wave halves its pair loop; measured 2.8 % faster at 1024 walkers and 2.2 % at 64
+    // on 256 CUs), one above that (25 % slower with two at 4096 walkers, where four
+    // walkers per SIMD already hide the latency).  The paper's step keeps one.
+    int split = o.split > 0 ? o.split
+                            : ((o.schedule == 0 && o.walkers_per_block == 0 && W <= 4 * n_cu) ? 2 : 1);
     const bool cull = o.cull > 0;
     auto smem_for = [&](int wpb) {
         return lds_layout(max_slab_len, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
