@@ -41,9 +41,14 @@ def _signature(workloads, precision: int) -> str:
 
 
 def _measure(workloads, precision: int, blob: bytes, opts: Dict, sweeps: int) -> float:
+    # with graph replay, one whole replay period (graph_intervals exchange intervals)
+    # is run before timing, so that the capture happens outside the timed region,
+    # and at least two periods are timed
+    period = workloads[0].swap_every * max(1, opts.get("graph_intervals", 0))
+    sweeps = max(sweeps, 2 * period)
     with regc.Regc(workloads, precision=precision, sample_capacity=0, **opts) as g:
         g.restore(blob)
-        g.run(workloads[0].swap_every)          # first launch: graph capture, caches
+        g.run(period)                           # first launches: graph capture, caches
         g.sync()
         t0 = time.perf_counter()
         g.run(sweeps)
