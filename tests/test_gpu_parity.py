@@ -219,6 +219,22 @@ def test_checkpoint_restore_continues_identically():
     assert np.array_equal(st["stats"], ref_st["stats"])
 
 
+def test_autotune_picks_the_fastest_measured_shape():
+    """The launch-shape autotuner measures every candidate (graph replay included)
+    and returns the best of its own table; the shape it picks leaves FP64
+    trajectories unchanged."""
+    from paper_1908_11118_amd import autotune
+    w = W.small_lj(n_t=4, n_mu=4, n_max=20)
+    _say("[autotune] small_lj 4x4")
+    res = autotune.autotune(w, precision=regc.FP64, warm_sweeps=50, measure_sweeps=20, cache_path=None)
+    rates = [row["trials_per_s"] for row in res["table"]]
+    assert len(rates) >= 8 and all(np.isfinite(r) and r > 0 for r in rates)
+    assert res["trials_per_s"] == max(rates)
+    assert res["options"] in [row["options"] for row in res["table"]]
+    assert any(row["options"].get("graph_intervals", 0) > 0 for row in res["table"])
+    _fp64_trajectory(w, 40, **res["options"])
+
+
 def test_capacity_and_state_errors():
     w = W.small_lj(n_t=2, n_mu=2, n_max=10)
     with regc.Regc(w, sample_capacity=4 * 5) as g:
