@@ -27,8 +27,9 @@
 //   SPLIT = 1: one wavefront per walker, several walkers per workgroup;
 //   SPLIT = 2: one walker per workgroup of two wavefronts; each takes half of the
 //              candidates, the two partial sums meet in LDS behind a barrier, both
-//              waves then take the same decision.  Two waves per SIMD hide latency
-//              when walkers are as few as SIMDs.
+//              waves then take the same decision and both write an accepted update
+//              into the walker's LDS copy.  Two waves per SIMD hide latency when
+//              walkers are as few as SIMDs.
 //   CULL  = false: every candidate pair is evaluated in full;
 //   CULL  = true : a first pass computes squared distances only and queues the pairs
 //              inside the cutoff in LDS (compacted across the wave); the LJ terms are
@@ -234,19 +235,25 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                             accepted = true;
                             stat += lane == 2 * kind + 1;
                             e += de;
+                            // every wave of the walker writes the update into the shared
+                            // LDS copy itself (the same value), so a wave needs only its own
+                            // write to be visible.  Across waves, the exchange barrier of
+                            // this trial ordered all reads before these writes, and that of
+                            // the next trial orders these writes before any later one; only
+                            // the ideal gas, which has no exchange, keeps a barrier below.
                             if (kind == 0) {
-                                if (part == 0 && lane == 0) {
+                                if (lane == 0) {
                                     Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
                                     gas[i] = v;
                                 }
                             } else if (kind == 1) {
-                                if (part == 0 && lane == 0) {
+                                if (lane == 0) {
                                     Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
                                     gas[n] = v;
                                 }
                                 n += 1;
                             } else {
-                                if (part == 0 && lane == 0 && i != n - 1) gas[i] = gas[n - 1];
+                                if (lane == 0 && i != n - 1) gas[i] = gas[n - 1];
                                 n -= 1;
                             }
                         }
@@ -254,7 +261,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                 }
                 if (accepted) {
                     bits |= 1u << tt;
-                    if (SPLIT == 1) wave_sync(); else __syncthreads();
+                    if (SPLIT == 1 || !ideal) wave_sync(); else __syncthreads();
                 }
             }
             if (tracing && part == 0 && lane == 0)
