@@ -55,3 +55,24 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     out = json.loads(r.stdout.strip().splitlines()[-1])
     assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_bench_reports_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    """The committed counter summary applies while the kernel's sources (and the
+    launch-shape code) hash to the profiled ones; any other hash gives no traffic."""
+    import hashlib
+    import os
+    import bench
+    h = hashlib.sha256()
+    for f in bench.KERNEL_SOURCES:
+        h.update(open(os.path.join(bench.ROOT, "paper_1908_11118_amd", "csrc", f), "rb").read())
+    current = tmp_path / "current.md"
+    current.write_text(f"# summary\n\nbytes_per_launch: 12345\nsource_sha256: {h.hexdigest()}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(current))
+    assert bench.measured_traffic() == 12345.0
+    stale = tmp_path / "stale.md"
+    stale.write_text(f"bytes_per_launch: 12345\nsource_sha256: {'0' * 64}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(stale))
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic() is None
