@@ -4,7 +4,9 @@ FP64 build: the sampler's network arithmetic reproduces the oracle's bit for bit
 so trajectories (accept bits, N, labels, statistics) must be identical to the
 oracle's learned chain and energies agree to 1e-10.  FP32 build (MFMA network):
 the stationary law is checked -- the ideal-gas Poisson mean under a random network
-and the LJ mean N of the plain FP64 oracle, within 4 standard errors."""
+and under a fixed proposal peaked on 16 voxels (with uniform positions, which tests
+the inverse-CDF voxel draw), and the LJ mean N of the plain FP64 oracle, within 4
+standard errors."""
 import math
 import sys
 
@@ -206,6 +208,55 @@ def test_learned_fp32_ideal_gas_poisson():
         mean_ref = float((np.arange(w.n_max + 1) * p).sum())
         m, se = batch_means(n_ser[:, s])
         assert abs(m - mean_ref) < 4 * se + 1e-9, (s, m, mean_ref, se)
+    assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
+
+
+def test_learned_fp32_draw_of_a_peaked_proposal():
+    """W4 = 0 and an output bias of 6 on 16 voxels: q is fixed, 61 % of it on 1/256 of
+    the box, and alpha = 1, so every insertion comes from the FP32 build's voxel draw.
+    The chain must still sample the ideal gas -- truncated-Poisson <N> per state and
+    uniform positions (the 16 peaked voxels hold 16/4096 of the particles) -- which
+    fails if the draw's law is not the q the acceptance divides by."""
+    import torch
+    w = W.ideal_gas(n_max=24).replace(t=W.linear_grid(0.9, 1.3, 4), mu=W.linear_grid(-4.6, -3.8, 4),
+                                      swap_every=10, sample_every=1)
+    p = W.mlp_init(3)
+    p["W4"][:] = 0.0
+    hot = np.random.default_rng(5).choice(4096, 16, replace=False)
+    p["b4"][hot] = 6.0
+    net = regc.Mlp(W.mlp_pack(p))
+    sweeps, every = 8000, 20
+    nw = w.n_states
+    _say(f"[learned fp32 peaked] S={nw} sweeps={sweeps}")
+    vox = torch.zeros((nw, w.n_max), dtype=torch.int16, device="cuda")
+    nd = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    in_hot = total = 0
+    with regc.Regc(w, precision=regc.FP32PAIR, sample_capacity=sweeps * nw) as g:
+        g.set_proposal(net, 1.0)
+        g.run(1000)
+        g.clear_samples()
+        for _ in range(sweeps // every):
+            g.run(every)
+            g.capture_voxels(vox.data_ptr(), nd.data_ptr())
+            g.sync()
+            torch.cuda.synchronize()
+            v = vox.cpu().numpy().astype(np.int64) & 0xFFFF
+            keep = np.arange(w.n_max)[None, :] < nd.cpu().numpy()[:, None]
+            in_hot += int(np.isin(v[keep], hot).sum())
+            total += int(keep.sum())
+        smp = g.samples()
+        ps = g.proposal_stats()
+    net.close()
+    n_ser, _ = per_state_series(smp, nw)
+    for s in range(nw):
+        T, mu = w.t[s // len(w.mu)], w.mu[s % len(w.mu)]
+        zv = math.exp(mu / T) * T ** 1.5 * w.volume
+        pr = truncated_poisson(zv, w.n_max)
+        mean_ref = float((np.arange(w.n_max + 1) * pr).sum())
+        m, se = batch_means(n_ser[:, s])
+        assert abs(m - mean_ref) < 4 * se + 1e-9, (s, m, mean_ref, se)
+    expected = 16.0 / 4096.0
+    assert total > 20000 and abs(in_hot / total - expected) < 0.3 * expected, (in_hot, total, expected)
     assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
 
 
