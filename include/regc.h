@@ -112,7 +112,9 @@ typedef struct {
  *  sample_every    record (E, N, state) of all walkers every sample_every sweeps
  *                  (0: never), before that sweep's exchange step.
  *  swap_scheme     0: even/odd T pairs and even/odd mu pairs; 1: T, mu and the two
- *                  diagonals inside 2x2 blocks (four types, p = 1/4 each, Sec. II.A.2).
+ *                  diagonals inside 2x2 blocks (four types, p = 1/4 each, Sec. II.A.2)
+ *                  whose origin (ol, om) in {0,1}^2 is drawn per exchange step (bits
+ *                  29 and 28 of the type word), so blocks of both tilings alternate.
  *  sample_capacity samples the context can hold (records x walkers); 0 -> enough
  *                  for 1024 records.
  *  trace_capacity  sweeps of accept-bit trace the context can hold (0: no trace).

@@ -103,6 +103,12 @@ def _declare(L):
     L.orc_md_forces.argtypes = [C.POINTER(_Config), _dp, C.c_int, _dp]
     L.orc_md_forces.restype = C.c_double
     L.orc_aiat_phase.argtypes = [C.c_int, _dp, C.c_int, _dp, _i32p]
+    L.orc_checkpoint_size.argtypes = [C.POINTER(_Config)]
+    L.orc_checkpoint_size.restype = C.c_size_t
+    L.orc_checkpoint.argtypes = [C.POINTER(_Config), C.POINTER(_Walkers), C.c_int64, C.c_void_p, C.c_size_t]
+    L.orc_checkpoint.restype = C.c_int
+    L.orc_restore.argtypes = [C.POINTER(_Config), C.POINTER(_Walkers), _i64p, C.c_void_p, C.c_size_t]
+    L.orc_restore.restype = C.c_int
     L.orc_obs_count.argtypes = [C.POINTER(_Config)]
     L.orc_obs_count.restype = C.c_int
     L.orc_observables.argtypes = [C.POINTER(_Config), _dp, C.c_int, _dp]
@@ -115,6 +121,13 @@ def _declare(L):
                                    _dp, C.c_int]
     L.orc_mbar_targets.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _i32p, _dp, C.c_int, _dp,
                                    _dp, _dp, _dp, _dp, _i32p, C.c_int]
+    L.orc_batch_means.argtypes = [C.c_int, C.c_int64, _i32p, _i32p, C.c_int, _dp, _dp]
+    L.orc_boot_multiplicity.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_uint64, _i32p]
+    L.orc_mbar_bootstrap.argtypes = [C.c_int, _dp, _dp, C.c_int64, _dp, _i32p, _i32p, C.c_int64, C.c_int64,
+                                     C.c_int, C.c_uint64, _dp, C.c_double, C.c_int, C.c_int, _dp, _dp, C.c_int,
+                                     _dp, _dp, _dp, _dp, C.c_int]
+    L.orc_mbar_bootstrap.restype = C.c_int
+    L.orc_heat_capacity_coverage.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp]
 
 
 def _p(a, t):
@@ -344,6 +357,22 @@ class Chain:
                                     walker, _p(gap, _dp))
         return v, float(gap[0])
 
+    def checkpoint(self) -> bytes:
+        """The sampling state between sweeps (the HIP library's checkpoint layout)."""
+        size = lib().orc_checkpoint_size(C.byref(self.cfg))
+        buf = C.create_string_buffer(size)
+        rc = lib().orc_checkpoint(C.byref(self.cfg), C.byref(self._walkers()), int(self.sweep[0]), buf, size)
+        if rc != 0:
+            raise RuntimeError(f"oracle checkpoint failed ({rc})")
+        return buf.raw
+
+    def restore(self, blob: bytes):
+        """Continue from a checkpoint (the oracle's or the HIP library's)."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        rc = lib().orc_restore(C.byref(self.cfg), C.byref(self._walkers()), _p(self.sweep, _i64p), buf, len(blob))
+        if rc != 0:
+            raise ValueError("checkpoint does not match this oracle configuration")
+
     def swap_step(self, q: int):
         W = self._walkers()
         lib().orc_swap_step(C.byref(self.cfg), C.byref(W), q)
@@ -430,3 +459,52 @@ def aiat_phase(min_e, mu):
     lib().orc_aiat_phase(len(me) - 1, _p(me, _dp), len(m), _p(m, _dp), _p(out, _i32p))
     return out
 
+
+
+def batch_means(n_states, state, n, n_batches=20):
+    """Per sampled state: mean N and its batch-means standard error (NaN for a state
+    with fewer samples than batches)."""
+    st = np.ascontiguousarray(state, dtype=np.int32)
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    mean, se = np.zeros(n_states), np.zeros(n_states)
+    lib().orc_batch_means(n_states, len(st), _p(st, _i32p), _p(nn, _i32p), n_batches, _p(mean, _dp), _p(se, _dp))
+    return mean, se
+
+
+def boot_multiplicity(records, block, replicate, seed):
+    """How often each record occurs in moving-block bootstrap replicate `replicate`."""
+    out = np.zeros(records, dtype=np.int32)
+    lib().orc_boot_multiplicity(records, block, replicate, seed, _p(out, _i32p))
+    return out
+
+
+def mbar_bootstrap(beta, lnz, e, n, state, record_size, block, n_boot, seed, f_start, tbeta, tlnz, n_max,
+                   tol=1e-10, max_iter=100000, n_threads=None):
+    """Bootstrap standard errors of <N> and C at target states.  Returns (se_n, se_c,
+    rep_n [n_boot, T], rep_c [n_boot, T], converged)."""
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    lnz = np.ascontiguousarray(lnz, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    st = np.ascontiguousarray(state, dtype=np.int32)
+    f0 = np.ascontiguousarray(f_start, dtype=np.float64)
+    tbeta = np.ascontiguousarray(tbeta, dtype=np.float64)
+    tlnz = np.ascontiguousarray(tlnz, dtype=np.float64)
+    T = len(tbeta)
+    se_n, se_c = np.zeros(T), np.zeros(T)
+    rn, rcap = np.zeros((n_boot, T)), np.zeros((n_boot, T))
+    rc = lib().orc_mbar_bootstrap(len(beta), _p(beta, _dp), _p(lnz, _dp), len(e), _p(e, _dp), _p(n, _i32p),
+                                  _p(st, _i32p), record_size, block, n_boot, seed, _p(f0, _dp), tol, max_iter, T,
+                                  _p(tbeta, _dp), _p(tlnz, _dp), n_max, _p(se_n, _dp), _p(se_c, _dp), _p(rn, _dp),
+                                  _p(rcap, _dp), n_threads or default_threads())
+    return se_n, se_c, rn, rcap, rc == 0
+
+
+def heat_capacity_coverage(tbeta, mean_n, mean_e, mean_e2, n_sites):
+    """C = beta^2 (<E^2> - <E>^2) and theta = <N> / n_sites at each target."""
+    tbeta = np.ascontiguousarray(tbeta, dtype=np.float64)
+    a, b, c = (np.ascontiguousarray(x, dtype=np.float64) for x in (mean_n, mean_e, mean_e2))
+    hc, cov = np.zeros(len(tbeta)), np.zeros(len(tbeta))
+    lib().orc_heat_capacity_coverage(len(tbeta), _p(tbeta, _dp), _p(a, _dp), _p(b, _dp), _p(c, _dp), float(n_sites),
+                                     _p(hc, _dp), _p(cov, _dp))
+    return hc, cov

@@ -673,7 +673,9 @@ static int trial(const orc_config *c, const orc_statec *sc, const double *lnk, d
  *   scheme 0: type 0 T-pairs (2a,2a+1), type 1 T-pairs (2a+1,2a+2),
  *             type 2 mu-pairs (2b,2b+1), type 3 mu-pairs (2b+1,2b+2).
  *   scheme 1: within 2x2 blocks: type 0 along T, type 1 along mu,
- *             type 2 main diagonal, type 3 anti-diagonal.
+ *             type 2 main diagonal, type 3 anti-diagonal; the blocks start at
+ *             (ol + 2a, om + 2b) with ol, om drawn per step (bits 29, 28 of the
+ *             type word), so blocks of the even and odd tilings alternate.
  * Pair acceptance from Eq. (1) of both walkers in both states. */
 static void swap_pair(const orc_config *c, const orc_statec *sc, orc_walkers *W, int64_t q,
                       int type, int sa, int sb)
@@ -710,8 +712,12 @@ static void swap_step(const orc_config *c, const orc_statec *sc, orc_walkers *W,
                 for (int m = type - 2; m + 1 < M; m += 2) swap_pair(c, sc, W, q, type, l * M + m, l * M + m + 1);
         }
     } else {
-        for (int l = 0; l + 1 < L; l += 2) {
-            for (int m = 0; m + 1 < M; m += 2) {
+        /* block origin (ol, om) in {0,1}^2 from the next two bits of the type word:
+         * the 2x2 blocks alternate between the even and odd tilings of each axis,
+         * so a configuration can leave the block it started in */
+        int ol = (int)((R[0] >> 29) & 1u), om = (int)((R[0] >> 28) & 1u);
+        for (int l = ol; l + 1 < L; l += 2) {
+            for (int m = om; m + 1 < M; m += 2) {
                 int s00 = l * M + m, s01 = l * M + m + 1, s10 = (l + 1) * M + m, s11 = (l + 1) * M + m + 1;
                 if (type == 0) { swap_pair(c, sc, W, q, type, s00, s10); swap_pair(c, sc, W, q, type, s01, s11); }
                 if (type == 1) { swap_pair(c, sc, W, q, type, s00, s01); swap_pair(c, sc, W, q, type, s10, s11); }
@@ -1080,3 +1086,102 @@ void orc_aiat_phase(int n_max, const double *min_e, int n_mu, const double *mu, 
     }
 }
 
+
+/* ------------------------------------------------------------------------- */
+/* Checkpoint of a single-class simulation                                   */
+/* ------------------------------------------------------------------------- */
+/* The sampling state between two sweeps is (sweep counter, per walker N, running
+ * energy, label, coordinates; walker-of-state table; per-state counters; exchange
+ * counters): continuing from it repeats the uninterrupted chain exactly, since every
+ * random number is keyed by (trial, sweep, walker).  Byte layout, little endian,
+ * shared with the HIP library's checkpoint so that a blob moves between the two:
+ *   u64 magic 0x3143474552, u32 version 1, u32 W, u32 n_max, u32 n_class (1),
+ *   i64 sweep, u64 seed;
+ *   i32 n[W], f64 e[W], i32 label[W], i32 wos[W], f64 xyz[W][n_max][3],
+ *   i64 stats[W][10], i64 swap_att[4][W], i64 swap_acc[4][W].
+ * Rows of xyz beyond a walker's N carry no state. */
+#define ORC_CKPT_MAGIC 0x3143474552ULL
+#define ORC_CKPT_HEADER 40
+
+size_t orc_checkpoint_size(const orc_config *c)
+{
+    const size_t S = (size_t)c->n_t * (size_t)c->n_mu;
+    return ORC_CKPT_HEADER + S * (4 + 8 + 4 + 4) + S * (size_t)c->n_max * 3 * 8 + S * ORC_NSTAT * 8 + 2 * 4 * S * 8;
+}
+
+static char *put(char *p, const void *src, size_t bytes)
+{
+    memcpy(p, src, bytes);
+    return p + bytes;
+}
+
+/* Writes the checkpoint into buf (cap bytes).  Returns 0, or -4 when it does not fit. */
+int orc_checkpoint(const orc_config *c, const orc_walkers *W, int64_t sweep, void *buf, size_t cap)
+{
+    const size_t S = (size_t)c->n_t * (size_t)c->n_mu;
+    if (cap < orc_checkpoint_size(c)) return -4;
+    uint64_t magic = ORC_CKPT_MAGIC, seed = c->seed;
+    uint32_t version = 1, w32 = (uint32_t)S, nmax = (uint32_t)c->n_max, ncls = 1;
+    char *p = (char *)buf;
+    p = put(p, &magic, 8);
+    p = put(p, &version, 4);
+    p = put(p, &w32, 4);
+    p = put(p, &nmax, 4);
+    p = put(p, &ncls, 4);
+    p = put(p, &sweep, 8);
+    p = put(p, &seed, 8);
+    p = put(p, W->n, S * 4);
+    p = put(p, W->e, S * 8);
+    p = put(p, W->label, S * 4);
+    p = put(p, W->wos, S * 4);
+    p = put(p, W->xyz, S * (size_t)c->n_max * 3 * 8);
+    p = put(p, W->stats, S * ORC_NSTAT * 8);
+    p = put(p, W->swap_att, 4 * S * 8);
+    put(p, W->swap_acc, 4 * S * 8);
+    return 0;
+}
+
+/* Restores a checkpoint written by orc_checkpoint (or by the HIP library for a
+ * context of the same single class).  Nothing changes unless the blob matches this
+ * configuration (size, magic, version, W, n_max, one class, seed), every N lies in
+ * 0..n_max and the labels are a permutation whose inverse is the walker-of-state
+ * table.  Returns 0 or -1. */
+int orc_restore(const orc_config *c, orc_walkers *W, int64_t *sweep, const void *buf, size_t size)
+{
+    const size_t S = (size_t)c->n_t * (size_t)c->n_mu;
+    if (size != orc_checkpoint_size(c)) return -1;
+    const char *p = (const char *)buf;
+    uint64_t magic, seed;
+    uint32_t version, w32, nmax, ncls;
+    int64_t sw;
+    memcpy(&magic, p, 8);
+    memcpy(&version, p + 8, 4);
+    memcpy(&w32, p + 12, 4);
+    memcpy(&nmax, p + 16, 4);
+    memcpy(&ncls, p + 20, 4);
+    memcpy(&sw, p + 24, 8);
+    memcpy(&seed, p + 32, 8);
+    if (magic != ORC_CKPT_MAGIC || version != 1 || w32 != (uint32_t)S || nmax != (uint32_t)c->n_max || ncls != 1 ||
+        seed != c->seed || sw < 0)
+        return -1;
+    const char *pn = p + ORC_CKPT_HEADER, *pe = pn + S * 4, *pl = pe + S * 8, *pw = pl + S * 4, *px = pw + S * 4;
+    const char *ps = px + S * (size_t)c->n_max * 3 * 8, *pa = ps + S * ORC_NSTAT * 8, *pc = pa + 4 * S * 8;
+    for (size_t w = 0; w < S; ++w) {
+        int32_t nn, lab, wo;
+        memcpy(&nn, pn + 4 * w, 4);
+        memcpy(&lab, pl + 4 * w, 4);
+        if (nn < 0 || nn > c->n_max || lab < 0 || (size_t)lab >= S) return -1;
+        memcpy(&wo, pw + 4 * (size_t)lab, 4);
+        if ((size_t)wo != w) return -1;
+    }
+    memcpy(W->n, pn, S * 4);
+    memcpy(W->e, pe, S * 8);
+    memcpy(W->label, pl, S * 4);
+    memcpy(W->wos, pw, S * 4);
+    memcpy(W->xyz, px, S * (size_t)c->n_max * 3 * 8);
+    memcpy(W->stats, ps, S * ORC_NSTAT * 8);
+    memcpy(W->swap_att, pa, 4 * S * 8);
+    memcpy(W->swap_acc, pc, 4 * S * 8);
+    *sweep = sw;
+    return 0;
+}

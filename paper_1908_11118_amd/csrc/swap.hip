@@ -4,7 +4,9 @@
 // every disjoint pair of that type is attempted independently.  Scheme 0: even
 // T-axis pairs (2a, 2a+1), odd T-axis pairs (2a+1, 2a+2), even and odd mu-axis
 // pairs.  Scheme 1: inside 2x2 blocks of the grid, pairs along T, along mu, and
-// along the two diagonals.  The pair acceptance is the ratio of the GC densities
+// along the two diagonals; the blocks start at (ol + 2a, om + 2b), the origin
+// (ol, om) in {0,1}^2 drawn with the type (bits 29 and 28 of its word), so the even
+// and odd tilings alternate and a configuration can cross the grid.  The pair acceptance is the ratio of the GC densities
 // (Eq. (1)) of both walkers in both states, i.e. Eq. (6) read as
 //     ln A = (beta_a - beta_b)(E_i - E_j) + (N_j - N_i)(ln z_a - ln z_b)
 // for walker i in state a and walker j in state b.  Labels are permuted; the
@@ -14,7 +16,7 @@
 
 namespace regc {
 
-__device__ __forceinline__ void pair_of(int scheme, int type, int p, int L, int M, int &sa, int &sb)
+__device__ __forceinline__ void pair_of(int scheme, int type, int ol, int om, int p, int L, int M, int &sa, int &sb)
 {
     if (scheme == 0) {
         if (type < 2) {
@@ -29,10 +31,10 @@ __device__ __forceinline__ void pair_of(int scheme, int type, int p, int L, int 
             sb = sa + 1;
         }
     } else {
-        const int bm = M / 2;
+        const int bm = (M - om) / 2;
         const int per = type < 2 ? 2 : 1;
         const int blk = p / per, k = p - blk * per;
-        const int l = 2 * (blk / bm), m = 2 * (blk - (blk / bm) * bm);
+        const int l = ol + 2 * (blk / bm), m = om + 2 * (blk - (blk / bm) * bm);
         const int s00 = l * M + m, s01 = s00 + 1, s10 = s00 + M, s11 = s10 + 1;
         if (type == 0) { sa = k ? s01 : s00; sb = k ? s11 : s10; }
         else if (type == 1) { sa = k ? s10 : s00; sb = k ? s11 : s01; }
@@ -41,13 +43,13 @@ __device__ __forceinline__ void pair_of(int scheme, int type, int p, int L, int 
     }
 }
 
-__device__ __forceinline__ int pair_count(int scheme, int type, int L, int M)
+__device__ __forceinline__ int pair_count(int scheme, int type, int ol, int om, int L, int M)
 {
     if (scheme == 0) {
         if (type < 2) return ((L - type) / 2) * M;
         return L * ((M - (type - 2)) / 2);
     }
-    return (type < 2 ? 2 : 1) * (L / 2) * (M / 2);
+    return (type < 2 ? 2 : 1) * ((L - ol) / 2) * ((M - om) / 2);
 }
 
 __global__ void __launch_bounds__(256) swap_kernel(SwapArgs a)
@@ -59,10 +61,13 @@ __global__ void __launch_bounds__(256) swap_kernel(SwapArgs a)
     const int64_t q = a.clock ? (a.clock[0] + a.interval) / a.swap_every - 1 : a.q;
     const uint4 T = philox4x32_10(make_uint4(0u, (uint32_t)q, stream, 3u), a.key0, a.key1);
     const int type = (int)(T.x >> 30);
-    const int P = pair_count(a.scheme, type, L, M);
+    // scheme 1: origin of the 2x2 blocks, so that blocks of both tilings alternate
+    const int ol = a.scheme == 1 ? (int)((T.x >> 29) & 1u) : 0;
+    const int om = a.scheme == 1 ? (int)((T.x >> 28) & 1u) : 0;
+    const int P = pair_count(a.scheme, type, ol, om, L, M);
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         int sa, sb;
-        pair_of(a.scheme, type, p, L, M, sa, sb);
+        pair_of(a.scheme, type, ol, om, p, L, M, sa, sb);
         const int lo = sa < sb ? sa : sb;
         const uint4 R = philox4x32_10(make_uint4((uint32_t)lo, (uint32_t)q, stream, 4u), a.key0, a.key1);
         const int ga = off + sa, gb = off + sb;

@@ -217,6 +217,30 @@ def test_checkpoint_restore_continues_identically():
     assert np.array_equal(got["e"], ref["e"])
     assert np.array_equal(got["xyz"], ref["xyz"])
     assert np.array_equal(st["stats"], ref_st["stats"])
+    # the oracle restored from the GPU's blob continues along the same trajectory, and
+    # the GPU restored from an oracle checkpoint along the oracle's
+    orc = oracle.Chain(w)
+    orc.restore(blob)
+    assert int(orc.sweep[0]) == 50
+    orc.run(70)
+    assert np.array_equal(orc.n, got["n"]) and np.array_equal(orc.label, got["label"])
+    assert np.allclose(orc.e, got["e"], rtol=1e-10, atol=1e-10)
+    for wk in range(nw):
+        assert np.allclose(orc.xyz[wk, : orc.n[wk]], got["xyz"][wk, : got["n"][wk]], rtol=0, atol=1e-12)
+    assert np.array_equal(orc.stats, st["stats"])
+    o2 = oracle.Chain(w)
+    o2.run(30)
+    oblob = o2.checkpoint()
+    o2.run(40)
+    with regc.Regc(w) as c:
+        c.restore(oblob)
+        assert c.sweep == 30
+        c.run(40)
+        g2 = c.walkers()
+        st2 = c.stats()
+    assert np.array_equal(g2["n"], o2.n) and np.array_equal(g2["label"], o2.label)
+    assert np.allclose(g2["e"], o2.e, rtol=1e-10, atol=1e-10)
+    assert np.array_equal(st2["stats"], o2.stats)
 
 
 def test_autotune_picks_the_fastest_measured_shape():

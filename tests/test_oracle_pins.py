@@ -193,9 +193,32 @@ def test_swap_step_pairs_are_neighbours(scheme):
         if scheme == 0:
             expect = {0: (L // 2) * M, 1: ((L - 1) // 2) * M, 2: L * (M // 2), 3: L * ((M - 1) // 2)}[t]
         else:
-            expect = {0: 2, 1: 2, 2: 1, 3: 1}[t] * (L // 2) * (M // 2)
+            # block origin from bits 29, 28 of the type word (Philox block (0, q, ~0, 3))
+            word = int(oracle.philox4x32_10([0, q, 0xFFFFFFFF, 3], [w.seed & 0xFFFFFFFF, w.seed >> 32])[0])
+            assert word >> 30 == t
+            ol, om = (word >> 29) & 1, (word >> 28) & 1
+            expect = {0: 2, 1: 2, 2: 1, 3: 1}[t] * ((L - ol) // 2) * ((M - om) // 2)
+            for wk in moved:
+                a, b = before[wk], ch.label[wk]
+                # both states inside one block of origin (ol + 2i, om + 2j)
+                la, ma, lb, mb = a // M, a % M, b // M, b % M
+                assert min(la, lb) >= ol and (la - ol) // 2 == (lb - ol) // 2
+                assert min(ma, mb) >= om and (ma - om) // 2 == (mb - om) // 2
         assert d.sum() == expect
     assert seen_types == {0, 1, 2, 3}
+
+
+def test_swap_scheme1_crosses_the_grid():
+    """With the block origin drawn per step, a label can leave its starting 2x2
+    block: with every swap accepted (ideal gas, all walkers empty) walker 0 visits
+    every state of an odd-sized grid, the edge rows and columns included."""
+    w = W.ideal_gas().replace(t=W.linear_grid(1.0, 1.0, 5), mu=W.linear_grid(-3, -3, 5), swap_scheme=1)
+    ch = oracle.Chain(w)
+    seen = set()
+    for q in range(4000):
+        ch.swap_step(q)
+        seen.add(int(ch.label[0]))
+    assert seen == set(range(ch.S))
 
 
 # ---------------------------------------------------------------------------
