@@ -154,7 +154,14 @@ typedef struct {
  *                  (particle i: block (2^31 + i, step, walker, 4)); an inserted
  *                  particle's from block (0, step, walker, 3); after an exchange the
  *                  velocities are scaled by sqrt(T_new / T_old).  Normals by Box-Muller.
- *  md_dt, md_tau   time step and thermostat time constant (0: no thermostat). */
+ *  md_dt, md_tau   time step and thermostat time constant (0: no thermostat).
+ *  resync_every    sweep schedule without the learned proposal: after every
+ *                  resync_every-th sweep (before its sample) each walker's running
+ *                  energy is replaced by its full recomputation in the context's
+ *                  precision (pair terms in FP32 or FP64, sums in FP64), so the FP32
+ *                  pair mode's accumulated rounding never grows; 0: default (100 in
+ *                  REGC_FP32PAIR, never in REGC_FP64, whose running sums match the
+ *                  oracle's), -1: never. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -174,6 +181,7 @@ typedef struct {
     int mc_cycles;
     int md_steps;
     double md_dt, md_tau;
+    int resync_every;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;
@@ -328,6 +336,50 @@ int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int 
 int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
                       double *mean_e, double *mean_e2, double *p_n, int32_t *phase);
 
+/* Estimates with their errors (Sec. II.B gives the estimator, not its error; the
+ * error definitions are readings of this library):
+ *  - at every sampled state s, the direct mean of N over the samples holding s and
+ *    its standard error by batch means: the samples of s in the order given, cut
+ *    into n_batches batches (batch b: series positions floor(b n_s / B) ..
+ *    floor((b+1) n_s / B) - 1), SE = sqrt(var(batch means) / B), (B - 1) variance;
+ *    NaN for a state with fewer than B samples;
+ *  - at every target, bootstrap standard errors of <N>, coverage and heat capacity:
+ *    the samples form records of record_size consecutive samples (0: the number of
+ *    grid states, i.e. one sample of every walker of a run per record); replicate
+ *    b (0..n_boot-1) concatenates ceil(R / block_records) blocks of block_records
+ *    records (0: R / n_batches), block j starting at record
+ *    floor(w (R - block_records + 1) / 2^32), w = word 0 of Philox4x32-10 block
+ *    (j, b, 0xFFFFFFFE, 7) keyed by seed, cut to R records; the self-consistent
+ *    equations are re-solved with every sample weighted by its record's multiplicity
+ *    (started from the full solution) and the averages re-evaluated; SE = standard
+ *    deviation over the replicates, (n_boot - 1) divisor;
+ *  - coverage theta = <N> / n_sites (monolayers of n_sites surface sites; n_sites > 0
+ *    is required when coverage or se_coverage is requested);
+ *  - heat capacity at constant mu, configurational: C = beta^2 (<E^2> - <E>^2). */
+typedef struct {
+    int n_batches;          /* >= 2 (default 20) */
+    int n_boot;             /* 0 (no bootstrap: its outputs are NaN) or >= 2 (default 100) */
+    int64_t record_size;    /* samples per record; 0 -> number of grid states */
+    int64_t block_records;  /* records per bootstrap block; 0 -> records / n_batches (at least 1) */
+    uint64_t seed;          /* Philox key of the block starts (default 1) */
+    double n_sites;         /* surface sites for the coverage */
+} regc_reweight_opts;
+
+void regc_default_reweight_opts(regc_reweight_opts *o);
+
+/* Solves (as regc_mbar_solve, from f = 0) and returns, on the target grid t =
+ * l*n_mu' + m: mean_n, se_n (bootstrap), phase (as regc_mbar_targets), coverage and
+ * se_coverage, heat_cap and se_heat_cap, p_n [t][n_max+1]; on the sampled grid:
+ * f_states [S], mean_state_n and se_state_n [S] (batch means).  Any output may be
+ * NULL.  EINVAL when the samples are not whole records or a block is longer than
+ * the records; ENOCONV (outputs still filled) when the solve or a replicate's solve
+ * did not converge.  Afterwards the handle holds the full-data solution, as after
+ * regc_mbar_solve. */
+int regc_reweight(regc_mbar *mb, const regc_grid *targets, double tol, int max_iter, const regc_reweight_opts *opts,
+                  double *f_states, double *mean_state_n, double *se_state_n, double *mean_n, double *se_n,
+                  int32_t *phase, double *coverage, double *se_coverage, double *heat_cap, double *se_heat_cap,
+                  double *p_n);
+
 /* Timing of the last solve: milliseconds in the iteration kernels and their
  * iteration count. */
 int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter);
@@ -415,6 +467,11 @@ int regc_mlp_forward(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, const 
  * grads may be NULL); no update. */
 int regc_mlp_loss_grads(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, const int32_t *n,
                         const int32_t *excl, const int32_t *target, double *loss, float *grads);
+/* One Adam step (as regc_mlp_train's) on the given batch (host arrays as
+ * regc_mlp_loss_grads); loss and grads (may be NULL) receive the batch's mean loss and
+ * the gradient the step applied. */
+int regc_mlp_step(regc_mlp *mlp, int B, int nmax, const uint16_t *vox, const int32_t *n, const int32_t *excl,
+                  const int32_t *target, double lr, double *loss, float *grads);
 /* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on batches drawn from a
  * device data set of n_examples configurations (vox_dev [n_examples][nmax],
  * n_dev [n_examples]): example and left-out particle from Philox keyed by seed;
@@ -434,8 +491,9 @@ void regc_mlp_destroy(regc_mlp *mlp);
  * block), a voxel v from the network's categorical for the current occupancy --
  * FP64: by Gumbel-max, argmax_v logit_v - ln(-ln u_v), u_v the open uniform of
  * word v%4 of Philox block (trial, sweep, walker, 16 + v/4); FP32 pair mode: by
- * inverse CDF over a fixed voxel order with one uniform from word x of block
- * (trial, sweep, walker, 16) -- and a uniform point inside
+ * inverse CDF over a fixed voxel order with one 53-bit uniform from words x, y of
+ * block (trial, sweep, walker, 16) over the weights expf(logit - max) summed in
+ * FP64, whose probabilities (w_v / sum) the acceptance uses -- and a uniform point inside
  * it (the trial's uniforms A2, A3, B0); otherwise a uniform point of V as in the
  * plain method.  The proposal density
  *   q(r|X) = alpha P(v(r)|occ(X)) / V_vox + (1 - alpha) / V
@@ -458,6 +516,17 @@ int regc_set_proposal(regc_ctx *ctx, regc_mlp *mlp, double alpha);
  * class without a network (never set, mlp = NULL or alpha = 0) inserts uniformly
  * as in the plain method.  cls out of range is EINVAL. */
 int regc_set_class_proposal(regc_ctx *ctx, int cls, regc_mlp *mlp, double alpha);
+
+/* The network of class cls exactly as the sampler evaluates it (its precision build:
+ * FP64 contexts the sequential FP32 sums of the parity build, FP32 contexts the MFMA
+ * layers), for checking it against a reference: n_conf configurations xyz
+ * [n_conf][n_max][3] (host, n_max the largest over classes) of n[c] particles, the
+ * occupancy taken without particle skip[c] (-1: none).  Outputs (host): logits
+ * [n_conf][4096], lse [n_conf] (the log-normaliser the sampler uses) and lnp
+ * [n_conf][4096], the log-probability of each voxel as the acceptance uses it.
+ * ESTATE when the class has no network. */
+int regc_proposal_eval(regc_ctx *ctx, int cls, int n_conf, const int32_t *n, const double *xyz, const int32_t *skip,
+                       float *logits, double *lse, double *lnp);
 
 /* Training data for the proposal network: writes, asynchronously on the
  * context's stream, the voxel of every particle of every walker into the device

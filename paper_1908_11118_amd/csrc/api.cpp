@@ -152,6 +152,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->md_steps = 0;
     o->md_dt = 0.005;
     o->md_tau = 0.1;
+    o->resync_every = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -184,6 +185,7 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->split >= 0 && o->split <= 2, REGC_EINVAL, "split must be 0, 1 or 2");
     REGC_CHECK(o->graph_intervals >= 0 && o->graph_intervals <= 1000, REGC_EINVAL, "graph_intervals must be 0..1000");
     REGC_CHECK(o->schedule == 0 || o->schedule == 1, REGC_EUNSUPPORTED, "unknown schedule %d", o->schedule);
+    REGC_CHECK(o->resync_every >= -1, REGC_EINVAL, "resync_every must be -1, 0 or positive");
     if (o->schedule == 1) {
         REGC_CHECK(o->x0 >= 0.0 && o->x0 <= 1.0, REGC_EINVAL, "x0 must lie in [0, 1]");
         REGC_CHECK(o->mc_cycles >= 0 && o->mc_cycles <= 1000, REGC_EINVAL, "mc_cycles must be 0..1000");
@@ -578,6 +580,8 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     a.max_slab_len = c->max_slab_len;
     a.gas_stride = c->nmax_all;
     a.max_slab_scan = c->max_slab_scan;
+    a.resync_every = c->opts.resync_every > 0 ? c->opts.resync_every
+                                              : (c->opts.resync_every == 0 && c->opts.precision == REGC_FP32PAIR ? 100 : 0);
     int rc;
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
@@ -952,6 +956,55 @@ static int set_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)
 extern "C" int regc_set_proposal(regc_ctx *c, regc_mlp *mlp, double alpha)
 {
     return set_proposal(c, -1, mlp, alpha);
+}
+
+extern "C" int regc_proposal_eval(regc_ctx *c, int cls, int n_conf, const int32_t *n, const double *xyz,
+                                  const int32_t *skip, float *logits, double *lse, double *lnp)
+{
+    REGC_CHECK(c && n && xyz && skip && logits && lse && lnp, REGC_EINVAL, "null argument");
+    REGC_CHECK(cls >= 0 && cls < (int)c->cls.size(), REGC_EINVAL, "class index %d out of range", cls);
+    REGC_CHECK(cls < (int)c->alpha.size() && c->alpha[cls] > 0.0, REGC_ESTATE, "class %d has no network", cls);
+    REGC_CHECK(n_conf > 0, REGC_EINVAL, "no configurations");
+    const ClassHost &h = c->cls[cls];
+    const int stride = c->nmax_all;
+    for (int k = 0; k < n_conf; ++k) {
+        REGC_CHECK(n[k] >= 0 && n[k] <= h.sys.n_max, REGC_EINVAL, "configuration %d: N out of range", k);
+        REGC_CHECK(skip[k] >= -1 && skip[k] < std::max(n[k], 1), REGC_EINVAL, "configuration %d: bad skip", k);
+    }
+    DevBuf<double> x_d, lse_d, lnp_d;
+    DevBuf<int32_t> n_d, s_d;
+    DevBuf<float> lg_d;
+    int rc;
+    const size_t nv = (size_t)n_conf * kNetNV;
+    if ((rc = x_d.alloc((size_t)n_conf * stride * 3)) || (rc = lse_d.alloc(n_conf)) || (rc = lnp_d.alloc(nv)) ||
+        (rc = n_d.alloc(n_conf)) || (rc = s_d.alloc(n_conf)) || (rc = lg_d.alloc(nv)))
+        return rc;
+    REGC_HIP(hipMemcpy(x_d.p, xyz, sizeof(double) * (size_t)n_conf * stride * 3, hipMemcpyHostToDevice));
+    REGC_HIP(hipMemcpy(n_d.p, n, sizeof(int32_t) * n_conf, hipMemcpyHostToDevice));
+    REGC_HIP(hipMemcpy(s_d.p, skip, sizeof(int32_t) * n_conf, hipMemcpyHostToDevice));
+    const uint16_t *w = c->net_w.p + (size_t)cls * kNetWords;
+    const float *bb = c->net_b.p + (size_t)cls * kNetBiases;
+    NetDev d;
+    d.w1 = w;
+    d.w2 = w + (size_t)kNetNV * kNetH;
+    d.w3 = d.w2 + (size_t)kNetH * kNetH;
+    d.w4 = d.w3 + (size_t)kNetH * kNetH;
+    d.b1 = bb;
+    d.b2 = bb + kNetH;
+    d.b3 = bb + 2 * kNetH;
+    d.b4 = bb + 3 * kNetH;
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    if (c->opts.precision == REGC_FP64)
+        REGC_HIP(launch_net_eval_f64(d, c->cls_d.p, cls, stride, n_conf, x_d.p, n_d.p, s_d.p, lg_d.p, lse_d.p,
+                                     lnp_d.p, c->stream));
+    else
+        REGC_HIP(launch_net_eval_f32(d, c->cls_d.p, cls, stride, n_conf, x_d.p, n_d.p, s_d.p, lg_d.p, lse_d.p,
+                                     lnp_d.p, c->stream));
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    REGC_HIP(hipMemcpy(logits, lg_d.p, sizeof(float) * nv, hipMemcpyDeviceToHost));
+    REGC_HIP(hipMemcpy(lse, lse_d.p, sizeof(double) * n_conf, hipMemcpyDeviceToHost));
+    REGC_HIP(hipMemcpy(lnp, lnp_d.p, sizeof(double) * nv, hipMemcpyDeviceToHost));
+    return REGC_OK;
 }
 
 extern "C" int regc_set_class_proposal(regc_ctx *c, int cls, regc_mlp *mlp, double alpha)

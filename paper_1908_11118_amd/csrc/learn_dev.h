@@ -66,6 +66,12 @@ __host__ __device__ inline LearnLds learn_lds(int max_slab_len, int gas_stride, 
 
 hipError_t launch_learned_f64(const SweepArgs &a, const LearnArgs &l, size_t smem, hipStream_t s);
 hipError_t launch_learned_f32(const SweepArgs &a, const LearnArgs &l, size_t smem, hipStream_t s);
+hipError_t launch_net_eval_f64(const NetDev &net, const ClassDev *cls, int cid, int stride, int n_conf,
+                               const double *xyz, const int32_t *n, const int32_t *skip, float *logits, double *lse,
+                               double *lnp, hipStream_t s);
+hipError_t launch_net_eval_f32(const NetDev &net, const ClassDev *cls, int cid, int stride, int n_conf,
+                               const double *xyz, const int32_t *n, const int32_t *skip, float *logits, double *lse,
+                               double *lnp, hipStream_t s);
 
 }  // namespace regc
 

@@ -13,9 +13,10 @@
 //   removal    ln A = ln N - ln z - ln V    + Lq(r_i | X \ i)  - beta dE,
 // which leaves Eq. (1) the stationary law for any network.  A voxel is drawn by
 // Gumbel-max (FP64 build: argmax_v logit_v - ln(-ln u_v), u_v from Philox block
-// (trial, sweep, walker, 16 + v/4), word v%4) or by inverse CDF with one uniform
-// from word x of block (trial, sweep, walker, 16) (FP32 build): both are exact
-// draws from the categorical.
+// (trial, sweep, walker, 16 + v/4), word v%4; the 32-bit u_v make each voxel's
+// probability the softmax up to their discreteness) or by inverse CDF with one
+// 53-bit uniform from words x, y of block (trial, sweep, walker, 16) over FP32
+// weights summed in FP64 (FP32 build), whose probabilities the acceptance uses.
 //
 // Per trial: the same Philox words as the plain sweep kernel (displacement and the
 // uniform branch give the plain trajectories); for insertions and removals the
@@ -35,8 +36,10 @@
 
 #if defined(REGC_FP64)
 #define LEARNED_LAUNCH launch_learned_f64
+#define NET_EVAL_LAUNCH launch_net_eval_f64
 #else
 #define LEARNED_LAUNCH launch_learned_f32
+#define NET_EVAL_LAUNCH launch_net_eval_f32
 #endif
 
 namespace regc {
@@ -224,7 +227,60 @@ struct NetLds {
     double *redd;      // [kLearnWaves] doubles
     float *redf;       // [kLearnWaves] floats
     int *redi;         // [kLearnWaves] ints (scan totals, argmax indices)
+    double *norm;      // FP32 build: ln of the FP64 sum of the weights of the current logits
+    float *mxf;        // FP32 build: the largest of the current logits
 };
+
+// Block-wide scan of one FP64 value per thread in thread order: wave scans, then the
+// wave totals added in order.  lo/hi = the sums before and through this thread (so
+// the intervals [lo, hi) of consecutive threads meet exactly and cover [0, total));
+// returns the total.  Both the normaliser and the voxel draw of the FP32 build use
+// it, so they see the same total bit for bit.
+__device__ __forceinline__ double block_scan(double v, double *red, int wave, int lane, double &lo, double &hi)
+{
+    double x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    double prev = __shfl_up(x, 1);
+    if (lane == 0) prev = 0.0;
+    __syncthreads();                  // earlier readers of red are done
+    if (lane == kWave - 1) red[wave] = x;
+    __syncthreads();
+    double base = 0.0, total = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLearnWaves; ++q) {
+        if (q == wave) base = total;
+        total += red[q];
+    }
+    lo = base + prev;
+    hi = base + x;
+    __syncthreads();
+    return total;
+}
+
+// FP32 build: the categorical of the current logits is P(v) = w_v / sum_u w_u with
+// w_v = expf(logit_v - max) in FP32 and the sum in FP64 in the order of block_scan
+// (thread t owns voxels t + 256 j, summed over j in order).  The voxel draw realises
+// exactly these weights, and the acceptance uses ln P(v) = ln w_v - ln sum, so the
+// proposal density in the acceptance is the one the draw follows up to FP64 rounding.
+__device__ __forceinline__ double weight_total(const NetLds &S, float mx, int tid, int wave, int lane)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kNetNV / kLT; ++j) v += (double)expf(S.logit[tid + kLT * j] - mx);
+    double lo, hi;
+    return block_scan(v, S.redd, wave, lane, lo, hi);
+}
+
+// ln P(v) of the current logits (lse: the value net_forward returned for them).
+__device__ __forceinline__ double log_prob(const NetLds &S, double lse, int v)
+{
+    if (kExact) return (double)S.logit[v] - lse;
+    return log((double)expf(S.logit[v] - S.mxf[0])) - S.norm[0];
+}
 
 // The network's logits for the occupancy without one particle in voxel `ex`
 // (-1: none) into S.logit; returns the log-normaliser.  Block-wide.
@@ -406,23 +462,25 @@ __device__ double net_forward(const NetDev &net, const NetLds &S, int ex, int ti
 #pragma unroll
         for (int q = 0; q < kNetNV / kLT; ++q) mx = fmaxf(mx, S.logit[tid + kLT * q]);
         mx = block_max(mx, S.redf);
-        float s = 0.f;
-#pragma unroll
-        for (int q = 0; q < kNetNV / kLT; ++q) s += expf(S.logit[tid + kLT * q] - mx);
-        s = block_sum(s, S.redf);
-        return (double)(mx + logf(s));
+        const double lsum = log(weight_total(S, mx, tid, wave, lane));
+        if (tid == 0) {
+            S.norm[0] = lsum;
+            S.mxf[0] = mx;
+        }
+        __syncthreads();
+        return (double)mx + lsum;
     }
 }
 
 // Voxel draw from softmax(logit) (block-wide).
 // FP64 build (the oracle's draw): Gumbel-max, argmax_v logit_v - ln(-ln u_v); thread
 // t takes the Philox blocks 16 + t + 256 r, r = 0..3, i.e. voxels 4 (t + 256 r) .. +3.
-// FP32 build: inverse CDF with one uniform u = (k + 1/2) 2^-23, k the top 23 bits of
-// word x of Philox block 16.  Thread t owns voxels t + 256 j, j = 0..15, with weights
-// p_v = exp(logit_v - lse); a block-wide inclusive scan of the threads' sums (wave
-// scans, then the wave totals added in order) cuts [0, total) into contiguous
-// intervals [lo_t, hi_t), and the thread whose interval holds u total walks its
-// weights.  u <= 1 - 2^-24 keeps u total below total, so exactly one thread draws.
+// FP32 build: inverse CDF with one 53-bit uniform u (words x, y of Philox block 16).
+// Thread t owns voxels t + 256 j, j = 0..15, with the FP32 weights w_v of log_prob; the
+// FP64 scan of the threads' sums cuts [0, total) into contiguous intervals [lo_t, hi_t),
+// and the thread whose interval holds u total (< total, as u <= 1 - 2^-53) walks its
+// weights in FP64.  Each voxel is drawn with probability w_v / total up to the FP64
+// rounding of the running sums (a few 2^-53 of the total per voxel).
 __device__ int draw_voxel(const NetLds &S, double lse, uint32_t t, uint32_t sweep, uint32_t w, uint32_t k0,
                           uint32_t k1, int tid)
 {
@@ -445,53 +503,36 @@ __device__ int draw_voxel(const NetLds &S, double lse, uint32_t t, uint32_t swee
     } else {
         constexpr int P = kNetNV / kLT;
         const int wave = tid / kWave, lane = tid % kWave;
-        const float shift = (float)lse;
+        const float mx = S.mxf[0];
         float p[P];
-        float s = 0.f;
+        double v = 0.0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            p[j] = expf(S.logit[tid + kLT * j] - shift);
-            s += p[j];
+            p[j] = expf(S.logit[tid + kLT * j] - mx);
+            v += (double)p[j];
         }
-        float x = s;                                  // inclusive scan over the wave
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const float y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        float ex = __shfl_up(x, 1);                   // exclusive: the previous lane's x
-        if (lane == 0) ex = 0.f;
-        __syncthreads();                              // earlier readers of redf, redi are done
-        if (lane == kWave - 1) S.redf[wave] = x;
-        if (tid == 0) S.redi[0] = 0;                  // (no interval holds a NaN target)
-        __syncthreads();
-        float base = 0.f, total = 0.f;
-#pragma unroll
-        for (int q = 0; q < kLearnWaves; ++q) {
-            if (q == wave) base = total;
-            total += S.redf[q];
-        }
+        double lo, hi;
+        if (tid == 0) S.redi[0] = 0;
+        const double total = block_scan(v, S.redd, wave, lane, lo, hi);
         const uint4 R = philox4x32_10(make_uint4(t, sweep, w, 16u), k0, k1);
-        const float u = ((float)(R.x >> 9) + 0.5f) * 1.1920928955078125e-7f;   // 2^-23
-        const float target = u * total;
-        const float lo = base + ex, hi = base + x;
+        const double target = uniform53(R.x, R.y) * total;      // in [0, total)
         if (lo <= target && target < hi) {
-            // the first voxel whose running sum passes the target; if rounding leaves
-            // the walk short of hi, the last voxel of positive weight
-            float c = lo;
+            // the first voxel whose running FP64 sum passes the target; if rounding
+            // leaves the walk short of hi, the last voxel of positive weight
+            double c = lo;
             int pick = -1, last = 0;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 if (p[j] > 0.f) last = j;
-                c += p[j];
+                c += (double)p[j];
                 if (pick < 0 && target < c) pick = j;
             }
             S.redi[0] = tid + kLT * (pick >= 0 ? pick : last);
         }
         __syncthreads();
-        const int v = S.redi[0];
+        const int vv = S.redi[0];
         __syncthreads();
-        return v;
+        return vv;
     }
 }
 
@@ -534,6 +575,8 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     S.redd = reinterpret_cast<double *>(smem + L.red);
     S.redf = reinterpret_cast<float *>(S.redd + kLearnWaves);
     S.redi = reinterpret_cast<int *>(S.redf + kLearnWaves);
+    S.norm = reinterpret_cast<double *>(S.redi + kLearnWaves);
+    S.mxf = reinterpret_cast<float *>(S.norm + 1);
 
     const int slab_len = C.slab_len;
     for (int k = tid; k < slab_len; k += kLT) {
@@ -681,7 +724,7 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
                         } else {
                             v = vold;
                         }
-                        const double lnp = (double)S.logit[v] - lse;
+                        const double lnp = log_prob(S, lse, v);
                         const double lq = log1p(alpha * (exp(lnp) * (double)kNetNV - 1.0));
                         c = kind == 1 ? (lnzv - lnk[n + 1]) - lq : (lnk[n] - lnzv) + lq;
                     }
@@ -807,6 +850,67 @@ __global__ void __launch_bounds__(kLT) learned_kernel(SweepArgs a, LearnArgs l)
     }
 }
 
+// The sampler's network on given configurations (one workgroup each): the occupancy
+// of the particles (positions rounded to Real, as the sampler holds them) without
+// particle skip[c] (-1: none), then net_forward.  logits [c][4096], lse [c] (the
+// normaliser the sampler returns), lnp [c][4096] = ln P(v) as the acceptance uses it.
+__global__ void __launch_bounds__(kLT) net_eval_kernel(NetDev net, const ClassDev *cls, int cid, int stride,
+                                                       const double *xyz, const int32_t *n_conf,
+                                                       const int32_t *skip, float *logits, double *lse_out,
+                                                       double *lnp_out)
+{
+    extern __shared__ __align__(32) unsigned char smem[];
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int c = blockIdx.x;
+    const ClassDev &C = cls[cid];
+    const LearnLds L = learn_lds(0, stride, (int)sizeof(Real));
+    uint32_t *occ = reinterpret_cast<uint32_t *>(smem + L.occ);
+    int *vox = reinterpret_cast<int *>(smem + L.vox);
+    NetLds S;
+    S.occ = occ;
+    S.list = reinterpret_cast<uint32_t *>(smem + L.list);
+    S.part = reinterpret_cast<float *>(smem + L.part);
+    S.h1 = reinterpret_cast<bf16 *>(smem + L.hid);
+    S.h2 = S.h1 + kNetH;
+    S.h3 = S.h2 + kNetH;
+    S.logit = reinterpret_cast<float *>(smem + L.logit);
+    float *bias = reinterpret_cast<float *>(smem + L.bias);
+    for (int k = tid; k < kNetNV; k += kLT) bias[k] = net.b4[k];
+    for (int k = tid; k < 3 * kNetH; k += kLT)
+        bias[kNetNV + k] = k < kNetH ? net.b1[k] : (k < 2 * kNetH ? net.b2[k - kNetH] : net.b3[k - 2 * kNetH]);
+    S.b4 = bias;
+    S.b1 = bias + kNetNV;
+    S.b2 = S.b1 + kNetH;
+    S.b3 = S.b2 + kNetH;
+    S.redd = reinterpret_cast<double *>(smem + L.red);
+    S.redf = reinterpret_cast<float *>(S.redd + kLearnWaves);
+    S.redi = reinterpret_cast<int *>(S.redf + kLearnWaves);
+    S.norm = reinterpret_cast<double *>(S.redi + kLearnWaves);
+    S.mxf = reinterpret_cast<float *>(S.norm + 1);
+    for (int k = tid; k < kNetNV; k += kLT) occ[k] = 0u;
+    Grid g;
+    g.gx = (double)kNetGrid / C.lx;
+    g.gy = (double)kNetGrid / C.ly;
+    g.gz = (double)kNetGrid / (C.zhi - C.zlo);
+    g.zlo = C.zlo;
+    __syncthreads();
+    const int n = n_conf[c];
+    const double *x = xyz + (size_t)c * stride * 3;
+    for (int k = tid; k < n; k += kLT) {
+        const int vv = voxel_of(g, (double)(Real)x[3 * k], (double)(Real)x[3 * k + 1], (double)(Real)x[3 * k + 2]);
+        vox[k] = vv;
+        atomicAdd(occ + vv, 1u);
+    }
+    __syncthreads();
+    const int ex = skip[c] >= 0 && skip[c] < n ? vox[skip[c]] : -1;
+    const double lse = net_forward(net, S, ex, tid, wave, lane);
+    for (int v = tid; v < kNetNV; v += kLT) {
+        logits[(size_t)c * kNetNV + v] = S.logit[v];
+        lnp_out[(size_t)c * kNetNV + v] = log_prob(S, lse, v);
+    }
+    if (tid == 0) lse_out[c] = lse;
+}
+
 }  // namespace fp64 / fp32
 
 using namespace REGC_PREC;
@@ -814,6 +918,16 @@ using namespace REGC_PREC;
 hipError_t LEARNED_LAUNCH(const SweepArgs &a, const LearnArgs &l, size_t smem, hipStream_t s)
 {
     hipLaunchKernelGGL(learned_kernel, dim3(a.n_walkers), dim3(kLT), smem, s, a, l);
+    return hipGetLastError();
+}
+
+hipError_t NET_EVAL_LAUNCH(const NetDev &net, const ClassDev *cls, int cid, int stride, int n_conf, const double *xyz,
+                           const int32_t *n, const int32_t *skip, float *logits, double *lse, double *lnp,
+                           hipStream_t s)
+{
+    const size_t smem = learn_lds(0, stride, (int)sizeof(Real)).total;
+    hipLaunchKernelGGL(net_eval_kernel, dim3(n_conf), dim3(kLT), smem, s, net, cls, cid, stride, xyz, n, skip, logits,
+                       lse, lnp);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "host_util.h"
+#include "philox_dev.h"
 #include "regc_dev.h"
 
 namespace regc {
@@ -96,10 +97,12 @@ __device__ __forceinline__ double wsum(double v)
 
 // One chunk (samples of a single N) per block: softmax over temperatures per
 // sample, partial sums of p_l(n) per chunk; log D_n when requested.
-template <int LMAX>
+// WEIGHTED: sample i counts wgt[i] times (bootstrap replicates; wgt in sorted order).
+template <int LMAX, bool WEIGHTED>
 __global__ void __launch_bounds__(kMbarThreads) mbar_chunk(int L, int nN, const double *beta_l, const double *logA,
                                                         const double *e, const int *chunk_n, const int *chunk_b,
-                                                        const int *chunk_e, double *partial, double *logd_out)
+                                                        const int *chunk_e, double *partial, double *logd_out,
+                                                        const double *wgt)
 {
     __shared__ double red[kMbarThreads / 64][LMAX];
     const int c = blockIdx.x;
@@ -127,7 +130,7 @@ __global__ void __launch_bounds__(kMbarThreads) mbar_chunk(int L, int nN, const 
             x[l] = l < L ? exp(x[l] - mx) : 0.0;
             sum += x[l];
         }
-        const double inv = 1.0 / sum;
+        const double inv = WEIGHTED ? wgt[i] / sum : 1.0 / sum;
 #pragma unroll
         for (int l = 0; l < LMAX; ++l) acc[l] += x[l] * inv;
         if (logd_out) logd_out[i] = mx + log(sum);
@@ -206,7 +209,8 @@ __global__ void mbar_gauge(int S, int g, const double *lnomega, double *fnew, do
 // Target temperatures: per chunk and target temperature the online (max, s0, s1, s2).
 __global__ void __launch_bounds__(kMbarThreads) mbar_target_chunk(int nT, const double *tbeta, const double *e,
                                                                const double *logd, const int *chunk_b,
-                                                               const int *chunk_e, double *tpart)
+                                                               const int *chunk_e, double *tpart,
+                                                               const double *wgt)
 {
     __shared__ double red[kMbarThreads / 64][4];
     const int c = blockIdx.x;
@@ -222,7 +226,7 @@ __global__ void __launch_bounds__(kMbarThreads) mbar_target_chunk(int nT, const 
                 s0 *= sc; s1 *= sc; s2 *= sc;
                 mx = y;
             }
-            const double w = exp(y - mx);
+            const double w = wgt ? wgt[i] * exp(y - mx) : exp(y - mx);
             s0 += w; s1 += w * E; s2 += w * E * E;
         }
         // wave combine
@@ -426,6 +430,114 @@ __global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *
     }
 }
 
+// ---- errors of the estimates ----
+// Batch means: per-state series position of every sample (samples sorted stably by
+// state), batch b = floor(rank B / n_s), integer sums of N per (state, batch).
+__global__ void bm_accumulate(int64_t ns, int B, const int32_t *sorted_state, const int32_t *sorted_idx,
+                              const int32_t *n_orig, const int64_t *state_start, const int64_t *state_count,
+                              unsigned long long *bsum, unsigned long long *bcnt)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < ns; p += (int64_t)gridDim.x * blockDim.x) {
+        const int s = sorted_state[p];
+        const int64_t rank = p - state_start[s], cnt = state_count[s];
+        const int b = (int)((rank * B) / cnt);
+        atomicAdd(bsum + (size_t)s * B + b, (unsigned long long)n_orig[sorted_idx[p]]);
+        atomicAdd(bcnt + (size_t)s * B + b, 1ull);
+    }
+}
+
+// mean and SE of each state from its batch sums (NaN below B samples); batch b's mean
+// is bsum / bcnt, SE = sqrt(sum (m_b - mean(m))^2 / ((B - 1) B)), batches in order.
+__global__ void bm_finish(int S, int B, const unsigned long long *bsum, const unsigned long long *bcnt,
+                          const int64_t *state_count, double *mean, double *se)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (state_count[s] < B) {
+        mean[s] = NAN;
+        se[s] = NAN;
+        return;
+    }
+    double tot = 0.0, mb = 0.0;
+    for (int b = 0; b < B; ++b) {
+        tot += (double)bsum[(size_t)s * B + b];
+        mb += (double)bsum[(size_t)s * B + b] / (double)bcnt[(size_t)s * B + b];
+    }
+    mb /= B;
+    double v = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double d = (double)bsum[(size_t)s * B + b] / (double)bcnt[(size_t)s * B + b] - mb;
+        v += d * d;
+    }
+    mean[s] = tot / (double)state_count[s];
+    se[s] = sqrt(v / (double)(B - 1) / (double)B);
+}
+
+// Moving-block bootstrap, replicate b: block j (of ceil(R / block)) starts at record
+// floor(w (R - block + 1) / 2^32), w = word 0 of Philox block (j, b, 0xFFFFFFFE, 7);
+// mult[r] counts the occurrences of record r in the concatenation cut to R records.
+__global__ void boot_mult(int64_t R, int64_t block, int b, uint32_t k0, uint32_t k1, int32_t *mult)
+{
+    const int64_t nb = (R + block - 1) / block;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nb; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 w = philox4x32_10(make_uint4((uint32_t)j, (uint32_t)b, 0xFFFFFFFEu, 7u), k0, k1);
+        const int64_t start = (int64_t)(((uint64_t)w.x * (uint64_t)(R - block + 1)) >> 32);
+        for (int64_t k = 0; k < block && j * block + k < R; ++k) atomicAdd(mult + start + k, 1);
+    }
+}
+
+__global__ void fill_i32(int64_t count, int32_t v, int32_t *x)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__global__ void fill_u64(int64_t count, unsigned long long *x)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0ull;
+}
+
+// Sample weights of a replicate in sorted order and the weighted count of each state.
+__global__ void boot_weights(int64_t ns, int64_t record_size, const int32_t *perm, const int32_t *state_orig,
+                             const int32_t *mult, double *wgt, unsigned long long *omega)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = perm[i];
+        const int32_t m = mult[o / record_size];
+        wgt[i] = (double)m;
+        if (m) atomicAdd(omega + state_orig[o], (unsigned long long)m);
+    }
+}
+
+// Heat capacity C = beta^2 (<E^2> - <E>^2) and coverage <N> / n_sites per target
+// (targets t = l n_mu + m, beta of row l).
+__global__ void heat_cov(int nT, int nMu, const double *tbeta, const double *mean_n, const double *mean_e,
+                         const double *mean_e2, double n_sites, double *heat, double *cov)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nT * nMu) return;
+    const double b = tbeta[k / nMu];
+    heat[k] = b * b * (mean_e2[k] - mean_e[k] * mean_e[k]);
+    if (cov) cov[k] = mean_n[k] / n_sites;
+}
+
+// Standard deviation over B replicates of every target ([B][K] in, (B - 1) divisor).
+__global__ void rep_sd(int B, int K, const double *rep, double *sd)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double m = 0.0;
+    for (int b = 0; b < B; ++b) m += rep[(size_t)b * K + k];
+    m /= B;
+    double v = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double d = rep[(size_t)b * K + k] - m;
+        v += d * d;
+    }
+    sd[k] = sqrt(v / (double)(B - 1));
+}
+
 }  // namespace regc
 
 using namespace regc;
@@ -448,6 +560,9 @@ struct regc_mbar {
     double ms_iter = 0.0;
     int64_t n_iter = 0;
     int method = 1, memory = 8;
+    DevBuf<int32_t> n_orig_d, s_orig_d;   // N and state of the samples in the order given
+    DevBuf<double> wgt_d;                 // bootstrap multiplicities in sorted order
+    bool weighted = false;
 };
 
 static double lnz_of(double T, double mu, double lambda1)
@@ -511,7 +626,9 @@ extern "C" int regc_mbar_set_samples(regc_mbar *mb, int64_t ns, const double *e,
     hipStream_t s = mb->stream;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     DevBuf<double> e_in;
-    DevBuf<int32_t> n_in, s_in, idx;
+    DevBuf<int32_t> &n_in = mb->n_orig_d, &s_in = mb->s_orig_d;
+    DevBuf<int32_t> idx;
+    mb->weighted = false;
     DevBuf<int32_t> &idx_out = mb->perm_d;
     DevBuf<uint32_t> keys, keys_out;
     DevBuf<unsigned long long> omega, seg;
@@ -595,14 +712,21 @@ static hipError_t launch_chunk(regc_mbar *mb, double *logd)
 {
     const int L = mb->L;
     hipStream_t s = mb->stream;
-#define CHUNK_CASE(LM)                                                                                      \
-    hipLaunchKernelGGL(mbar_chunk<LM>, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, L, mb->nN, mb->beta_d.p, \
-                       mb->logA_d.p, mb->e_d.p, mb->chunk_n_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p,         \
-                       mb->partial_d.p, logd)
-    if (L <= 8) CHUNK_CASE(8);
-    else if (L <= 16) CHUNK_CASE(16);
-    else if (L <= 32) CHUNK_CASE(32);
-    else CHUNK_CASE(64);
+#define CHUNK_CASE(LM, WT)                                                                                     \
+    hipLaunchKernelGGL((mbar_chunk<LM, WT>), dim3(mb->nchunks), dim3(kMbarThreads), 0, s, L, mb->nN, mb->beta_d.p, \
+                       mb->logA_d.p, mb->e_d.p, mb->chunk_n_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p,               \
+                       mb->partial_d.p, logd, mb->wgt_d.p)
+    if (mb->weighted) {
+        if (L <= 8) CHUNK_CASE(8, true);
+        else if (L <= 16) CHUNK_CASE(16, true);
+        else if (L <= 32) CHUNK_CASE(32, true);
+        else CHUNK_CASE(64, true);
+    } else {
+        if (L <= 8) CHUNK_CASE(8, false);
+        else if (L <= 16) CHUNK_CASE(16, false);
+        else if (L <= 32) CHUNK_CASE(32, false);
+        else CHUNK_CASE(64, false);
+    }
 #undef CHUNK_CASE
     return hipGetLastError();
 }
@@ -685,13 +809,12 @@ extern "C" int regc_mbar_set_solver(regc_mbar *mb, int method, int memory)
 // squares ill-posed).  A step that raises the residual tenfold restarts the history;
 // a non-finite map value returns to the last finite one and takes plain steps for a
 // while.  Converged when max |g(x) - x| over sampled states < tol.
-extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters, double *delta)
+// start: NULL (f = 0) or the starting iterate [S] (host).
+static int solve_core(regc_mbar *mb, double tol, int max_iter, const double *start, int *iters, double *delta)
 {
-    REGC_CHECK(mb, REGC_EINVAL, "null handle");
-    REGC_CHECK(mb->have_samples, REGC_ESTATE, "no samples loaded");
-    REGC_CHECK(max_iter > 0 && tol > 0, REGC_EINVAL, "max_iter and tol must be positive");
     hipStream_t s = mb->stream;
-    REGC_HIP(hipMemsetAsync(mb->f_d.p, 0, sizeof(double) * mb->S, s));
+    if (start) REGC_HIP(hipMemcpyAsync(mb->f_d.p, start, sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
+    else REGC_HIP(hipMemsetAsync(mb->f_d.p, 0, sizeof(double) * mb->S, s));
     ScopedEvent e0, e1;
     REGC_HIP(e0.create());
     REGC_HIP(e1.create());
@@ -702,6 +825,7 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     const int n = (int)idx.size();
     const int m = std::min(mb->memory, std::max(n - 2, 0));
     std::vector<double> x(mb->S, 0.0), gx(mb->S), xs(n), gs(n), r(n);
+    if (start) x.assign(start, start + mb->S);
     std::deque<std::vector<double>> hist_r, hist_g;   // last residuals and map values (sampled part)
     double d = INFINITY, d_prev = INFINITY;
     int it = 0, plain_left = 0;
@@ -766,7 +890,6 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     REGC_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
     mb->ms_iter = ms;
     mb->n_iter = it;
-    if (f_out) REGC_HIP(hipMemcpy(f_out, mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
     if (iters) *iters = it;
     if (delta) *delta = d;
     mb->solved = true;
@@ -777,37 +900,75 @@ extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *
     return REGC_OK;
 }
 
+extern "C" int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int *iters, double *delta)
+{
+    REGC_CHECK(mb, REGC_EINVAL, "null handle");
+    REGC_CHECK(mb->have_samples, REGC_ESTATE, "no samples loaded");
+    REGC_CHECK(max_iter > 0 && tol > 0, REGC_EINVAL, "max_iter and tol must be positive");
+    const int rc = solve_core(mb, tol, max_iter, nullptr, iters, delta);
+    if (rc != REGC_OK && rc != REGC_ENOCONV) return rc;
+    if (f_out) REGC_HIP(hipMemcpy(f_out, mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
+    return rc;
+}
+
+// Target grid constants (beta per row, ln z per target) on the device.
+struct TargetDev {
+    int nT = 0, nMu = 0, nK = 0;
+    DevBuf<double> tb_d, tz_d;
+};
+
+static int target_grid(regc_mbar *mb, const regc_grid *targets, TargetDev &T)
+{
+    T.nT = targets->n_t;
+    T.nMu = targets->n_mu;
+    T.nK = T.nT * T.nMu;
+    REGC_CHECK(T.nT > 0 && T.nMu > 0, REGC_EINVAL, "empty target grid");
+    std::vector<double> tb(T.nT), tz(T.nK);
+    for (int l = 0; l < T.nT; ++l) {
+        REGC_CHECK(targets->t[l] > 0, REGC_EINVAL, "target temperatures must be positive");
+        tb[l] = 1.0 / targets->t[l];
+        for (int m = 0; m < T.nMu; ++m) tz[l * T.nMu + m] = lnz_of(targets->t[l], targets->mu[m], mb->lambda1);
+    }
+    int rc;
+    if ((rc = T.tb_d.alloc(T.nT)) || (rc = T.tz_d.alloc(T.nK))) return rc;
+    REGC_HIP(hipMemcpyAsync(T.tb_d.p, tb.data(), sizeof(double) * T.nT, hipMemcpyHostToDevice, mb->stream));
+    REGC_HIP(hipMemcpyAsync(T.tz_d.p, tz.data(), sizeof(double) * T.nK, hipMemcpyHostToDevice, mb->stream));
+    return REGC_OK;
+}
+
+// Reweighted averages at the targets into device arrays (any may be NULL but mn).
+static int targets_dev(regc_mbar *mb, const TargetDev &T, double *f, double *mn, double *me, double *me2,
+                       double *pn, int32_t *ph)
+{
+    hipStream_t s = mb->stream;
+    DevBuf<double> tpart;
+    int rc;
+    if ((rc = tpart.alloc((size_t)mb->nchunks * T.nT * 4))) return rc;
+    hipLaunchKernelGGL(mbar_target_chunk, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, T.nT, T.tb_d.p, mb->e_d.p,
+                       mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, tpart.p, mb->weighted ? mb->wgt_d.p : nullptr);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mbar_target_eval, dim3(T.nT), dim3(256), sizeof(double) * 3 * mb->nN, s, T.nT, T.nMu, mb->nN,
+                       tpart.p, mb->seg_c0_d.p, mb->seg_c1_d.p, T.tz_d.p, f, mn, me, me2, pn, ph);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));     // tpart is freed on return
+    return REGC_OK;
+}
+
 extern "C" int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
                                  double *mean_e, double *mean_e2, double *p_n, int32_t *phase)
 {
     REGC_CHECK(mb && targets && mean_n && targets->t && targets->mu, REGC_EINVAL, "null argument");
     REGC_CHECK(mb->solved, REGC_ESTATE, "solve first");
-    const int nT = targets->n_t, nMu = targets->n_mu, nK = nT * nMu;
-    REGC_CHECK(nT > 0 && nMu > 0, REGC_EINVAL, "empty target grid");
-    std::vector<double> tb(nT), tz(nK);
-    for (int l = 0; l < nT; ++l) {
-        REGC_CHECK(targets->t[l] > 0, REGC_EINVAL, "target temperatures must be positive");
-        tb[l] = 1.0 / targets->t[l];
-        for (int m = 0; m < nMu; ++m) tz[l * nMu + m] = lnz_of(targets->t[l], targets->mu[m], mb->lambda1);
-    }
-    hipStream_t s = mb->stream;
-    DevBuf<double> tb_d, tz_d, tpart, f_d, mn_d, me_d, me2_d, pn_d;
-    DevBuf<int32_t> ph_d;
+    TargetDev T;
     int rc;
-    if ((rc = tb_d.alloc(nT)) || (rc = tz_d.alloc(nK)) || (rc = tpart.alloc((size_t)mb->nchunks * nT * 4)) ||
-        (rc = f_d.alloc(nK)) || (rc = mn_d.alloc(nK)) || (rc = me_d.alloc(nK)) || (rc = me2_d.alloc(nK)) ||
+    if ((rc = target_grid(mb, targets, T))) return rc;
+    const int nK = T.nK;
+    DevBuf<double> f_d, mn_d, me_d, me2_d, pn_d;
+    DevBuf<int32_t> ph_d;
+    if ((rc = f_d.alloc(nK)) || (rc = mn_d.alloc(nK)) || (rc = me_d.alloc(nK)) || (rc = me2_d.alloc(nK)) ||
         (rc = ph_d.alloc(nK)) || (rc = pn_d.alloc(p_n ? (size_t)nK * mb->nN : 1)))
         return rc;
-    REGC_HIP(hipMemcpyAsync(tb_d.p, tb.data(), sizeof(double) * nT, hipMemcpyHostToDevice, s));
-    REGC_HIP(hipMemcpyAsync(tz_d.p, tz.data(), sizeof(double) * nK, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(mbar_target_chunk, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, nT, tb_d.p, mb->e_d.p,
-                       mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, tpart.p);
-    REGC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mbar_target_eval, dim3(nT), dim3(256), sizeof(double) * 3 * mb->nN, s, nT, nMu, mb->nN,
-                       tpart.p, mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d.p, f_d.p, mn_d.p, me_d.p, me2_d.p,
-                       p_n ? pn_d.p : nullptr, ph_d.p);
-    REGC_HIP(hipGetLastError());
-    REGC_HIP(hipStreamSynchronize(s));
+    if ((rc = targets_dev(mb, T, f_d.p, mn_d.p, me_d.p, me2_d.p, p_n ? pn_d.p : nullptr, ph_d.p))) return rc;
     if (f) REGC_HIP(hipMemcpy(f, f_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
     REGC_HIP(hipMemcpy(mean_n, mn_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
     if (mean_e) REGC_HIP(hipMemcpy(mean_e, me_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
@@ -844,6 +1005,7 @@ extern "C" int regc_mbar_observables(regc_mbar *mb, const regc_grid *targets, do
     REGC_CHECK(mb && targets && targets->t && targets->mu, REGC_EINVAL, "null argument");
     REGC_CHECK(mb->solved, REGC_ESTATE, "solve first");
     REGC_CHECK(mb->n_obs > 0, REGC_ESTATE, "no observables loaded");
+    REGC_CHECK(!mb->weighted, REGC_ESTATE, "a bootstrap is in progress");
     const int nT = targets->n_t, nMu = targets->n_mu, nK = nT * nMu, no = mb->n_obs;
     REGC_CHECK(nT > 0 && nMu > 0, REGC_EINVAL, "empty target grid");
     std::vector<double> tb(nT), tz(nK);
@@ -881,3 +1043,228 @@ extern "C" int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n
 }
 
 extern "C" void regc_mbar_destroy(regc_mbar *mb) { delete mb; }
+
+// ---------------------------------------------------------------------------
+// Estimates with their errors: the solve, the averages at the targets, batch means
+// at the sampled states and a moving-block bootstrap over records (re-solving with
+// the records' multiplicities as sample weights, warm-started from the full solve).
+extern "C" void regc_default_reweight_opts(regc_reweight_opts *o)
+{
+    if (!o) return;
+    o->n_batches = 20;
+    o->n_boot = 100;
+    o->record_size = 0;
+    o->block_records = 0;
+    o->seed = 1;
+    o->n_sites = 0.0;
+}
+
+// Sets the handle's state counts (and gauge) from a device array of counts.
+static int set_omega(regc_mbar *mb, const unsigned long long *omega_d)
+{
+    std::vector<unsigned long long> h(mb->S);
+    REGC_HIP(hipMemcpyAsync(h.data(), omega_d, sizeof(unsigned long long) * mb->S, hipMemcpyDeviceToHost, mb->stream));
+    REGC_HIP(hipStreamSynchronize(mb->stream));
+    mb->lnomega.assign(mb->S, -INFINITY);
+    mb->gauge = -1;
+    for (int k = 0; k < mb->S; ++k)
+        if (h[k] > 0) {
+            mb->lnomega[k] = std::log((double)h[k]);
+            if (mb->gauge < 0) mb->gauge = k;
+        }
+    REGC_HIP(hipMemcpyAsync(mb->lnomega_d.p, mb->lnomega.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice,
+                            mb->stream));
+    return REGC_OK;
+}
+
+// log D of the current f (after changing the weights or restoring f)
+static int refresh_logd(regc_mbar *mb)
+{
+    hipLaunchKernelGGL(mbar_loga, dim3(mb->L), dim3(256), 0, mb->stream, mb->M, mb->nN, mb->lnomega_d.p, mb->f_d.p,
+                       mb->lnz_d.p, mb->logA_d.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(launch_chunk(mb, mb->logd_d.p));
+    return REGC_OK;
+}
+
+static int batch_means_dev(regc_mbar *mb, int B, double *mean_d, double *se_d)
+{
+    hipStream_t s = mb->stream;
+    const int64_t ns = mb->ns;
+    DevBuf<uint32_t> keys, keys_out;
+    DevBuf<int32_t> idx, idx_out;
+    DevBuf<int64_t> start_d, count_d;
+    DevBuf<unsigned long long> bsum, bcnt, omega, seg;
+    DevBuf<int> bad;
+    int rc;
+    if ((rc = keys.alloc(ns)) || (rc = keys_out.alloc(ns)) || (rc = idx.alloc(ns)) || (rc = idx_out.alloc(ns)) ||
+        (rc = start_d.alloc(mb->S)) || (rc = count_d.alloc(mb->S)) || (rc = bsum.alloc((size_t)mb->S * B)) ||
+        (rc = bcnt.alloc((size_t)mb->S * B)) || (rc = omega.alloc(mb->S)) || (rc = seg.alloc(mb->nN)) ||
+        (rc = bad.alloc(1)))
+        return rc;
+    const int grid = (int)std::min<int64_t>((ns + 255) / 256, 4096);
+    // stable sort of the sample indices by state: each state's series in sample order
+    hipLaunchKernelGGL(mbar_iota_gather, dim3(grid), dim3(256), 0, s, ns, mb->s_orig_d.p, keys.p, idx.p);
+    REGC_HIP(hipGetLastError());
+    int end_bit = 1;
+    while ((1 << end_bit) < mb->S) ++end_bit;
+    size_t temp_bytes = 0;
+    REGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
+                                                end_bit, s));
+    DevBuf<unsigned char> temp;
+    if ((rc = temp.alloc(temp_bytes))) return rc;
+    REGC_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
+                                                end_bit, s));
+    // per-state counts (the unweighted ones) and series starts
+    std::vector<unsigned long long> cnt(mb->S);
+    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(256), 0, s, (int64_t)mb->S, omega.p);
+    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(256), 0, s, (int64_t)mb->nN, seg.p);
+    hipLaunchKernelGGL(mbar_count, dim3(grid), dim3(256), 0, s, ns, mb->n_orig_d.p, mb->s_orig_d.p, mb->nN, mb->S,
+                       omega.p, seg.p, bad.p);     // (samples were validated when loaded)
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipMemcpyAsync(cnt.data(), omega.p, sizeof(unsigned long long) * mb->S, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> start(mb->S), count(mb->S);
+    int64_t acc = 0;
+    for (int k = 0; k < mb->S; ++k) {
+        start[k] = acc;
+        count[k] = (int64_t)cnt[k];
+        acc += count[k];
+    }
+    REGC_HIP(hipMemcpyAsync(start_d.p, start.data(), sizeof(int64_t) * mb->S, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(count_d.p, count.data(), sizeof(int64_t) * mb->S, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)mb->S * B, bsum.p);
+    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)mb->S * B, bcnt.p);
+    hipLaunchKernelGGL(bm_accumulate, dim3(grid), dim3(256), 0, s, ns, B, (const int32_t *)keys_out.p, idx_out.p,
+                       mb->n_orig_d.p, start_d.p, count_d.p, bsum.p, bcnt.p);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bm_finish, dim3((mb->S + 255) / 256), dim3(256), 0, s, mb->S, B, bsum.p, bcnt.p, count_d.p,
+                       mean_d, se_d);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    return REGC_OK;
+}
+
+extern "C" int regc_reweight(regc_mbar *mb, const regc_grid *targets, double tol, int max_iter,
+                             const regc_reweight_opts *opts, double *f_states, double *mean_state_n,
+                             double *se_state_n, double *mean_n, double *se_n, int32_t *phase, double *coverage,
+                             double *se_coverage, double *heat_cap, double *se_heat_cap, double *p_n)
+{
+    REGC_CHECK(mb && targets && targets->t && targets->mu, REGC_EINVAL, "null argument");
+    REGC_CHECK(mb->have_samples, REGC_ESTATE, "no samples loaded");
+    REGC_CHECK(max_iter > 0 && tol > 0, REGC_EINVAL, "max_iter and tol must be positive");
+    regc_reweight_opts o;
+    regc_default_reweight_opts(&o);
+    if (opts) o = *opts;
+    const int64_t rs = o.record_size > 0 ? o.record_size : mb->S;
+    REGC_CHECK(o.n_batches >= 2 && o.n_boot >= 0 && o.n_boot != 1, REGC_EINVAL,
+               "n_batches must be >= 2 and n_boot 0 or >= 2");
+    REGC_CHECK(mb->ns % rs == 0, REGC_EINVAL, "%lld samples are not whole records of %lld", (long long)mb->ns,
+               (long long)rs);
+    const int64_t R = mb->ns / rs;
+    const int64_t blk = o.block_records > 0 ? o.block_records : std::max<int64_t>(1, R / o.n_batches);
+    REGC_CHECK(blk <= R, REGC_EINVAL, "bootstrap blocks of %lld records exceed the %lld records", (long long)blk,
+               (long long)R);
+    REGC_CHECK((coverage == nullptr && se_coverage == nullptr) || o.n_sites > 0, REGC_EINVAL,
+               "coverage needs n_sites > 0");
+    hipStream_t s = mb->stream;
+    mb->weighted = false;
+    int rc = solve_core(mb, tol, max_iter, nullptr, nullptr, nullptr);
+    if (rc != REGC_OK && rc != REGC_ENOCONV) return rc;
+    const int solve_rc = rc;
+    std::vector<double> f0(mb->S);
+    REGC_HIP(hipMemcpy(f0.data(), mb->f_d.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
+    if (f_states) std::copy(f0.begin(), f0.end(), f_states);
+    TargetDev T;
+    if ((rc = target_grid(mb, targets, T))) return rc;
+    const int nK = T.nK;
+    DevBuf<double> mn, me, me2, pn, heat, cov, smean, sse;
+    DevBuf<int32_t> ph;
+    if ((rc = mn.alloc(nK)) || (rc = me.alloc(nK)) || (rc = me2.alloc(nK)) || (rc = ph.alloc(nK)) ||
+        (rc = pn.alloc(p_n ? (size_t)nK * mb->nN : 1)) || (rc = heat.alloc(nK)) || (rc = cov.alloc(nK)) ||
+        (rc = smean.alloc(mb->S)) || (rc = sse.alloc(mb->S)))
+        return rc;
+    if ((rc = targets_dev(mb, T, nullptr, mn.p, me.p, me2.p, p_n ? pn.p : nullptr, ph.p))) return rc;
+    hipLaunchKernelGGL(heat_cov, dim3((nK + 255) / 256), dim3(256), 0, s, T.nT, T.nMu, T.tb_d.p, mn.p, me.p, me2.p,
+                       o.n_sites > 0 ? o.n_sites : 1.0, heat.p, cov.p);
+    REGC_HIP(hipGetLastError());
+    if ((rc = batch_means_dev(mb, o.n_batches, smean.p, sse.p))) return rc;
+    REGC_HIP(hipStreamSynchronize(s));
+    if (mean_n) REGC_HIP(hipMemcpy(mean_n, mn.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (phase) REGC_HIP(hipMemcpy(phase, ph.p, sizeof(int32_t) * nK, hipMemcpyDeviceToHost));
+    if (p_n) REGC_HIP(hipMemcpy(p_n, pn.p, sizeof(double) * nK * mb->nN, hipMemcpyDeviceToHost));
+    if (heat_cap) REGC_HIP(hipMemcpy(heat_cap, heat.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (coverage) REGC_HIP(hipMemcpy(coverage, cov.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (mean_state_n) REGC_HIP(hipMemcpy(mean_state_n, smean.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
+    if (se_state_n) REGC_HIP(hipMemcpy(se_state_n, sse.p, sizeof(double) * mb->S, hipMemcpyDeviceToHost));
+    const bool want_boot = se_n || se_coverage || se_heat_cap;
+    if (!want_boot || o.n_boot == 0) {
+        const double nan = NAN;
+        for (int k = 0; k < nK; ++k) {
+            if (se_n) se_n[k] = nan;
+            if (se_coverage) se_coverage[k] = nan;
+            if (se_heat_cap) se_heat_cap[k] = nan;
+        }
+        return solve_rc;
+    }
+    // bootstrap replicates
+    const int B = o.n_boot;
+    const std::vector<double> lnomega0 = mb->lnomega;
+    const int gauge0 = mb->gauge;
+    DevBuf<int32_t> mult;
+    DevBuf<unsigned long long> omega;
+    DevBuf<double> rep_n, rep_c, sd_n, sd_c, bme, bme2;
+    if ((rc = mult.alloc(R)) || (rc = omega.alloc(mb->S)) || (rc = mb->wgt_d.alloc(mb->ns)) ||
+        (rc = rep_n.alloc((size_t)B * nK)) || (rc = rep_c.alloc((size_t)B * nK)) || (rc = sd_n.alloc(nK)) ||
+        (rc = sd_c.alloc(nK)) || (rc = bme.alloc(nK)) || (rc = bme2.alloc(nK)))
+        return rc;
+    const int grid = (int)std::min<int64_t>((mb->ns + 255) / 256, 4096);
+    const int64_t nblk = (R + blk - 1) / blk;
+    int boot_rc = REGC_OK;
+    for (int b = 0; b < B && boot_rc == REGC_OK; ++b) {
+        hipLaunchKernelGGL(fill_i32, dim3((unsigned)std::min<int64_t>((R + 255) / 256, 4096)), dim3(256), 0, s, R, 0,
+                           mult.p);
+        hipLaunchKernelGGL(boot_mult, dim3((unsigned)std::min<int64_t>((nblk + 255) / 256, 4096)), dim3(256), 0, s, R,
+                           blk, b, (uint32_t)o.seed, (uint32_t)(o.seed >> 32), mult.p);
+        hipLaunchKernelGGL(fill_u64, dim3(1), dim3(256), 0, s, (int64_t)mb->S, omega.p);
+        hipLaunchKernelGGL(boot_weights, dim3(grid), dim3(256), 0, s, mb->ns, rs, mb->perm_d.p, mb->s_orig_d.p, mult.p,
+                           mb->wgt_d.p, omega.p);
+        REGC_HIP(hipGetLastError());
+        if ((rc = set_omega(mb, omega.p))) { boot_rc = rc; break; }
+        mb->weighted = true;
+        rc = solve_core(mb, tol, max_iter, f0.data(), nullptr, nullptr);
+        if (rc != REGC_OK && rc != REGC_ENOCONV) { boot_rc = rc; break; }
+        if (rc == REGC_ENOCONV) boot_rc = REGC_ENOCONV;
+        if ((rc = targets_dev(mb, T, nullptr, rep_n.p + (size_t)b * nK, bme.p, bme2.p, nullptr, ph.p))) {
+            boot_rc = rc;
+            break;
+        }
+        hipLaunchKernelGGL(heat_cov, dim3((nK + 255) / 256), dim3(256), 0, s, T.nT, T.nMu, T.tb_d.p,
+                           rep_n.p + (size_t)b * nK, bme.p, bme2.p, 1.0, rep_c.p + (size_t)b * nK, nullptr);
+        REGC_HIP(hipGetLastError());
+    }
+    // back to the full data: counts, f, log D
+    mb->weighted = false;
+    mb->lnomega = lnomega0;
+    mb->gauge = gauge0;
+    REGC_HIP(hipMemcpyAsync(mb->lnomega_d.p, lnomega0.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(mb->f_d.p, f0.data(), sizeof(double) * mb->S, hipMemcpyHostToDevice, s));
+    if ((rc = refresh_logd(mb))) return rc;
+    REGC_HIP(hipStreamSynchronize(s));
+    if (boot_rc != REGC_OK && boot_rc != REGC_ENOCONV) return boot_rc;
+    hipLaunchKernelGGL(rep_sd, dim3((nK + 255) / 256), dim3(256), 0, s, B, nK, rep_n.p, sd_n.p);
+    hipLaunchKernelGGL(rep_sd, dim3((nK + 255) / 256), dim3(256), 0, s, B, nK, rep_c.p, sd_c.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    std::vector<double> h(nK);
+    REGC_HIP(hipMemcpy(h.data(), sd_n.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (se_n) std::copy(h.begin(), h.end(), se_n);
+    if (se_coverage)
+        for (int k = 0; k < nK; ++k) se_coverage[k] = h[k] / o.n_sites;
+    if (se_heat_cap) REGC_HIP(hipMemcpy(se_heat_cap, sd_c.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
+    if (boot_rc == REGC_ENOCONV) {
+        set_error("a bootstrap replicate did not converge");
+        return REGC_ENOCONV;
+    }
+    return solve_rc;
+}

@@ -546,6 +546,34 @@ extern "C" int regc_mlp_loss_grads(regc_mlp *h, int B, int nmax, const uint16_t 
     return REGC_OK;
 }
 
+extern "C" int regc_mlp_step(regc_mlp *h, int B, int nmax, const uint16_t *vox, const int32_t *n,
+                             const int32_t *excl, const int32_t *target, double lr, double *loss, float *grads)
+{
+    REGC_CHECK(h && vox && n && excl && target, REGC_EINVAL, "null argument");
+    REGC_CHECK(lr > 0, REGC_EINVAL, "learning rate must be positive");
+    int rc;
+    if ((rc = check_batch(B, nmax, vox, n, excl, target)) || (rc = mlp_workspace(h, B, nmax)) ||
+        (rc = upload_batch(h, B, nmax, vox, n, excl, target)) || (rc = mlp_backward_dev(h, B, nmax)))
+        return rc;
+    hipStream_t s = h->stream;
+    const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+    h->t += 1;
+    const float c1 = 1.0f - powf(beta1, (float)h->t), c2 = 1.0f - powf(beta2, (float)h->t);
+    hipLaunchKernelGGL(adam_update, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, s, (size_t)NPARAM, h->p.p,
+                       h->g.p, h->m.p, h->v.p, (float)lr, c1, c2, beta1, beta2, eps, h->p16.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipStreamSynchronize(s));
+    if (loss) {
+        std::vector<float> l(B);
+        REGC_HIP(hipMemcpy(l.data(), h->loss.p, sizeof(float) * B, hipMemcpyDeviceToHost));
+        double acc = 0.0;
+        for (float x : l) acc += x;
+        *loss = acc / B;
+    }
+    if (grads) REGC_HIP(hipMemcpy(grads, h->g.p, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
 extern "C" int regc_mlp_train(regc_mlp *h, int64_t n_examples, int nmax, const uint16_t *vox_dev,
                               const int32_t *n_dev, int64_t steps, int batch, double lr, uint64_t seed,
                               double *mean_loss)

@@ -76,6 +76,7 @@ struct SweepArgs {
     int max_slab_len;               // LDS carve sizes of this launch
     int gas_stride;                 // LDS entries per walker (max n_max over classes)
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
+    int resync_every;               // > 0: running energy recomputed after every resync_every-th sweep
 };
 
 // Structural observables of every walker at a sample point (see regc.h).

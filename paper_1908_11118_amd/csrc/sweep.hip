@@ -267,7 +267,20 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
             if (tracing && part == 0 && lane == 0)
                 a.trace_bits[((size_t)(sweep - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
         }
-        // ---- end of sweep: trace N, sample record ----
+        // ---- end of sweep: running energy resynchronised, trace N, sample record ----
+        if (a.resync_every > 0 && (sweep + 1) % a.resync_every == 0 && !ideal) {
+            const double pe = full_energy_part<SPLIT>(gas, n, sv, b, gg, gs, lane, part);
+            if (SPLIT == 1) {
+                e = pe;
+            } else {
+                double *mine = xch + ((xcount & 1) * 2 + part) * 2;
+                if (lane == 0) mine[0] = pe;
+                __syncthreads();
+                const double *x0 = xch + (xcount & 1) * 4;
+                e = x0[0] + x0[2];
+                ++xcount;
+            }
+        }
         if (part == 0 && lane == 0) {
             if (tracing) a.trace_n[(size_t)(sweep - a.trace_sweep0) * a.n_walkers + w] = n;
             if (a.sample_every > 0 && (sweep + 1) % a.sample_every == 0) {

@@ -174,6 +174,43 @@ __device__ __forceinline__ uint32_t wrap_col(int c, int d, int nc)
     return min(u, u - (uint32_t)nc);
 }
 
+// Slab entry kk (0 <= kk < 9 cap) of the 3x3 column block around column (cx, cy):
+// slot kk % cap of the block's column sp = kk / cap, sp = 3 (dy + 1) + (dx + 1).
+__device__ __forceinline__ int block_entry(const SlabView &sv, int cx, int cy, int kk)
+{
+    const int sp = (int)(((float)kk + 0.5f) * sv.inv_cap);
+    const int q = (sp * 11) >> 5;   // sp / 3 for sp in 0..8
+    const uint32_t ux = wrap_col(cx, sp - 3 * q - 1, sv.ncx);
+    const uint32_t uy = wrap_col(cy, q - 1, sv.ncy);
+    return (int)((uy * (uint32_t)sv.ncx + ux) * (uint32_t)sv.cap) + (kk - sp * sv.cap);
+}
+
+// This wave's part (wave `part` of SPLIT) of the walker's total energy: every gas
+// pair once and every gas atom against the slab entries that can lie within the
+// cutoff (its column block, or all entries when unbinned), pair terms in Real,
+// per-lane sums in FP64.  Returns the wave-uniform partial sum.
+template <int SPLIT>
+__device__ double full_energy_part(const Real4 *gas, int n, const SlabView &sv, const Box &b, const Pair &gg,
+                                   const Pair &gs, int lane, int part)
+{
+    double acc = 0.0;
+    const int total = sv.bins ? 9 * sv.cap : sv.len;
+    for (int i = 0; i < n; ++i) {
+        const Real4 p = gas[i];
+        for (int j = i + 1 + part * kWave + lane; j < n; j += SPLIT * kWave)
+            acc += (double)lj(dist2(b, p.x, p.y, p.z, gas[j]), gg);
+        if (p.z < sv.top_plus_rc) {
+            int cx = 0, cy = 0;
+            if (sv.bins) column_of(sv, p.x, p.y, cx, cy);
+            for (int k = part * kWave + lane; k < total; k += SPLIT * kWave) {
+                const int idx = sv.bins ? block_entry(sv, cx, cy, k) : k;
+                acc += (double)lj(dist2(b, p.x, p.y, p.z, sv.atoms[idx]), gs);
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
 // Appends the lanes' values whose predicate holds to an LDS queue (wave-wide
 // compaction): each lane's slot is the number of set predicate bits below it.
 __device__ __forceinline__ void push(Real *queue, int &count, bool pred, Real value)
@@ -262,15 +299,7 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
                 const int k = k0 + u * kWave + lane;
                 vv[u] = k < total;
                 const int kk = vv[u] ? k : 0;
-                int idx = kk;
-                if (bins) {
-                    const int sp = (int)(((float)kk + 0.5f) * sv.inv_cap);
-                    const int q = (sp * 11) >> 5;   // sp / 3 for sp in 0..8
-                    const uint32_t ux = wrap_col(cx, sp - 3 * q - 1, sv.ncx);
-                    const uint32_t uy = wrap_col(cy, q - 1, sv.ncy);
-                    idx = (int)((uy * (uint32_t)sv.ncx + ux) * (uint32_t)sv.cap) + (kk - sp * sv.cap);
-                }
-                g[u] = sv.atoms[idx];
+                g[u] = sv.atoms[bins ? block_entry(sv, cx, cy, kk) : kk];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)

@@ -34,7 +34,8 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
            "regc_set_proposal", "regc_set_class_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
            "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables",
-           "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error"]
+           "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error",
+           "regc_default_reweight_opts", "regc_reweight", "regc_mlp_step", "regc_proposal_eval"]
 
 
 class RegcError(RuntimeError):
@@ -69,6 +70,11 @@ class ObsSpec(C.Structure):
                 ("n_r", C.c_int)]
 
 
+class ReweightOpts(C.Structure):
+    _fields_ = [("n_batches", C.c_int), ("n_boot", C.c_int), ("record_size", C.c_int64),
+                ("block_records", C.c_int64), ("seed", C.c_uint64), ("n_sites", C.c_double)]
+
+
 class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("precision", C.c_int), ("p_disp", C.c_double), ("p_ins", C.c_double),
                 ("max_disp", C.c_double), ("trials_per_sweep", C.c_int), ("swap_every", C.c_int),
@@ -76,7 +82,7 @@ class Opts(C.Structure):
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
                 ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
                 ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
-                ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double)]
+                ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double), ("resync_every", C.c_int)]
 
 
 _lib = None
@@ -127,6 +133,10 @@ def lib():
         L.regc_mbar_solve.argtypes = [vp, C.c_double, C.c_int, _dp, C.POINTER(C.c_int), _dp]
         L.regc_mbar_targets.argtypes = [vp, C.POINTER(Grid), _dp, _dp, _dp, _dp, _dp, _i32p]
         L.regc_mbar_timing.argtypes = [vp, _dp, _i64p]
+        L.regc_default_reweight_opts.argtypes = [C.POINTER(ReweightOpts)]
+        L.regc_default_reweight_opts.restype = None
+        L.regc_reweight.argtypes = [vp, C.POINTER(Grid), C.c_double, C.c_int, C.POINTER(ReweightOpts)] + \
+            [_dp] * 5 + [_i32p] + [_dp] * 5
         L.regc_mbar_destroy.argtypes = [vp]
         L.regc_mbar_destroy.restype = None
         _u16p = C.POINTER(C.c_uint16)
@@ -140,6 +150,9 @@ def lib():
                                           C.POINTER(C.c_float)]
         L.regc_mlp_train.argtypes = [vp, C.c_int64, C.c_int, vp, vp, C.c_int64, C.c_int, C.c_double,
                                      C.c_uint64, _dp]
+        L.regc_mlp_step.argtypes = [vp, C.c_int, C.c_int, _u16p, _i32p, _i32p, _i32p, C.c_double, _dp,
+                                    C.POINTER(C.c_float)]
+        L.regc_proposal_eval.argtypes = [vp, C.c_int, C.c_int, _i32p, _dp, _i32p, C.POINTER(C.c_float), _dp, _dp]
         L.regc_mlp_timing.argtypes = [vp, _dp, _i64p]
         L.regc_mlp_destroy.argtypes = [vp]
         L.regc_mlp_destroy.restype = None
@@ -195,7 +208,7 @@ class Regc:
 
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
                  walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
-                 cull: int = 0, graph_intervals: int = 0, stream=None):
+                 cull: int = 0, graph_intervals: int = 0, resync_every: int = 0, stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
         self.workloads = wl
@@ -224,6 +237,7 @@ class Regc:
         o.md_steps = int(getattr(w0, "md_steps", 0))
         o.md_dt = float(getattr(w0, "md_dt", 0.005))
         o.md_tau = float(getattr(w0, "md_tau", 0.1))
+        o.resync_every = resync_every
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:
@@ -406,6 +420,21 @@ class Regc:
         (asynchronous on the context's stream)."""
         _check(lib().regc_capture_voxels(self.h, C.c_void_p(vox_dev_ptr), C.c_void_p(n_dev_ptr)))
 
+    def proposal_eval(self, n, xyz, skip, cls: int = 0):
+        """The sampler's network on configurations: (logits [C, 4096], lse [C], lnp [C, 4096])."""
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        nc = len(n)
+        x = np.zeros((nc, self.n_max_all, 3))
+        for k in range(nc):
+            x[k, : n[k]] = np.asarray(xyz[k], dtype=np.float64).reshape(-1, 3)[: n[k]]
+        sk = np.ascontiguousarray(skip, dtype=np.int32)
+        lg = np.zeros((nc, 4096), np.float32)
+        lse = np.zeros(nc)
+        lnp = np.zeros((nc, 4096))
+        _check(lib().regc_proposal_eval(self.h, cls, nc, _p(n, _i32p), _p(x, _dp), _p(sk, _i32p), _p(lg, _fp),
+                                        _p(lse, _dp), _p(lnp, _dp)))
+        return lg, lse, lnp
+
     def proposal_stats(self):
         """{'passes', 'cached', 'drawn', 'drawn_accepted'} of the learned proposal."""
         out = np.zeros(4, np.int64)
@@ -474,6 +503,37 @@ class Mbar:
         _check(lib().regc_mbar_targets(self.h, C.byref(g), _p(f, _dp), _p(mn, _dp), _p(me, _dp), _p(me2, _dp),
                                        _p(pn, _dp), _p(ph, _i32p)))
         return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "p_n": pn, "phase": ph}
+
+    def reweight(self, t, mu, tol: float = 1e-10, max_iter: int = 10000, n_batches: int = 20, n_boot: int = 100,
+                 record_size: int = 0, block_records: int = 0, seed: int = 1, n_sites: float = 0.0,
+                 allow_noconv: bool = False):
+        """Estimates with errors (regc_reweight): on the sampled grid f, direct mean N
+        and its batch-means SE; on the target grid mean N, bootstrap SE, phase,
+        coverage (n_sites > 0) and heat capacity with their SEs, p(N)."""
+        keep = []
+        g = _grid(t, mu, keep)
+        K = len(keep[0]) * len(keep[1])
+        S = len(self.t) * len(self.mu)
+        o = ReweightOpts()
+        lib().regc_default_reweight_opts(C.byref(o))
+        o.n_batches, o.n_boot, o.record_size, o.block_records = n_batches, n_boot, record_size, block_records
+        o.seed, o.n_sites = seed, n_sites
+        out = {k: np.zeros(S) for k in ("f_states", "mean_state_n", "se_state_n")}
+        for k in ("mean_n", "se_n", "coverage", "se_coverage", "heat_cap", "se_heat_cap"):
+            out[k] = np.zeros(K)
+        out["phase"] = np.zeros(K, np.int32)
+        out["p_n"] = np.zeros((K, self.n_max + 1))
+        cov = n_sites > 0
+        rc = _check(lib().regc_reweight(
+            self.h, C.byref(g), tol, max_iter, C.byref(o), _p(out["f_states"], _dp), _p(out["mean_state_n"], _dp),
+            _p(out["se_state_n"], _dp), _p(out["mean_n"], _dp), _p(out["se_n"], _dp), _p(out["phase"], _i32p),
+            _p(out["coverage"], _dp) if cov else None, _p(out["se_coverage"], _dp) if cov else None,
+            _p(out["heat_cap"], _dp), _p(out["se_heat_cap"], _dp), _p(out["p_n"], _dp)),
+            allow=(ENOCONV,) if allow_noconv else ())
+        if not cov:
+            del out["coverage"], out["se_coverage"]
+        out["converged"] = rc == OK
+        return out
 
     def set_observables(self, obs):
         """Per-sample observables [ns, n_obs] in the order of the samples (uint32)."""
@@ -559,6 +619,17 @@ class Mlp:
         g = np.zeros(self.n_params, np.float32)
         _check(lib().regc_mlp_loss_grads(self.h, B, nmax, _p(vox, _u16p), _p(n, _i32p), _p(excl, _i32p),
                                          _p(tgt, _i32p), C.byref(loss), _p(g, _fp)))
+        return loss.value, g
+
+    def step(self, vox, n, excl, target, lr: float = 1e-3):
+        """One Adam step on the batch; returns (loss, the gradient applied)."""
+        vox, n, excl = self._batch(vox, n, excl)
+        tgt = np.ascontiguousarray(target, dtype=np.int32)
+        B, nmax = vox.shape
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        _check(lib().regc_mlp_step(self.h, B, nmax, _p(vox, _u16p), _p(n, _i32p), _p(excl, _i32p), _p(tgt, _i32p),
+                                   lr, C.byref(loss), _p(g, _fp)))
         return loss.value, g
 
     def train(self, n_examples: int, nmax: int, vox_dev_ptr: int, n_dev_ptr: int, steps: int, batch: int = 256,
