@@ -161,7 +161,16 @@ typedef struct {
  *                  precision (pair terms in FP32 or FP64, sums in FP64), so the FP32
  *                  pair mode's accumulated rounding never grows; 0: default (100 in
  *                  REGC_FP32PAIR, never in REGC_FP64, whose running sums match the
- *                  oracle's), -1: never. */
+ *                  oracle's), -1: never.
+ *  batch_trials    sweep schedule without the learned proposal: 2 or 4 evaluates that
+ *                  many consecutive trials of a walker at once (one wavefront per walker,
+ *                  64 / batch_trials lanes per trial) on the configuration at the start
+ *                  of the batch, then decides them in order, correcting each trial's
+ *                  energy change by its pair terms with the moves accepted before it in
+ *                  the batch and leaving to the next batch a trial whose particle index
+ *                  or particle an earlier accepted move changed: the accept/reject
+ *                  sequence and configurations are those of one trial at a time.  1: one
+ *                  trial at a time (split and cull apply).  0: 1. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -182,6 +191,7 @@ typedef struct {
     int md_steps;
     double md_dt, md_tau;
     int resync_every;
+    int batch_trials;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;
@@ -263,11 +273,17 @@ int regc_clear_samples(regc_ctx *ctx);
  * total number of states (sum over classes); any pointer may be NULL. */
 int regc_get_stats(regc_ctx *ctx, int64_t *stats, int64_t *swap_att, int64_t *swap_acc);
 
-/* Work counters of the sweep kernel since create: candidates = pair terms
- * evaluated (a displacement evaluates each candidate at the old and the new
- * position, so it counts twice), within_cutoff = those with r < rcut.  Either
- * pointer may be NULL. */
+/* Work counters of the sweep kernel since create: candidates = pair terms a trial
+ * needs (the one-trial kernel: gas and slab candidates at the old and the new
+ * position of a displacement; the batched kernel, which keeps each particle's slab
+ * energy: gas candidates at both positions, slab candidates at the new one),
+ * within_cutoff = those with r < rcut (the batched kernel counts them only while
+ * regc_count_pairs is on).  Either pointer may be NULL. */
 int regc_get_pair_counts(regc_ctx *ctx, int64_t *candidates, int64_t *within_cutoff);
+
+/* on != 0: the batched-trial kernel also counts the pair terms inside the cutoff
+ * (a diagnostic variant of the kernel, a little slower); 0: it does not. */
+int regc_count_pairs(regc_ctx *ctx, int on);
 
 /* Histogram of recorded N per state: S_total x (n_max_all + 1) counts, where
  * n_max_all is the largest n_max over the classes. */

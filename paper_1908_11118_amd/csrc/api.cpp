@@ -49,6 +49,8 @@ struct regc_ctx {
     hipStream_t stream = nullptr;
     int wpb = 1, split = 1, nblocks = 0, max_slab_len = 0, max_slab_scan = 0;
     bool cull = false;
+    int batch = 1;     // trials per pass of the sweep kernel (1: one-trial kernel)
+    bool count_pairs = false;   // batched kernel: count pair terms inside the cutoff
     size_t smem = 0;
 
     DevBuf<ClassDev> cls_d;
@@ -153,6 +155,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->md_dt = 0.005;
     o->md_tau = 0.1;
     o->resync_every = 0;
+    o->batch_trials = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -186,6 +189,8 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->graph_intervals >= 0 && o->graph_intervals <= 1000, REGC_EINVAL, "graph_intervals must be 0..1000");
     REGC_CHECK(o->schedule == 0 || o->schedule == 1, REGC_EUNSUPPORTED, "unknown schedule %d", o->schedule);
     REGC_CHECK(o->resync_every >= -1, REGC_EINVAL, "resync_every must be -1, 0 or positive");
+    REGC_CHECK(o->batch_trials >= 0 && o->batch_trials <= 4 && o->batch_trials != 3, REGC_EINVAL,
+               "batch_trials must be 0, 1, 2 or 4");
     if (o->schedule == 1) {
         REGC_CHECK(o->x0 >= 0.0 && o->x0 <= 1.0, REGC_EINVAL, "x0 must lie in [0, 1]");
         REGC_CHECK(o->mc_cycles >= 0 && o->mc_cycles <= 1000, REGC_EINVAL, "mc_cycles must be 0..1000");
@@ -336,10 +341,16 @@ static int ctx_alloc_and_init(regc_ctx *c)
     // wave halves its pair loop; measured 2.8 % faster at 1024 walkers and 2.2 % at 64
     // on 256 CUs), one above that (25 % slower with two at 4096 walkers, where four
     // walkers per SIMD already hide the latency).  The paper's step keeps one.
-    int split = o.split > 0 ? o.split
-                            : ((o.schedule == 0 && o.walkers_per_block == 0 && W <= 4 * n_cu) ? 2 : 1);
-    const bool cull = o.cull > 0;
+    // one trial at a time unless batched trials are requested (measured slower at 1024
+    // walkers on 256 CUs: one wave per SIMD leaves the batch's serial decisions exposed)
+    const int batch = o.schedule != 0 ? 1 : (o.batch_trials > 0 ? o.batch_trials : 1);
+    int split = batch > 1 ? 1
+                          : (o.split > 0 ? o.split
+                                         : ((o.schedule == 0 && o.walkers_per_block == 0 && W <= 4 * n_cu &&
+                                             c->pot.mode != REGC_MODE_IDEAL) ? 2 : 1));
+    const bool cull = batch == 1 && o.cull > 0;
     auto smem_for = [&](int wpb) {
+        if (batch > 1) return batch_lds(max_slab_len, nmax, wpb, real).total;
         return lds_layout(max_slab_len, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
     };
     int wpb = split == 2 ? 1 : o.walkers_per_block;
@@ -350,6 +361,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
     c->wpb = wpb;
     c->split = split;
     c->cull = cull;
+    c->batch = batch;
     c->smem = smem_for(wpb);
     if (o.schedule == 1 && o.md_steps > 0) {
         c->smem = lds_round(c->smem) + md_lds_bytes(nmax, wpb);
@@ -580,6 +592,7 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     a.max_slab_len = c->max_slab_len;
     a.gas_stride = c->nmax_all;
     a.max_slab_scan = c->max_slab_scan;
+    a.count_pairs = c->count_pairs ? 1 : 0;
     a.resync_every = c->opts.resync_every > 0 ? c->opts.resync_every
                                               : (c->opts.resync_every == 0 && c->opts.precision == REGC_FP32PAIR ? 100 : 0);
     int rc;
@@ -623,9 +636,9 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
         else
             REGC_HIP(launch_learned_f32(a, l, c->learn_smem, stream));
     } else if (c->opts.precision == REGC_FP64) {
-        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
+        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
     } else {
-        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->smem, stream));
+        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
     }
     if (ev && (rc = record_event(c, c->ev_sweep, false))) return rc;
     return REGC_OK;
@@ -1299,6 +1312,15 @@ extern "C" int regc_get_stats(regc_ctx *c, int64_t *stats, int64_t *swap_att, in
     if (stats) REGC_HIP(hipMemcpy(stats, c->stats_d.p, sizeof(int64_t) * (size_t)c->W * kNStat, hipMemcpyDeviceToHost));
     if (swap_att) REGC_HIP(hipMemcpy(swap_att, c->att_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
     if (swap_acc) REGC_HIP(hipMemcpy(swap_acc, c->acc_d.p, sizeof(int64_t) * 4 * c->W, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+extern "C" int regc_count_pairs(regc_ctx *c, int on)
+{
+    REGC_CHECK(c, REGC_EINVAL, "null context");
+    REGC_HIP(hipStreamSynchronize(c->stream));
+    c->count_pairs = on != 0;
+    invalidate_graph(c);
     return REGC_OK;
 }
 

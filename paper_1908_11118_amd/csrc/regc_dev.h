@@ -77,6 +77,7 @@ struct SweepArgs {
     int gas_stride;                 // LDS entries per walker (max n_max over classes)
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
     int resync_every;               // > 0: running energy recomputed after every resync_every-th sweep
+    int count_pairs;                // batched kernel: count the pair terms inside the cutoff
 };
 
 // Structural observables of every walker at a sample point (see regc.h).
@@ -177,11 +178,32 @@ __host__ __device__ inline LdsLayout lds_layout(int max_slab_len, int gas_stride
     return L;
 }
 
+// LDS carve of the batched-trial sweep kernel: class slab, ln k table, and per walker
+// the gas coordinates and each particle's energy with the frozen slab.
+struct BatchLds {
+    size_t slab, lnk, gas, eslab, total;
+};
+
+__host__ __device__ inline BatchLds batch_lds(int max_slab_len, int gas_stride, int walkers, int real_size)
+{
+    BatchLds L;
+    const size_t r4 = 4 * (size_t)real_size;
+    size_t off = 0;
+    L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
+    L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
+    L.gas = off;     off = lds_round(off + (size_t)walkers * gas_stride * r4);
+    L.eslab = off;   off = lds_round(off + (size_t)walkers * gas_stride * real_size);
+    L.total = off;
+    return L;
+}
+
 // launchers (defined in the .hip files)
-hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
-                            hipStream_t s);
-hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
-                            hipStream_t s);
+// batch: 2 or 4 runs the batched-trial kernel (one wave per walker), else the one-trial
+// kernel with `split` waves per walker and `cull`
+hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
+                            size_t smem, hipStream_t s);
+hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
+                            size_t smem, hipStream_t s);
 hipError_t launch_paper_f64(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
                             hipStream_t s);
 hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,

@@ -239,8 +239,11 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                             // LDS copy itself (the same value), so a wave needs only its own
                             // write to be visible.  Across waves, the exchange barrier of
                             // this trial ordered all reads before these writes, and that of
-                            // the next trial orders these writes before any later one; only
-                            // the ideal gas, which has no exchange, keeps a barrier below.
+                            // the next trial orders these writes before any later one.  The
+                            // ideal gas has no exchange: its barrier here keeps the other
+                            // wave's read of this trial's particle before the writes, and the
+                            // one below keeps the writes before the next trial's reads.
+                            if (SPLIT == 2 && ideal) __syncthreads();
                             if (kind == 0) {
                                 if (lane == 0) {
                                     Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
@@ -318,6 +321,404 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
             a.n[w] = n;
             a.e[w] = e;
         }
+    }
+}
+
+// ---- batched trials -------------------------------------------------------------
+// The trials of one walker form a chain, and with one walker per SIMD a trial's
+// dependent steps (broadcasts, LDS round trips, reductions, the decision) leave the
+// vector unit idle.  This kernel evaluates B consecutive trials t .. t+B-1 of a walker
+// at once, G = 64 / B lanes each, against the configuration X0 at the start of the
+// batch, and then decides them in order, each exactly as the one-trial-at-a-time chain
+// would:
+//   - the energy change of trial h on the current configuration is its value on X0
+//     plus, for every earlier trial g of the batch that was accepted, the pair terms
+//     between h's positions and g's: with P the new position of a trial (displacement
+//     target, insertion point) and Q the old one (displaced or removed particle),
+//       dE_h += [phi(P_h - P_g) - phi(Q_h - P_g)] - [phi(P_h - Q_g) - phi(Q_h - Q_g)],
+//     computed in the same pass (lane 4 g + k of h's group holds term k), and a new
+//     pair P_h, P_g closer than the hard core rejects h;
+//   - trial h is evaluated again in the next pass (the batch ends before it) when an
+//     earlier accepted trial of the batch changed what h proposes or what its X0 value
+//     assumed: its particle index floor(A1 N / 2^32) under the current N, its particle
+//     (a slot whose occupant changed: displaced, refilled by a removal, emptied by a
+//     removal, filled by an insertion), an insertion no longer at the cap or a
+//     particle present in a walker that was empty, or a hard-core flag raised on X0;
+//   - the Metropolis test uses the prefactor of the current N.
+// Each particle's energy with the frozen slab is kept in LDS (computed at the start of
+// the launch, replaced when the particle moves), so a displacement sums slab terms at
+// its new position only and a removal none.  The accept/reject sequence, N, the
+// coordinates and the counters are those of the sequential chain; energies differ
+// only in the order of the sum.  Trial 0 of every batch is exact, so each pass decides
+// at least one trial.  COUNT adds the count of pair terms inside the cutoff.
+template <int B, bool COUNT>
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) batch_kernel(SweepArgs a)
+{
+    constexpr int G = kWave / B;
+    static_assert(G >= 4 * (B - 1), "a group must hold the pair terms with all earlier trials");
+    extern __shared__ __align__(32) unsigned char smem[];
+    // the wave index is the same in all lanes; readfirstlane lets the compiler know, so
+    // the walker index and the chain's state (N, E, the decisions) live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / G, gl = lane % G;
+    const int waves = blockDim.x / kWave;
+    const int blk = blockIdx.x;
+    const int cid = a.block_class[blk];
+    const ClassDev &C = a.cls[cid];
+    const int nw = a.block_nw[blk];
+
+    const BatchLds L = batch_lds(a.max_slab_len, a.gas_stride, waves, (int)sizeof(Real));
+    Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
+    double *lnk = reinterpret_cast<double *>(smem + L.lnk);
+    Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)wave * a.gas_stride;
+    Real *eslab = reinterpret_cast<Real *>(smem + L.eslab) + (size_t)wave * a.gas_stride;
+
+    const int slab_len = C.slab_len;
+    for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
+#if defined(REGC_FP64)
+        const double *src = a.slab4 + 4 * (size_t)(C.slab_off + k);
+#else
+        const float *src = a.slab4f + 4 * (size_t)(C.slab_off + k);
+#endif
+        Real4 v;
+        v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
+        slab[k] = v;
+    }
+    for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
+    __syncthreads();
+    if (wave >= nw) return;
+
+    const int w = a.block_w0[blk] + wave;
+    const int n_max = C.n_max;
+    const int K = C.trials;
+    int n = a.n[w];
+    double e = a.e[w];
+    const int label = a.label[w];
+    const int sg = C.state_off + label;
+    const double beta = a.beta[sg];
+    const double lnz = a.lnz[sg];
+    const double lnzv = lnz + C.lnv;
+
+    // wave-uniform constants kept in VGPRs: the loop holds more uniform values than
+    // there are SGPRs, and spilled SGPRs cost a lane read per use
+    Box b;
+    b.lx = in_vgpr((Real)C.lx); b.ly = in_vgpr((Real)C.ly); b.hx = in_vgpr((Real)C.half_lx);
+    b.hy = in_vgpr((Real)C.half_ly); b.ix = in_vgpr((Real)C.inv_lx); b.iy = in_vgpr((Real)C.inv_ly);
+    Pair gg, gs;
+    gg.sig2 = in_vgpr((Real)a.pot.sig2_gg); gg.eps4 = in_vgpr((Real)a.pot.eps4_gg);
+    gg.shift = in_vgpr((Real)a.pot.shift_gg); gg.rc2 = in_vgpr((Real)a.pot.rc2); gg.hc2 = in_vgpr((Real)a.pot.hc2_gg);
+    gs.sig2 = in_vgpr((Real)a.pot.sig2_gs); gs.eps4 = in_vgpr((Real)a.pot.eps4_gs);
+    gs.shift = in_vgpr((Real)a.pot.shift_gs); gs.rc2 = gg.rc2; gs.hc2 = in_vgpr((Real)a.pot.hc2_gs);
+    const bool ideal = a.pot.ideal != 0;
+    SlabView sv;
+    sv.atoms = slab; sv.len = slab_len; sv.bins = C.bins;
+    sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
+    sv.inv_cap = in_vgpr(C.bins ? 1.0f / (float)C.cap : 0.f);
+    sv.inv_cw_x = in_vgpr((Real)C.inv_cw_x); sv.inv_cw_y = in_vgpr((Real)C.inv_cw_y);
+    sv.top_plus_rc = in_vgpr((Real)(C.slab_top + sqrt(a.pot.rc2)));
+    const double lx = in_vgpr(C.lx), ly = in_vgpr(C.ly), zlo = in_vgpr(C.zlo), zhi = in_vgpr(C.zhi);
+    const double H = in_vgpr(C.zhi - C.zlo);
+    const double md = in_vgpr(a.max_disp);
+    const double tinv = in_vgpr(1.0 / beta);
+    const double lnzv_v = in_vgpr(lnzv);
+    const int slab_scan = C.bins ? 9 * C.cap : slab_len;
+    Real4 far;                      // a position beyond the cutoff of every atom: absent P or Q
+    far.x = 0; far.y = 0; far.z = (Real)1.0e4; far.w = 0;
+
+    // coordinates, and each particle's slab energy (lane per particle, slab entries in order)
+    {
+        const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            Real4 v;
+            v.x = (Real)src[3 * k]; v.y = (Real)src[3 * k + 1]; v.z = (Real)src[3 * k + 2]; v.w = 0;
+            gas[k] = v;
+            Real es = 0;
+            if (!ideal && v.z < sv.top_plus_rc) {
+                int cx = 0, cy = 0;
+                if (sv.bins) column_of_lanes(sv, v.x, v.y, cx, cy);
+                for (int q = 0; q < slab_scan; ++q)
+                    es += lj(dist2(b, v.x, v.y, v.z, sv.atoms[sv.bins ? block_entry(sv, cx, cy, q) : q]), gs);
+            }
+            eslab[k] = es;
+        }
+    }
+    wave_sync();
+
+    uint32_t stat = 0;     // lane k < kNStat holds counter k
+    uint32_t useful = 0;
+    uint64_t cand = 0;
+
+    const int64_t sweep_first = a.clock ? a.clock[0] + a.sweep0 : a.sweep0;
+    for (int it = 0; it < a.n_sweeps; ++it) {
+        const int64_t sweep = sweep_first + it;
+        const bool tracing = a.trace_bits != nullptr && (sweep - a.trace_sweep0) < a.trace_cap &&
+                             sweep >= a.trace_sweep0;
+        for (int t0 = 0; t0 < K; t0 += 32) {
+            const uint4 R = philox4x32_10(
+                make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)sweep, (uint32_t)w, (uint32_t)(lane & 1)),
+                a.key0, a.key1);
+            const double f0 = uniform_open(R.z), f1 = uniform_open(R.w), f2 = uniform_open(R.x);
+            const double f3 = log(uniform53(R.y, R.z));
+            const int tn = K - t0 < 32 ? K - t0 : 32;
+            uint32_t bits = 0;
+            for (int t = 0; t < tn;) {
+                const int nb = tn - t < B ? tn - t : B;
+                const int n0 = n;
+                const bool act = grp < nb;
+                // this group's trial t + grp: words of Philox blocks A (lane 2m) and B (lane 2m + 1)
+                const int src = 2 * (t + (act ? grp : 0));
+                const uint32_t A0 = (uint32_t)__shfl((int)R.x, src);
+                const uint32_t A1 = (uint32_t)__shfl((int)R.y, src);
+                const double ux = __shfl(f0, src), uy = __shfl(f1, src);
+                const double uz = __shfl(f2, src + 1), lnU = __shfl(f3, src + 1);
+                const int kind = (uint64_t)A0 < a.th_disp ? 0 : ((uint64_t)A0 < a.th_ins ? 1 : 2);
+                const bool skip = kind == 1 ? n0 >= n_max : n0 == 0;
+                const int i = kind == 1 || skip ? 0 : (int)(((uint64_t)A1 * (uint64_t)n0) >> 32);
+                const int ex = kind == 1 ? -1 : i;                // the gas atom left out of the sum
+                const Real4 o = gas[i];
+                const Real eo = kind == 1 || skip ? Real(0) : eslab[i];
+                double px = 0.0, py = 0.0, pz = 0.0, c;
+                bool wall = false;
+                if (kind == 0) {
+                    px = (double)o.x + md * (2.0 * ux - 1.0);
+                    py = (double)o.y + md * (2.0 * uy - 1.0);
+                    pz = (double)o.z + md * (2.0 * uz - 1.0);
+                    if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
+                    if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
+                    wall = !skip && (pz < zlo || pz > zhi);
+                    c = 0.0;
+                } else if (kind == 1) {
+                    px = lx * ux;
+                    py = ly * uy;
+                    pz = zlo + H * uz;
+                    c = lnzv_v - lnk[n0 + 1];                     // ln z V / (N+1)
+                } else {
+                    c = lnk[n0] - lnzv_v;                         // ln N / (z V)
+                }
+                const double thr = (c - lnU) * tinv;              // accept iff dE <= thr
+                const bool live = act && !skip && !wall;          // the trial moves a particle
+                const bool compute = live && !ideal;
+                Real4 P = far, Q = far;
+                if (live && kind != 2) { P.x = (Real)px; P.y = (Real)py; P.z = (Real)pz; }
+                if (live && kind != 1) { Q.x = o.x; Q.y = o.y; Q.z = o.z; }
+                const bool need_slab = compute && P.z < sv.top_plus_rc;
+
+                Real acc = 0, vs = 0;
+                bool core = false;
+                uint32_t use = 0;
+                Real cterm = 0;
+                bool ccore = false;
+                if (!ideal) {
+                    for (int j0 = 0; j0 < n0; j0 += G) {
+                        const int j = j0 + gl;
+                        const bool v = compute && j < n0 && j != ex;
+                        const Real4 g4 = gas[j < n0 ? j : 0];
+                        const Real r2p = dist2(b, P.x, P.y, P.z, g4);
+                        const Real r2q = dist2(b, Q.x, Q.y, Q.z, g4);
+                        core |= v && r2p < gg.hc2;
+                        if (COUNT) use += (uint32_t)(v && r2p < gg.rc2) + (uint32_t)(v && r2q < gg.rc2);
+                        acc += v ? lj(r2p, gg) : Real(0);
+                        acc -= v ? lj(r2q, gg) : Real(0);
+                    }
+                    // slab terms at the new position only (the old one's are cached)
+                    if (__any(need_slab)) {
+                        int cx = 0, cy = 0;
+                        if (sv.bins) column_of_lanes(sv, P.x, P.y, cx, cy);
+                        for (int k0 = 0; k0 < slab_scan; k0 += G) {
+                            const int k = k0 + gl;
+                            const bool v = need_slab && k < slab_scan;
+                            const int kk = k < slab_scan ? k : 0;
+                            const Real4 s4 = sv.atoms[sv.bins ? block_entry(sv, cx, cy, kk) : kk];
+                            const Real r2p = dist2(b, P.x, P.y, P.z, s4);
+                            core |= v && r2p < gs.hc2;
+                            if (COUNT) use += (uint32_t)(v && r2p < gs.rc2);
+                            vs += v ? lj(r2p, gs) : Real(0);
+                        }
+                    }
+                    // pair terms with the positions of earlier trials of the batch
+                    if (B > 1) {
+                        const int g = gl >> 2, k = gl & 3;
+                        const int from = (g * G) & (kWave - 1);
+                        Real4 X;
+                        const Real xp = __shfl(P.x, from), yp = __shfl(P.y, from), zp = __shfl(P.z, from);
+                        const Real xq = __shfl(Q.x, from), yq = __shfl(Q.y, from), zq = __shfl(Q.z, from);
+                        X.x = k < 2 ? xp : xq; X.y = k < 2 ? yp : yq; X.z = k < 2 ? zp : zq; X.w = 0;
+                        const Real4 Y = (k & 1) == 0 ? P : Q;
+                        // both positions present (an absent one sits at the far point,
+                        // and two absent ones would coincide)
+                        const Real zfar = (Real)1.0e3;
+                        const bool valid = act && g < grp && X.z < zfar && Y.z < zfar;
+                        const Real r2 = dist2(b, Y.x, Y.y, Y.z, X);
+                        const Real term = valid ? lj(r2, gg) : Real(0);
+                        // the quad's four terms signed and summed: every lane of the quad
+                        // holds [phi(P_h-P_g) - phi(Q_h-P_g)] - [phi(P_h-Q_g) - phi(Q_h-Q_g)]
+                        cterm = quad_sum((k == 1 || k == 2) ? -term : term);
+                        ccore = valid && k == 0 && r2 < gg.hc2;
+                    }
+                }
+                const Real vP = group_sum<G>(vs);                 // slab energy at P
+                const Real sde = group_sum<G>(acc) + vP - eo;     // dE on X0
+                const uint64_t core_lanes = __ballot(core);
+                const uint64_t ccore_lanes = __ballot(ccore);
+                const uint32_t packed = (uint32_t)kind | (skip ? 4u : 0u) | (wall ? 8u : 0u) | (compute ? 16u : 0u) |
+                                        (need_slab ? 32u : 0u) | ((uint32_t)i << 8);
+
+                // ---- every trial under every outcome of the earlier trials of the batch ----
+                // Lane s < 2^h of trial h's group takes the scenario "trial g < h accepted iff
+                // bit g of s": N and the changed slots after those trials, h's corrected dE,
+                // and h's outcome.  The decisions then follow the one consistent path.
+                uint32_t pk[B];
+#pragma unroll
+                for (int g = 0; g < B; ++g)
+                    pk[g] = g < nb ? (uint32_t)__builtin_amdgcn_readlane((int)packed, g * G) : 0u;
+                Real cg[B > 1 ? B - 1 : 1];
+#pragma unroll
+                for (int g = 0; g + 1 < B; ++g) cg[g] = __shfl(cterm, (lane & ~(G - 1)) + 4 * g);
+                const uint32_t sc = (uint32_t)gl;
+                int ncur = n0;
+                uint64_t tmask = 0;          // changed slots, as bits of (slot mod 64)
+                double de = (double)sde;
+                bool ccr = false;
+#pragma unroll
+                for (int g = 0; g + 1 < B; ++g) {
+                    if (g < grp && ((sc >> g) & 1u)) {
+                        const int kg = (int)(pk[g] & 3u), ig = (int)(pk[g] >> 8);
+                        if (kg == 0) {
+                            tmask |= 1ull << (ig & 63);
+                        } else if (kg == 1) {
+                            tmask |= 1ull << (ncur & 63);
+                            ncur += 1;
+                        } else {
+                            tmask |= (1ull << (ig & 63)) | (1ull << ((ncur - 1) & 63));
+                            ncur -= 1;
+                        }
+                        de += (double)cg[g];
+                        ccr |= ((ccore_lanes >> (grp * G + 4 * g)) & 1ull) != 0;
+                    }
+                }
+                const bool gcore = ((core_lanes >> (grp * G)) & (G == 64 ? ~0ull : ((1ull << G) - 1))) != 0;
+                bool redo = false;
+                if (sc != 0) {
+                    redo = compute && gcore;
+                    if (kind == 1) redo |= skip && ncur < n_max;
+                    else if (n0 == 0) redo |= ncur > 0;
+                    else if (ncur > 0)
+                        redo |= (int)(((uint64_t)A1 * (uint64_t)ncur) >> 32) != i || ((tmask >> (i & 63)) & 1ull) != 0;
+                }
+                const bool capemp = kind == 1 ? ncur >= n_max : ncur == 0;
+                double th = thr;
+                if (kind != 0 && ncur != n0) {
+                    // (scenarios off the real path may imply an N outside 0..n_max)
+                    const int nq = ncur < 0 ? 0 : (ncur > n_max ? n_max : ncur);
+                    th = ((kind == 1 ? lnzv_v - lnk[nq + 1] : lnk[nq] - lnzv_v) - lnU) * tinv;
+                }
+                const bool cr = compute && kind != 2 && (gcore || ccr);
+                if (!compute) de = 0.0;
+                const bool scen = act && sc < (1u << grp);
+                const bool ok = scen && !redo && !capemp && !wall && !cr && de <= th;
+                const uint64_t redo_m = __ballot(scen && redo);
+                const uint64_t acc_m = __ballot(ok);
+                const uint64_t cap_m = __ballot(scen && !redo && capemp);
+                const uint64_t wall_m = __ballot(scen && !redo && !capemp && wall);
+                const uint64_t core_m = __ballot(scen && !redo && !capemp && !wall && cr);
+
+                // ---- the path: trial h's scenario is the accept bits of trials 0..h-1 ----
+                int nres = 0;
+                uint32_t path = 0;
+                int nw = n0;                 // N along the path
+                for (int h = 0; h < nb; ++h) {
+                    const int L0 = h * G + (int)path;
+                    if ((redo_m >> L0) & 1ull) break;
+                    ++nres;
+                    const int kd = (int)(pk[h] & 3u);
+                    int ev = -1;
+                    if ((cap_m >> L0) & 1ull) ev = kd == 1 ? 6 : 7;
+                    else if ((wall_m >> L0) & 1ull) ev = 8;
+                    else if ((core_m >> L0) & 1ull) ev = 9;
+                    else if ((acc_m >> L0) & 1ull) ev = 2 * kd + 1;
+                    stat += (lane == 2 * kd) + (lane == ev);
+                    if ((pk[h] & 16u) && ev != 6 && ev != 7 && ev != 8)
+                        cand += (uint64_t)(kd == 0 ? 2 : 1) * (uint64_t)(kd == 1 ? nw : nw - 1) +
+                                (uint64_t)((pk[h] & 32u) ? slab_scan : 0);
+                    if (ev == 2 * kd + 1) {
+                        path |= 1u << h;
+                        nw += kd == 1 ? 1 : (kd == 2 ? -1 : 0);
+                    }
+                }
+                // the accepted moves of the path, in order
+                if (path) {
+                    bits |= path << t;
+                    for (uint32_t m = path; m; m &= m - 1) {
+                        const int h = __builtin_ctz(m);
+                        const int L0 = h * G + (int)(path & ((1u << h) - 1u));
+                        const int kd = (int)(pk[h] & 3u), is = (int)(pk[h] >> 8);
+                        e = in_vgpr(e + bcast(de, L0));
+                        // LDS updates in program order (a wave's LDS operations complete in
+                        // order); the next pass's reads follow the fence below
+                        if (kd == 0) {
+                            if (lane == h * G) {
+                                gas[is] = P;
+                                eslab[is] = vP;
+                            }
+                        } else if (kd == 1) {
+                            if (lane == h * G) {
+                                gas[n] = P;
+                                eslab[n] = vP;
+                            }
+                            n += 1;
+                        } else {
+                            if (lane == 0 && is != n - 1) {
+                                gas[is] = gas[n - 1];
+                                eslab[is] = eslab[n - 1];
+                            }
+                            n -= 1;
+                        }
+                    }
+                    wave_sync();
+                }
+                if (COUNT) useful += grp < nres ? use : 0u;
+                t += nres;
+            }
+            if (tracing && lane == 0)
+                a.trace_bits[((size_t)(sweep - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
+        }
+        // ---- end of sweep: running energy resynchronised, trace N, sample record ----
+        if (a.resync_every > 0 && (sweep + 1) % a.resync_every == 0 && !ideal)
+            e = full_energy_part<1>(gas, n, sv, b, gg, gs, lane, 0);
+        if (lane == 0) {
+            if (tracing) a.trace_n[(size_t)(sweep - a.trace_sweep0) * a.n_walkers + w] = n;
+            if (a.sample_every > 0 && (sweep + 1) % a.sample_every == 0) {
+                const int64_t rec = (sweep + 1) / a.sample_every - 1 - a.rec_base;
+                const size_t idx = (size_t)rec * a.n_walkers + w;
+                a.samp_e[idx] = e;
+                a.samp_n[idx] = n;
+                a.samp_s[idx] = label;
+                atomicAdd(a.hist + (size_t)sg * a.hist_stride + n, 1ull);
+            }
+        }
+    }
+
+    {
+        double *dst = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            const Real4 v = gas[k];
+            dst[3 * k] = (double)v.x; dst[3 * k + 1] = (double)v.y; dst[3 * k + 2] = (double)v.z;
+        }
+    }
+    {
+        uint32_t u = useful;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+        if (lane == 0 && a.pairs) {
+            atomicAdd(a.pairs, (unsigned long long)cand);
+            atomicAdd(a.pairs + 1, (unsigned long long)u);
+        }
+    }
+    if (lane < kNStat && stat) atomicAdd(a.stats + (size_t)sg * kNStat + lane, (unsigned long long)stat);
+    if (lane == 0) {
+        a.n[w] = n;
+        a.e[w] = e;
     }
 }
 
@@ -778,11 +1179,17 @@ hipError_t PAPER_LAUNCH(const SweepArgs &a, const PaperArgs &p, int n_blocks, in
     return hipGetLastError();
 }
 
-hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, size_t smem,
-                        hipStream_t s)
+hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
+                        size_t smem, hipStream_t s)
 {
     const dim3 grid(n_blocks), block(kWave * waves_per_block);
-    if (split == 2) {
+    if (batch == 4) {
+        if (a.count_pairs) hipLaunchKernelGGL((batch_kernel<4, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((batch_kernel<4, false>), grid, block, smem, s, a);
+    } else if (batch == 2) {
+        if (a.count_pairs) hipLaunchKernelGGL((batch_kernel<2, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((batch_kernel<2, false>), grid, block, smem, s, a);
+    } else if (split == 2) {
         if (cull) hipLaunchKernelGGL((sweep_kernel<2, true>), grid, block, smem, s, a);
         else hipLaunchKernelGGL((sweep_kernel<2, false>), grid, block, smem, s, a);
     } else {

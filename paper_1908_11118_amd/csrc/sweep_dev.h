@@ -115,6 +115,47 @@ __device__ __forceinline__ double wave_sum(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Sum over each quad of lanes (4 lanes), the total in every lane of the quad.
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += dpp_f32<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+
+__device__ __forceinline__ double quad_sum(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    return v;
+}
+
+// Sum over aligned groups of G lanes (16, 32 or 64), the total in every lane of the
+// group; the order of the additions is fixed (DPP within rows of 16, then across rows).
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+    v += dpp_f32<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f32<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_f32<0x140, 0xF>(v);   // row_mirror: every lane holds its row's sum
+    if (G >= 32) v += __shfl_xor(v, 16);
+    if (G >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    v += dpp_f64<0x141, 0xF>(v);
+    v += dpp_f64<0x140, 0xF>(v);
+    if (G >= 32) v += __shfl_xor(v, 16);
+    if (G >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -143,6 +184,13 @@ __device__ __forceinline__ double bcast(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ float bcast(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ Real bcast_real(Real v, int lane) { return bcast(v, lane); }
+
 // Slab access: all atoms, or the 3x3 block of x-y columns around a column
 // (periodic in x and y; column ids row-major, y outer).
 struct SlabView {
@@ -162,6 +210,15 @@ __device__ __forceinline__ void column_of(const SlabView &sv, Real x, Real y, in
     const int iy = (int)(y * sv.inv_cw_y);
     cx = __builtin_amdgcn_readfirstlane(ix < 0 ? 0 : (ix >= sv.ncx ? sv.ncx - 1 : ix));
     cy = __builtin_amdgcn_readfirstlane(iy < 0 ? 0 : (iy >= sv.ncy ? sv.ncy - 1 : iy));
+}
+
+// Column of a position as a per-lane value (positions that differ between lanes).
+__device__ __forceinline__ void column_of_lanes(const SlabView &sv, Real x, Real y, int &cx, int &cy)
+{
+    const int ix = (int)(x * sv.inv_cw_x);
+    const int iy = (int)(y * sv.inv_cw_y);
+    cx = ix < 0 ? 0 : (ix >= sv.ncx ? sv.ncx - 1 : ix);
+    cy = iy < 0 ? 0 : (iy >= sv.ncy ? sv.ncy - 1 : iy);
 }
 
 // Periodic neighbour c + d (d in -1..1) of a column index in [0, nc): as an

@@ -35,7 +35,8 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_set_proposal", "regc_set_class_proposal", "regc_capture_voxels", "regc_get_proposal_stats", "regc_set_observables",
            "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables",
            "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error",
-           "regc_default_reweight_opts", "regc_reweight", "regc_mlp_step", "regc_proposal_eval"]
+           "regc_default_reweight_opts", "regc_reweight", "regc_mlp_step", "regc_proposal_eval",
+           "regc_count_pairs"]
 
 
 class RegcError(RuntimeError):
@@ -82,7 +83,8 @@ class Opts(C.Structure):
                 ("trace_capacity", C.c_int64), ("walkers_per_block", C.c_int), ("sweeps_per_launch", C.c_int),
                 ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
                 ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
-                ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double), ("resync_every", C.c_int)]
+                ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double), ("resync_every", C.c_int),
+                ("batch_trials", C.c_int)]
 
 
 _lib = None
@@ -118,6 +120,7 @@ def lib():
         L.regc_get_stats.argtypes = [vp, _i64p, _i64p, _i64p]
         L.regc_get_histograms.argtypes = [vp, _i64p]
         L.regc_get_pair_counts.argtypes = [vp, _i64p, _i64p]
+        L.regc_count_pairs.argtypes = [vp, C.c_int]
         L.regc_get_trace.argtypes = [vp, _u32p, _i32p, C.c_int64, _i64p]
         L.regc_timing_enable.argtypes = [vp, C.c_int]
         L.regc_timing_get.argtypes = [vp, _dp, _i64p, _dp, _i64p]
@@ -208,7 +211,8 @@ class Regc:
 
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
                  walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
-                 cull: int = 0, graph_intervals: int = 0, resync_every: int = 0, stream=None):
+                 cull: int = 0, graph_intervals: int = 0, resync_every: int = 0, batch_trials: int = 0,
+                 stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
         self.workloads = wl
@@ -238,6 +242,7 @@ class Regc:
         o.md_dt = float(getattr(w0, "md_dt", 0.005))
         o.md_tau = float(getattr(w0, "md_tau", 0.1))
         o.resync_every = resync_every
+        o.batch_trials = batch_trials
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:
@@ -334,6 +339,9 @@ class Regc:
         acc = np.zeros((4, self.W), np.int64)
         _check(lib().regc_get_stats(self.h, _p(st, _i64p), _p(att, _i64p), _p(acc, _i64p)))
         return {"stats": st, "swap_att": att, "swap_acc": acc}
+
+    def count_pairs(self, on: bool = True):
+        _check(lib().regc_count_pairs(self.h, int(on)))
 
     def pair_counts(self):
         a, b = C.c_int64(), C.c_int64()

@@ -118,6 +118,34 @@ def test_fp64_invariant_to_launch_shape(wpb, spl, split, cull):
     _fp64_trajectory(w2, 40, walkers_per_block=wpb, sweeps_per_launch=spl, split=split, cull=cull)
 
 
+@pytest.mark.parametrize("batch,wpb,spl", [(1, 0, 0), (2, 1, 3), (2, 4, 0), (4, 1, 7), (4, 8, 0)])
+def test_fp64_batched_trials_keep_the_trajectories(batch, wpb, spl):
+    """Trials decided in batches of 2 or 4 (corrected by the pair terms of the moves
+    accepted earlier in the batch, a trial whose particle index or particle changed
+    left to the next batch) give the sequential chain's accept bits, N, labels and
+    counters: small N, N above a group's lanes, a binned slab, walkers per block."""
+    w = W.small_lj(n_t=4, n_mu=4, n_max=20, n_sweeps=60)
+    _fp64_trajectory(w, 60, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    w2 = W.config2(60).replace(t=np.array([0.9, 1.6]), mu=np.array([-3.0, -2.0]), n_max=160, sample_every=5)
+    _, wk = _fp64_trajectory(w2, 60, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    assert wk["n"].max() > 100
+    # a dense, strongly interacting system: many accepted moves inside each batch
+    w3 = W.small_lj(n_t=2, n_mu=2, n_max=40, t=(0.7, 1.2), mu=(-3.0, -1.5), height=5.0)
+    _, wk3 = _fp64_trajectory(w3, 150, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    assert wk3["n"].max() > 25
+
+
+def test_fp64_batched_trials_ideal_gas_and_caps():
+    """The batched kernel where only prefactors decide (ideal gas: every index
+    change after an accepted insertion or removal), at the cap N = n_max and with one
+    trial per sweep."""
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300, batch_trials=4)
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=2, n_max=6).replace(mu=W.linear_grid(-3.0, -2.0, 2)), 200,
+                     batch_trials=4)
+    _fp64_trajectory(W.small_lj(n_t=2, n_mu=3, n_max=8).replace(trials_per_sweep=1), 200, batch_trials=4)
+    _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=300).replace(swap_every=0), 300, batch_trials=2)
+
+
 @pytest.mark.parametrize("split,cull", [(1, 0), (2, 0), (1, 1), (2, 1)])
 def test_fp64_dense_walkers(split, cull):
     """N well above 64 (a wave's width), binned 8x8x3 slab: both waves of a split
@@ -141,8 +169,9 @@ def test_fp64_edge_cases():
     _fp64_trajectory(W.small_lj(n_t=2, n_mu=3, n_max=8).replace(trials_per_sweep=1), 300)
     # no slab at all
     _fp64_trajectory(W.small_lj(n_t=2, n_mu=2, n_max=15).replace(slab=np.zeros((0, 3))), 150)
-    # ideal gas mode
+    # ideal gas mode, also with two waves per walker in the one-trial kernel
     _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300)
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300, split=2)
 
 
 def _batch_classes():
