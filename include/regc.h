@@ -352,6 +352,20 @@ int regc_mbar_solve(regc_mbar *mb, double tol, int max_iter, double *f_out, int 
 int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
                       double *mean_e, double *mean_e2, double *p_n, int32_t *phase);
 
+/* regc_mbar_targets without p_n, for callers that cannot allocate memory (code
+ * under stream capture, serving loops, hosts that forbid allocation): it calls no
+ * allocator and keeps its device intermediates (target constants, per-chunk partial
+ * sums, outputs before the copy) in a fixed 4 MiB array of the library that every
+ * GPU holds from the first call on it (with that GPU current) until the process ends.
+ * Limits: n_t <= 1024, n_t * n_mu <= 4096, and nT + 6 nK + 4 nT * chunks <= 2^19
+ * doubles, where chunks is the number of 2048-sample chunks of the samples cut at
+ * each N (EINVAL beyond, nothing launched).  Outputs are host arrays as in
+ * regc_mbar_targets and equal to its outputs; the call synchronises the handle's
+ * stream.  Calls that overlap on one GPU (from several host threads) share the
+ * array and race. */
+int regc_mbar_targets_static(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
+                             double *mean_e, double *mean_e2, int32_t *phase);
+
 /* Estimates with their errors (Sec. II.B gives the estimator, not its error; the
  * error definitions are readings of this library):
  *  - at every sampled state s, the direct mean of N over the samples holding s and

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
+#include <mutex>
 #include <vector>
 
 #include "host_util.h"
@@ -975,6 +976,82 @@ extern "C" int regc_mbar_targets(regc_mbar *mb, const regc_grid *targets, double
     if (mean_e2) REGC_HIP(hipMemcpy(mean_e2, me2_d.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
     if (phase) REGC_HIP(hipMemcpy(phase, ph_d.p, sizeof(int32_t) * nK, hipMemcpyDeviceToHost));
     if (p_n) REGC_HIP(hipMemcpy(p_n, pn_d.p, sizeof(double) * nK * mb->nN, hipMemcpyDeviceToHost));
+    return REGC_OK;
+}
+
+// ---- reweighted averages without allocation ----
+// Device scratch of regc_mbar_targets_static: the target constants, the per-chunk
+// partial sums and the outputs before their copy to the host.  Every GPU the library
+// runs on holds its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 19;     // 4 MiB
+constexpr int kStaticMaxT = 1024, kStaticMaxK = 4096;
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+static std::mutex g_static_mu;
+static double *g_static_ptr[kStaticMaxDevices];
+
+// The current device's scratch address (looked up once per device, with it current).
+static int static_scratch(double **out)
+{
+    int dev = -1;
+    REGC_HIP(hipGetDevice(&dev));
+    REGC_CHECK(dev >= 0 && dev < kStaticMaxDevices, REGC_EINVAL, "device %d beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        REGC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        REGC_CHECK(p != nullptr, REGC_EINVAL, "no address for the static scratch on device %d", dev);
+        g_static_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_static_ptr[dev];
+    return REGC_OK;
+}
+
+extern "C" int regc_mbar_targets_static(regc_mbar *mb, const regc_grid *targets, double *f, double *mean_n,
+                                        double *mean_e, double *mean_e2, int32_t *phase)
+{
+    REGC_CHECK(mb && targets && mean_n && targets->t && targets->mu, REGC_EINVAL, "null argument");
+    REGC_CHECK(mb->solved, REGC_ESTATE, "solve first");
+    const int nT = targets->n_t, nMu = targets->n_mu;
+    REGC_CHECK(nT > 0 && nMu > 0, REGC_EINVAL, "empty target grid");
+    REGC_CHECK(nT <= kStaticMaxT && (int64_t)nT * nMu <= kStaticMaxK, REGC_EINVAL,
+               "target grid %d x %d beyond the static limits (%d temperatures, %d targets)", nT, nMu, kStaticMaxT,
+               kStaticMaxK);
+    const int nK = nT * nMu;
+    // scratch: tb [nT] | tz [nK] | partials [nchunks][nT][4] | f, mean_n, mean_e, mean_e2, phase [nK] each
+    const size_t need = (size_t)nT + (size_t)nK + (size_t)mb->nchunks * nT * 4 + (size_t)5 * nK;
+    REGC_CHECK(need <= kStaticScratchDoubles, REGC_EINVAL,
+               "%zu doubles of scratch needed (%d sample chunks x %d temperatures), %zu available", need,
+               mb->nchunks, nT, kStaticScratchDoubles);
+    double tb[kStaticMaxT], tz[kStaticMaxK];
+    for (int l = 0; l < nT; ++l) {
+        REGC_CHECK(targets->t[l] > 0, REGC_EINVAL, "target temperatures must be positive");
+        tb[l] = 1.0 / targets->t[l];
+        for (int m = 0; m < nMu; ++m) tz[l * nMu + m] = lnz_of(targets->t[l], targets->mu[m], mb->lambda1);
+    }
+    double *sp = nullptr;
+    int rc;
+    if ((rc = static_scratch(&sp))) return rc;
+    double *tb_d = sp, *tz_d = tb_d + nT, *part = tz_d + nK, *f_d = part + (size_t)mb->nchunks * nT * 4;
+    double *mn_d = f_d + nK, *me_d = mn_d + nK, *me2_d = me_d + nK;
+    int32_t *ph_d = reinterpret_cast<int32_t *>(me2_d + nK);
+    hipStream_t s = mb->stream;
+    REGC_HIP(hipMemcpyAsync(tb_d, tb, sizeof(double) * nT, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(tz_d, tz, sizeof(double) * nK, hipMemcpyHostToDevice, s));
+    // every partial and output entry read below is written by these two kernels
+    hipLaunchKernelGGL(mbar_target_chunk, dim3(mb->nchunks), dim3(kMbarThreads), 0, s, nT, tb_d, mb->e_d.p,
+                       mb->logd_d.p, mb->chunk_b_d.p, mb->chunk_e_d.p, part, mb->weighted ? mb->wgt_d.p : nullptr);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mbar_target_eval, dim3(nT), dim3(256), sizeof(double) * 3 * mb->nN, s, nT, nMu, mb->nN, part,
+                       mb->seg_c0_d.p, mb->seg_c1_d.p, tz_d, f_d, mn_d, me_d, me2_d, nullptr, ph_d);
+    REGC_HIP(hipGetLastError());
+    if (f) REGC_HIP(hipMemcpyAsync(f, f_d, sizeof(double) * nK, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipMemcpyAsync(mean_n, mn_d, sizeof(double) * nK, hipMemcpyDeviceToHost, s));
+    if (mean_e) REGC_HIP(hipMemcpyAsync(mean_e, me_d, sizeof(double) * nK, hipMemcpyDeviceToHost, s));
+    if (mean_e2) REGC_HIP(hipMemcpyAsync(mean_e2, me2_d, sizeof(double) * nK, hipMemcpyDeviceToHost, s));
+    if (phase) REGC_HIP(hipMemcpyAsync(phase, ph_d, sizeof(int32_t) * nK, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipStreamSynchronize(s));     // the stack copies of tb, tz live until here
     return REGC_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_sample_count", "regc_get_samples", "regc_samples_device", "regc_clear_samples",
            "regc_get_stats", "regc_get_pair_counts", "regc_get_histograms", "regc_get_trace", "regc_timing_enable", "regc_timing_get",
            "regc_checkpoint", "regc_restore", "regc_destroy", "regc_mbar_create", "regc_mbar_set_stream",
-           "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_set_solver", "regc_mbar_solve", "regc_mbar_targets",
+           "regc_mbar_set_samples", "regc_mbar_load_run", "regc_mbar_set_solver", "regc_mbar_solve", "regc_mbar_targets", "regc_mbar_targets_static",
            "regc_mbar_timing", "regc_mbar_destroy", "regc_mlp_param_count", "regc_mlp_create",
            "regc_mlp_set_stream", "regc_mlp_set_params", "regc_mlp_get_params", "regc_mlp_forward",
            "regc_mlp_loss_grads", "regc_mlp_train", "regc_mlp_timing", "regc_mlp_destroy",
@@ -511,6 +511,18 @@ class Mbar:
         _check(lib().regc_mbar_targets(self.h, C.byref(g), _p(f, _dp), _p(mn, _dp), _p(me, _dp), _p(me2, _dp),
                                        _p(pn, _dp), _p(ph, _i32p)))
         return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "p_n": pn, "phase": ph}
+
+    def targets_static(self, t, mu):
+        """regc_mbar_targets_static: the averages of targets() without p_n, with no
+        allocation in the library."""
+        keep = []
+        g = _grid(t, mu, keep)
+        K = len(keep[0]) * len(keep[1])
+        f, mn, me, me2 = np.zeros(K), np.zeros(K), np.zeros(K), np.zeros(K)
+        ph = np.zeros(K, np.int32)
+        _check(lib().regc_mbar_targets_static(self.h, C.byref(g), _p(f, _dp), _p(mn, _dp), _p(me, _dp),
+                                              _p(me2, _dp), _p(ph, _i32p)))
+        return {"f": f, "mean_n": mn, "mean_e": me, "mean_e2": me2, "phase": ph}
 
     def reweight(self, t, mu, tol: float = 1e-10, max_iter: int = 10000, n_batches: int = 20, n_boot: int = 100,
                  record_size: int = 0, block_records: int = 0, seed: int = 1, n_sites: float = 0.0,
