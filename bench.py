@@ -84,7 +84,10 @@ def main():
     ap.add_argument("--graph", type=int, default=-1, help="graph_intervals (-1: 0 for c2, 10 for c3)")
     ap.add_argument("--learned-seconds", type=float, default=60.0,
                     help="GPU-time cap of the plain and learned runs of the time-to-accuracy leg (0: skip the leg)")
-    ap.add_argument("--schedule-seconds", type=float, default=30.0,
+    ap.add_argument("--c3-sweeps", type=int, default=10000,
+                    help="sweeps of the 4096-replica uneven batch leg (0: skip)")
+    ap.add_argument("--c3-burnin", type=int, default=2000, help="untimed equilibration sweeps of that leg")
+    ap.add_argument("--schedule-seconds", type=float, default=0.0,
                     help="GPU-time cap of the runs of that leg with the paper's REGC step (MC and MD forms; "
                          "0: skip them)")
     ap.add_argument("--learned-tau", type=float, default=0.5, help="standard-error target (particles) of that leg")
@@ -99,6 +102,7 @@ def main():
     ap.add_argument("--fs-train-steps", type=int, default=5000, help="full stack: Adam steps per class network")
     ap.add_argument("--fs-sweeps", type=int, default=2000, help="full stack: production sweeps (sampled every 2)")
     ap.add_argument("--fs-oracle-sweeps", type=int, default=3000, help="full stack: oracle sweeps on the subset")
+    ap.add_argument("--fs-boot", type=int, default=20, help="full stack: bootstrap replicates of the error maps")
     ap.add_argument("--fs-tmin", type=float, default=0.88,
                     help="full stack: lowest temperature of the restricted reweighting (below it the states "
                          "on either side of the condensation do not exchange configurations)")
@@ -169,6 +173,7 @@ def main():
     flops_launch = FLOPS_PER_PAIR * cand / max(tm["n_sweep"], 1)
     graph = opts.get("graph_intervals", 0) > 0
     achieved = flops_launch / (ms_kernel * 1e-3) / 1e12
+    achieved_in = FLOPS_PER_PAIR * useful / max(tm["n_sweep"], 1) / (ms_kernel * 1e-3) / 1e12
     wk = g.walkers(xyz=True)
 
     acc = {k: float(d[:, 2 * i + 1].sum() / max(d[:, 2 * i].sum(), 1))
@@ -200,6 +205,8 @@ def main():
                    else "FP64", "mean_N": float(wk["n"].mean()), "max_N": int(wk["n"].max())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
+                     "basis": "candidate pair terms (gas atoms + slab column block, twice per displacement)",
+                     "achieved_in_cutoff": achieved_in, "frac_in_cutoff": achieved_in / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic() if (args.workload == "c2" and prec == regc.FP32PAIR and not graph)
                      else None,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
@@ -293,12 +300,9 @@ def main():
         # consistency at the sampled states: reweighted <N> against the direct per-state
         # means, for the solve over all states and for the solve over T >= 0.88 only (the
         # low-T rows do not exchange configurations across the condensation)
-        from paper_1908_11118_amd import proposal as P
         smp = gm.samples()
         S = w.n_states
-        nn = np.take_along_axis(smp["n"].reshape(-1, S), np.argsort(smp["state"].reshape(-1, S), axis=1),
-                                axis=1).astype(np.float64)
-        m_dir, se_dir = P.mean_se(list(nn.T))
+        m_dir, se_dir = regc.batch_means(smp["state"], smp["n"], S)
         at = mb.targets(w.t, w.mu)["mean_n"]
         l0 = int(np.searchsorted(w.t, 0.88))
         keep = smp["state"] // len(w.mu) >= l0
@@ -333,6 +337,9 @@ def main():
             "restricted_solve": {"mean_z": float(z_hi.mean()), "frac_abs_z_gt_3": float(np.mean(np.abs(z_hi) > 3))}}
         mb.close()
         gm.close()
+    if args.c3_sweeps > 0 and args.workload == "c2":
+        g.close()
+        result["c3"] = c3_leg(args, prec)
     if args.learned_seconds > 0:
         result["learned"] = learned_leg(args)
     if args.full_stack:
@@ -373,16 +380,95 @@ def production_leg(args, w, wk, prec):
         mb.load_run(g, 0, skip)
         t0 = time.perf_counter()
         f, conv, iters, delta = mb.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
-        tg = W.linear_grid(0.5, 2.0, 64), W.linear_grid(-8.0, -2.0, 64)
-        tr = mb.targets(*tg)
         t_mb = time.perf_counter() - t0
+        # estimates with errors on a 64 x 64 grid: coverage of the 8 x 8 hollow sites of
+        # the slab's top layer and heat capacity, bootstrap SEs over 100 replicates
+        tg = W.linear_grid(0.5, 2.0, 64), W.linear_grid(-8.0, -2.0, 64)
+        t0 = time.perf_counter()
+        rw = mb.reweight(*tg, tol=1e-8, max_iter=3000, n_batches=20, n_boot=100, n_sites=64.0, allow_noconv=True)
+        t_rw = time.perf_counter() - t0
         mb.close()
-    cov = tr["mean_n"] / 64.0                       # 8 x 8 hollow sites of the slab's top layer
     out["reweighting"] = {"samples": (n_rec - skip) * w.n_states, "iterations": iters, "converged": bool(conv),
                           "seconds": t_mb, "target_grid": "64 T x 64 mu",
-                          "phases": int(len(set(tr["phase"].tolist()))),
-                          "coverage_range": [float(cov.min()), float(cov.max())]}
+                          "phases": int(len(set(rw["phase"].tolist()))),
+                          "coverage_range": [float(rw["coverage"].min()), float(rw["coverage"].max())],
+                          "coverage_se_max": float(np.nanmax(rw["se_coverage"])),
+                          "coverage_se_median": float(np.nanmedian(rw["se_coverage"])),
+                          "heat_capacity_max": float(rw["heat_cap"].max()),
+                          "heat_capacity_se_median": float(np.nanmedian(rw["se_heat_cap"])),
+                          "mean_n_se_max": float(np.nanmax(rw["se_n"])),
+                          "sampled_states_se_max": float(np.nanmax(rw["se_state_n"])),
+                          "errors": "bootstrap over 100 replicates of blocks of records (targets), batch means of "
+                                    "20 batches (sampled states)",
+                          "estimates_with_errors_seconds": t_rw, "estimates_converged": bool(rw["converged"])}
     say(f"[production] {out}")
+    return out
+
+
+def c3_leg(args, prec):
+    """The 4096-replica uneven batch: four slab classes {6,8,10,12}^2 x 3 (108-432
+    atoms), boxes 1.5 n x 1.5 n x 12, each class a 32 T x 32 mu grid, N <= 500, K = 501,
+    exchange every 10 sweeps, every interval one graph replay; c3_sweeps timed sweeps
+    after c3_burnin untimed ones.  Throughput and the sweep kernel against the FP32
+    roofline on both the candidate and the in-cutoff basis."""
+    import torch
+
+    from paper_1908_11118_amd import regc
+    from paper_1908_11118_amd import workloads as W
+
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    wl = W.config3_classes()
+    n_w = sum(x.n_states for x in wl)
+    per_sweep = sum(x.n_states * x.trials for x in wl)
+    recs = (args.c3_burnin + args.c3_sweeps) // wl[0].sample_every + 2
+    out = {"workload": "REGC 4096 replicas: four slab classes {6,8,10,12}^2 x 3 (108-432 atoms), boxes 9-18 x 12, "
+                       "each 32 T x 32 mu, N <= 500, K = 501, exchange every 10 sweeps, one graph replay per interval",
+           "sweeps": args.c3_sweeps, "burnin_sweeps": args.c3_burnin}
+    with regc.Regc(wl, precision=prec, sample_capacity=recs * n_w, graph_intervals=10) as g:
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.c3_burnin:
+            k = min(1000, args.c3_burnin - done)
+            g.run(k)
+            g.sync()
+            done += k
+            say(f"[c3] burn-in {done}/{args.c3_burnin} sweeps, {time.perf_counter() - t0:.1f} s")
+        st0 = g.stats()["stats"].copy()
+        pc0 = g.pair_counts()
+        g.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.c3_sweeps:
+            k = min(2000, args.c3_sweeps - done)
+            g.run(k)
+            g.sync()
+            done += k
+            say(f"[c3] {done}/{args.c3_sweeps} sweeps, {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = g.timing()
+        d = g.stats()["stats"] - st0
+        pc1 = g.pair_counts()
+        wk = g.walkers()
+    trials = int(d[:, [0, 2, 4]].sum())
+    assert trials == args.c3_sweeps * per_sweep, "trial count mismatch"
+    cand, useful = pc1[0] - pc0[0], pc1[1] - pc0[1]
+    ms = tm["ms_sweep"]
+    achieved = FLOPS_PER_PAIR * cand / (ms * 1e-3) / 1e12
+    achieved_in = FLOPS_PER_PAIR * useful / (ms * 1e-3) / 1e12
+    out.update({"value": trials / elapsed, "unit": "trial moves/s", "seconds": elapsed,
+                "mean_N": float(wk["n"].mean()), "max_N": int(wk["n"].max()),
+                "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / PEAK_FP32_TFLOPS,
+                             "basis": "candidate pair terms (gas atoms + slab column block, twice per displacement)",
+                             "achieved_in_cutoff": achieved_in, "frac_in_cutoff": achieved_in / PEAK_FP32_TFLOPS,
+                             "traffic": None,
+                             "timed_unit": "graph replay (10 sweeps + exchange), HIP events on the context stream",
+                             "replays": tm["n_sweep"], "ms_per_replay": ms / max(tm["n_sweep"], 1),
+                             "candidate_pairs_per_replay": cand / max(tm["n_sweep"], 1),
+                             "useful_pair_fraction": useful / max(cand, 1), "flops_per_pair": FLOPS_PER_PAIR}})
+    say(f"[c3] {out['value']:.3g} trial moves/s")
     return out
 
 
@@ -474,6 +560,23 @@ def learned_leg(args):
     return out
 
 
+def oracle_heat_capacity(w, r):
+    """The oracle's heat capacity at each sampled state of an oracle run r: its own
+    reweighting of that state's samples alone (the plain sample moments)."""
+    import numpy as np
+
+    import oracle
+    beta, lnz = oracle.state_arrays(w)
+    out = np.zeros(w.n_states)
+    for k in range(w.n_states):
+        sel = r["state"] == k
+        e, n = r["e"][sel], r["n"][sel]
+        _, logd, _, _, _ = oracle.mbar_solve(beta[k:k + 1], lnz[k:k + 1], [int(sel.sum())], e, n, tol=1e-12)
+        t = oracle.mbar_targets(beta[k:k + 1], lnz[k:k + 1], e, n, logd, w.n_max)
+        out[k] = oracle.heat_capacity_coverage(beta[k:k + 1], t["mean_n"], t["mean_e"], t["mean_e2"], 1.0)[0][0]
+    return out
+
+
 def full_stack_leg(args):
     """4096 uneven replicas (four slab classes 6x6 .. 12x12 x 3, N <= 500) with one
     learned insertion proposal per class fused into the sweep, FP32 pairs; the
@@ -541,12 +644,14 @@ def full_stack_leg(args):
         skip = n_rec // 10
         maps, maps_hi = [], []
         for c, w in enumerate(wl):
+            n_sites = float(int(round(w.lx / 1.5)) ** 2)       # hollow sites of the top layer
             mb = regc.Mbar(w.t, w.mu, w.n_max)
             mb.load_run(g, c, skip)
             t0 = time.perf_counter()
             f, conv, iters, delta = mb.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
-            tr = mb.targets(w.t, w.mu)
             dt = time.perf_counter() - t0
+            tr = mb.reweight(w.t, w.mu, tol=1e-8, max_iter=3000, n_boot=args.fs_boot, n_sites=n_sites,
+                             allow_noconv=True)
             mb.close()
             o, cn = offs[c], cnts[c]
             E = smp["e"].reshape(-1, Wa)[skip:, o:o + cn].ravel()
@@ -557,18 +662,19 @@ def full_stack_leg(args):
             mh = regc.Mbar(w.t[l0:], w.mu, w.n_max)
             mh.set_samples(E[keep], Nn[keep], St[keep] - l0 * len(w.mu))
             _, conv_h, it_h, _ = mh.solve(tol=1e-8, max_iter=3000, allow_noconv=True)
-            trh = mh.targets(w.t[l0:], w.mu)
+            trh = mh.reweight(w.t[l0:], w.mu, tol=1e-8, max_iter=3000, n_boot=args.fs_boot, n_sites=n_sites,
+                              allow_noconv=True)
             mh.close()
-            beta = np.repeat(1.0 / w.t, len(w.mu))
-            heat = beta ** 2 * (tr["mean_e2"] - tr["mean_e"] ** 2)
-            n_sites = int(round(w.lx / 1.5)) ** 2
-            cov = tr["mean_n"] / n_sites
+            cov, heat = tr["coverage"], tr["heat_cap"]
             maps.append(tr)
             maps_hi.append((l0, trh))
             out.setdefault("reweighting", []).append(
                 {"class": w.name, "samples": int(len(E)), "iterations": iters, "converged": bool(conv),
                  "seconds": dt, "coverage_range": [float(cov.min()), float(cov.max())],
-                 "heat_capacity_max": float(heat.max()), "phases": int(len(set(tr["phase"].tolist()))),
+                 "coverage_se_median": float(np.nanmedian(tr["se_coverage"])),
+                 "heat_capacity_max": float(heat.max()),
+                 "heat_capacity_se_median": float(np.nanmedian(tr["se_heat_cap"])),
+                 "phases": int(len(set(tr["phase"].tolist()))),
                  "restricted_t_min": float(w.t[l0]), "restricted_iterations": it_h,
                  "restricted_converged": bool(conv_h)})
             say(f"[full stack] class {c}: reweighting {iters} iterations, {dt:.2f} s")
@@ -592,14 +698,10 @@ def full_stack_leg(args):
     r = ch.run(args.fs_oracle_sweeps)
     t_or = time.perf_counter() - t0
     S = ws.n_states
-    order = np.argsort(r["state"].reshape(-1, S), axis=1)
-    n_or = np.take_along_axis(r["n"].reshape(-1, S), order, axis=1).astype(np.float64)
-    e_or = np.take_along_axis(r["e"].reshape(-1, S), order, axis=1)
-    m_or, se_or = P.mean_se(list(n_or.T))
-    sm_n = smp["n"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]]
-    sm_s = smp["state"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]]
-    n_gpu = np.take_along_axis(sm_n, np.argsort(sm_s, axis=1), axis=1).astype(np.float64)
-    m_gpu, se_gpu = P.mean_se(list(n_gpu.T))
+    m_or, se_or = oracle.batch_means(S, r["state"], r["n"], 20)
+    sm_n = smp["n"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]].ravel()
+    sm_s = smp["state"].reshape(-1, Wa)[skip:, offs[0]:offs[0] + cnts[0]].ravel()
+    m_gpu, se_gpu = regc.batch_means(sm_s, sm_n, cnts[0])
     sub_states = np.array([(4 * a) * len(w0.mu) + 4 * b for a in range(len(sub_t)) for b in range(len(sub_mu))])
     se_c = np.maximum(np.sqrt(se_or ** 2 + se_gpu[sub_states] ** 2), 0.02)     # floor: states pinned at the cap
     hi = np.repeat(sub_t >= args.fs_tmin, len(sub_mu))
@@ -613,10 +715,9 @@ def full_stack_leg(args):
     mbar_all = maps[0]["mean_n"][sub_states]
     mbar_hi = np.full(len(sub_states), np.nan)
     mbar_hi[hi] = trh["mean_n"][sub_states[hi] - l0 * len(w0.mu)]
-    beta_s = np.repeat(1.0 / sub_t, len(sub_mu))
-    heat_or = beta_s ** 2 * e_or.var(axis=0)
+    heat_or = oracle_heat_capacity(ws, r)
     heat_hi = np.full(len(sub_states), np.nan)
-    heat_hi[hi] = (beta_s[hi] ** 2 * (trh["mean_e2"] - trh["mean_e"] ** 2)[sub_states[hi] - l0 * len(w0.mu)])
+    heat_hi[hi] = trh["heat_cap"][sub_states[hi] - l0 * len(w0.mu)]
     out["oracle_subset"] = {
         "grid": "8 x 8 (every fourth T and mu of the 6x6 class), its own REGC from the GPU's configurations",
         "sweeps": args.fs_oracle_sweeps, "seconds": t_or, "threads": oracle.default_threads(),

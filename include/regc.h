@@ -410,6 +410,17 @@ int regc_reweight(regc_mbar *mb, const regc_grid *targets, double tol, int max_i
                   int32_t *phase, double *coverage, double *se_coverage, double *heat_cap, double *se_heat_cap,
                   double *p_n);
 
+/* Per-state mean of N and its batch-means standard error, the definition of
+ * regc_reweight's se_state_n: the samples of each state in the order given, cut into
+ * n_batches batches (batch b: series positions floor(b n_s / B) .. floor((b+1) n_s / B)
+ * - 1), SE = sqrt(var(batch means) / B) with the (B - 1) variance; NaN for a state
+ * with fewer than B samples.  state [ns] in 0..n_states-1 and n [ns] >= 0 are host
+ * arrays, or device arrays when on_device; mean and se [n_states] are host arrays.
+ * Runs on `stream` (a hipStream_t, NULL: the null stream) and returns after it.
+ * EINVAL on an out-of-range state or a negative N. */
+int regc_batch_means(int64_t ns, const int32_t *state, const int32_t *n, int n_states, int n_batches,
+                     int on_device, double *mean, double *se, void *stream);
+
 /* Timing of the last solve: milliseconds in the iteration kernels and their
  * iteration count. */
 int regc_mbar_timing(regc_mbar *mb, double *ms_iter_total, int64_t *n_iter);

@@ -434,6 +434,19 @@ __global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *
 // ---- errors of the estimates ----
 // Batch means: per-state series position of every sample (samples sorted stably by
 // state), batch b = floor(rank B / n_s), integer sums of N per (state, batch).
+// per-state sample counts; bad when a state is out of range or an N negative
+__global__ void bm_count(int64_t ns, const int32_t *st, const int32_t *n, int S, unsigned long long *omega, int *bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = st[i];
+        if (k < 0 || k >= S || n[i] < 0) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        atomicAdd(omega + k, 1ull);
+    }
+}
+
 __global__ void bm_accumulate(int64_t ns, int B, const int32_t *sorted_state, const int32_t *sorted_idx,
                               const int32_t *n_orig, const int64_t *state_start, const int64_t *state_count,
                               unsigned long long *bsum, unsigned long long *bcnt)
@@ -1164,27 +1177,39 @@ static int refresh_logd(regc_mbar *mb)
     return REGC_OK;
 }
 
-static int batch_means_dev(regc_mbar *mb, int B, double *mean_d, double *se_d)
+// Per-state mean of N and its batch-means SE of ns samples (state, n) in the order
+// given, device arrays; outputs device arrays [S].  EINVAL on a state outside 0..S-1
+// or a negative N.
+static int batch_means_dev(hipStream_t s, int64_t ns, const int32_t *st_d, const int32_t *n_d, int S, int B,
+                           double *mean_d, double *se_d)
 {
-    hipStream_t s = mb->stream;
-    const int64_t ns = mb->ns;
     DevBuf<uint32_t> keys, keys_out;
     DevBuf<int32_t> idx, idx_out;
     DevBuf<int64_t> start_d, count_d;
-    DevBuf<unsigned long long> bsum, bcnt, omega, seg;
+    DevBuf<unsigned long long> bsum, bcnt, omega;
     DevBuf<int> bad;
     int rc;
     if ((rc = keys.alloc(ns)) || (rc = keys_out.alloc(ns)) || (rc = idx.alloc(ns)) || (rc = idx_out.alloc(ns)) ||
-        (rc = start_d.alloc(mb->S)) || (rc = count_d.alloc(mb->S)) || (rc = bsum.alloc((size_t)mb->S * B)) ||
-        (rc = bcnt.alloc((size_t)mb->S * B)) || (rc = omega.alloc(mb->S)) || (rc = seg.alloc(mb->nN)) ||
-        (rc = bad.alloc(1)))
+        (rc = start_d.alloc(S)) || (rc = count_d.alloc(S)) || (rc = bsum.alloc((size_t)S * B)) ||
+        (rc = bcnt.alloc((size_t)S * B)) || (rc = omega.alloc(S)) || (rc = bad.alloc(1)))
         return rc;
     const int grid = (int)std::min<int64_t>((ns + 255) / 256, 4096);
+    // per-state counts (and the validation of the inputs) first
+    std::vector<unsigned long long> cnt(S);
+    int h_bad = 0;
+    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S, omega.p);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, 0, bad.p);
+    hipLaunchKernelGGL(bm_count, dim3(grid), dim3(256), 0, s, ns, st_d, n_d, S, omega.p, bad.p);
+    REGC_HIP(hipGetLastError());
+    REGC_HIP(hipMemcpyAsync(cnt.data(), omega.p, sizeof(unsigned long long) * S, hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    REGC_HIP(hipStreamSynchronize(s));
+    REGC_CHECK(!h_bad, REGC_EINVAL, "a sample's state is outside 0..%d or its N is negative", S - 1);
     // stable sort of the sample indices by state: each state's series in sample order
-    hipLaunchKernelGGL(mbar_iota_gather, dim3(grid), dim3(256), 0, s, ns, mb->s_orig_d.p, keys.p, idx.p);
+    hipLaunchKernelGGL(mbar_iota_gather, dim3(grid), dim3(256), 0, s, ns, st_d, keys.p, idx.p);
     REGC_HIP(hipGetLastError());
     int end_bit = 1;
-    while ((1 << end_bit) < mb->S) ++end_bit;
+    while ((1 << end_bit) < S) ++end_bit;
     size_t temp_bytes = 0;
     REGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
                                                 end_bit, s));
@@ -1192,33 +1217,49 @@ static int batch_means_dev(regc_mbar *mb, int B, double *mean_d, double *se_d)
     if ((rc = temp.alloc(temp_bytes))) return rc;
     REGC_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
                                                 end_bit, s));
-    // per-state counts (the unweighted ones) and series starts
-    std::vector<unsigned long long> cnt(mb->S);
-    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(256), 0, s, (int64_t)mb->S, omega.p);
-    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(256), 0, s, (int64_t)mb->nN, seg.p);
-    hipLaunchKernelGGL(mbar_count, dim3(grid), dim3(256), 0, s, ns, mb->n_orig_d.p, mb->s_orig_d.p, mb->nN, mb->S,
-                       omega.p, seg.p, bad.p);     // (samples were validated when loaded)
-    REGC_HIP(hipGetLastError());
-    REGC_HIP(hipMemcpyAsync(cnt.data(), omega.p, sizeof(unsigned long long) * mb->S, hipMemcpyDeviceToHost, s));
-    REGC_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> start(mb->S), count(mb->S);
+    std::vector<int64_t> start(S), count(S);
     int64_t acc = 0;
-    for (int k = 0; k < mb->S; ++k) {
+    for (int k = 0; k < S; ++k) {
         start[k] = acc;
         count[k] = (int64_t)cnt[k];
         acc += count[k];
     }
-    REGC_HIP(hipMemcpyAsync(start_d.p, start.data(), sizeof(int64_t) * mb->S, hipMemcpyHostToDevice, s));
-    REGC_HIP(hipMemcpyAsync(count_d.p, count.data(), sizeof(int64_t) * mb->S, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)mb->S * B, bsum.p);
-    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)mb->S * B, bcnt.p);
-    hipLaunchKernelGGL(bm_accumulate, dim3(grid), dim3(256), 0, s, ns, B, (const int32_t *)keys_out.p, idx_out.p,
-                       mb->n_orig_d.p, start_d.p, count_d.p, bsum.p, bcnt.p);
+    REGC_HIP(hipMemcpyAsync(start_d.p, start.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
+    REGC_HIP(hipMemcpyAsync(count_d.p, count.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S * B, bsum.p);
+    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S * B, bcnt.p);
+    hipLaunchKernelGGL(bm_accumulate, dim3(grid), dim3(256), 0, s, ns, B, (const int32_t *)keys_out.p, idx_out.p, n_d,
+                       start_d.p, count_d.p, bsum.p, bcnt.p);
     REGC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(bm_finish, dim3((mb->S + 255) / 256), dim3(256), 0, s, mb->S, B, bsum.p, bcnt.p, count_d.p,
-                       mean_d, se_d);
+    hipLaunchKernelGGL(bm_finish, dim3((S + 255) / 256), dim3(256), 0, s, S, B, bsum.p, bcnt.p, count_d.p, mean_d,
+                       se_d);
     REGC_HIP(hipGetLastError());
     REGC_HIP(hipStreamSynchronize(s));
+    return REGC_OK;
+}
+
+extern "C" int regc_batch_means(int64_t ns, const int32_t *state, const int32_t *n, int n_states, int n_batches,
+                                int on_device, double *mean, double *se, void *stream)
+{
+    REGC_CHECK(state && n && mean && se, REGC_EINVAL, "null argument");
+    REGC_CHECK(ns > 0 && ns <= INT32_MAX, REGC_EINVAL, "sample count must be 1..2^31-1");
+    REGC_CHECK(n_states > 0 && n_batches >= 2, REGC_EINVAL, "n_states must be positive and n_batches >= 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf<int32_t> st_in, n_in;
+    DevBuf<double> m_d, se_d;
+    int rc;
+    if ((rc = m_d.alloc(n_states)) || (rc = se_d.alloc(n_states))) return rc;
+    const int32_t *st_d = state, *n_d = n;
+    if (!on_device) {
+        if ((rc = st_in.alloc(ns)) || (rc = n_in.alloc(ns))) return rc;
+        REGC_HIP(hipMemcpyAsync(st_in.p, state, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        REGC_HIP(hipMemcpyAsync(n_in.p, n, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        st_d = st_in.p;
+        n_d = n_in.p;
+    }
+    if ((rc = batch_means_dev(s, ns, st_d, n_d, n_states, n_batches, m_d.p, se_d.p))) return rc;
+    REGC_HIP(hipMemcpy(mean, m_d.p, sizeof(double) * n_states, hipMemcpyDeviceToHost));
+    REGC_HIP(hipMemcpy(se, se_d.p, sizeof(double) * n_states, hipMemcpyDeviceToHost));
     return REGC_OK;
 }
 
@@ -1265,7 +1306,9 @@ extern "C" int regc_reweight(regc_mbar *mb, const regc_grid *targets, double tol
     hipLaunchKernelGGL(heat_cov, dim3((nK + 255) / 256), dim3(256), 0, s, T.nT, T.nMu, T.tb_d.p, mn.p, me.p, me2.p,
                        o.n_sites > 0 ? o.n_sites : 1.0, heat.p, cov.p);
     REGC_HIP(hipGetLastError());
-    if ((rc = batch_means_dev(mb, o.n_batches, smean.p, sse.p))) return rc;
+    if ((rc = batch_means_dev(mb->stream, mb->ns, mb->s_orig_d.p, mb->n_orig_d.p, mb->S, o.n_batches, smean.p,
+                              sse.p)))
+        return rc;
     REGC_HIP(hipStreamSynchronize(s));
     if (mean_n) REGC_HIP(hipMemcpy(mean_n, mn.p, sizeof(double) * nK, hipMemcpyDeviceToHost));
     if (phase) REGC_HIP(hipMemcpy(phase, ph.p, sizeof(int32_t) * nK, hipMemcpyDeviceToHost));

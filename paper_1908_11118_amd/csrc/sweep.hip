@@ -478,24 +478,19 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) batch_kernel(Swee
                 const int ex = kind == 1 ? -1 : i;                // the gas atom left out of the sum
                 const Real4 o = gas[i];
                 const Real eo = kind == 1 || skip ? Real(0) : eslab[i];
-                double px = 0.0, py = 0.0, pz = 0.0, c;
-                bool wall = false;
-                if (kind == 0) {
-                    px = (double)o.x + md * (2.0 * ux - 1.0);
-                    py = (double)o.y + md * (2.0 * uy - 1.0);
-                    pz = (double)o.z + md * (2.0 * uz - 1.0);
-                    if (px < 0.0) px += lx; else if (px >= lx) px -= lx;
-                    if (py < 0.0) py += ly; else if (py >= ly) py -= ly;
-                    wall = !skip && (pz < zlo || pz > zhi);
-                    c = 0.0;
-                } else if (kind == 1) {
-                    px = lx * ux;
-                    py = ly * uy;
-                    pz = zlo + H * uz;
-                    c = lnzv_v - lnk[n0 + 1];                     // ln z V / (N+1)
-                } else {
-                    c = lnk[n0] - lnzv_v;                         // ln N / (z V)
-                }
+                // (the kinds differ between the wave's groups: selects, not branches)
+                double dx = (double)o.x + md * (2.0 * ux - 1.0);
+                double dy = (double)o.y + md * (2.0 * uy - 1.0);
+                const double dz = (double)o.z + md * (2.0 * uz - 1.0);
+                dx = dx < 0.0 ? dx + lx : (dx >= lx ? dx - lx : dx);
+                dy = dy < 0.0 ? dy + ly : (dy >= ly ? dy - ly : dy);
+                const double px = kind == 0 ? dx : lx * ux;
+                const double py = kind == 0 ? dy : ly * uy;
+                const double pz = kind == 0 ? dz : zlo + H * uz;
+                const bool wall = (kind == 0) & !skip & ((dz < zlo) | (dz > zhi));
+                const double ln0 = lnk[n0], ln1 = lnk[n0 + 1];
+                // 0, ln z V / (N+1) or ln N / (z V)
+                const double c = kind == 0 ? 0.0 : (kind == 1 ? lnzv_v - ln1 : ln0 - lnzv_v);
                 const double thr = (c - lnU) * tinv;              // accept iff dE <= thr
                 const bool live = act && !skip && !wall;          // the trial moves a particle
                 const bool compute = live && !ideal;
@@ -580,43 +575,33 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) batch_kernel(Swee
                 uint64_t tmask = 0;          // changed slots, as bits of (slot mod 64)
                 double de = (double)sde;
                 bool ccr = false;
+                // (branch-free: the trial kinds are wave-uniform, the scenarios are not)
 #pragma unroll
                 for (int g = 0; g + 1 < B; ++g) {
-                    if (g < grp && ((sc >> g) & 1u)) {
-                        const int kg = (int)(pk[g] & 3u), ig = (int)(pk[g] >> 8);
-                        if (kg == 0) {
-                            tmask |= 1ull << (ig & 63);
-                        } else if (kg == 1) {
-                            tmask |= 1ull << (ncur & 63);
-                            ncur += 1;
-                        } else {
-                            tmask |= (1ull << (ig & 63)) | (1ull << ((ncur - 1) & 63));
-                            ncur -= 1;
-                        }
-                        de += (double)cg[g];
-                        ccr |= ((ccore_lanes >> (grp * G + 4 * g)) & 1ull) != 0;
-                    }
+                    const bool take = (g < grp) & (((sc >> g) & 1u) != 0);
+                    const int kg = (int)(pk[g] & 3u), ig = (int)(pk[g] >> 8);
+                    const uint64_t bi = kg != 1 ? 1ull << (ig & 63) : 0ull;       // moved or refilled slot
+                    const uint64_t bn = kg != 0 ? 1ull << ((kg == 1 ? ncur : ncur - 1) & 63) : 0ull;
+                    tmask |= take ? (bi | bn) : 0ull;
+                    ncur += take ? (kg == 1 ? 1 : (kg == 2 ? -1 : 0)) : 0;
+                    de += take ? (double)cg[g] : 0.0;
+                    ccr |= take & (((ccore_lanes >> (grp * G + 4 * g)) & 1ull) != 0);
                 }
+                // (scenarios off the real path may imply an N outside 0..n_max)
+                const int nq = ncur < 0 ? 0 : (ncur > n_max ? n_max : ncur);
+                const double lq = lnk[kind == 1 ? nq + 1 : nq];
                 const bool gcore = ((core_lanes >> (grp * G)) & (G == 64 ? ~0ull : ((1ull << G) - 1))) != 0;
-                bool redo = false;
-                if (sc != 0) {
-                    redo = compute && gcore;
-                    if (kind == 1) redo |= skip && ncur < n_max;
-                    else if (n0 == 0) redo |= ncur > 0;
-                    else if (ncur > 0)
-                        redo |= (int)(((uint64_t)A1 * (uint64_t)ncur) >> 32) != i || ((tmask >> (i & 63)) & 1ull) != 0;
-                }
+                const bool ichg = ((uint32_t)(((uint64_t)A1 * (uint64_t)(uint32_t)nq) >> 32) != (uint32_t)i) |
+                                  (((tmask >> (i & 63)) & 1ull) != 0);
+                const bool rk = kind == 1 ? skip & (ncur < n_max) : (n0 == 0 ? ncur > 0 : (ncur > 0) & ichg);
+                const bool redo = (sc != 0) & ((compute & gcore) | rk);
                 const bool capemp = kind == 1 ? ncur >= n_max : ncur == 0;
-                double th = thr;
-                if (kind != 0 && ncur != n0) {
-                    // (scenarios off the real path may imply an N outside 0..n_max)
-                    const int nq = ncur < 0 ? 0 : (ncur > n_max ? n_max : ncur);
-                    th = ((kind == 1 ? lnzv_v - lnk[nq + 1] : lnk[nq] - lnzv_v) - lnU) * tinv;
-                }
-                const bool cr = compute && kind != 2 && (gcore || ccr);
-                if (!compute) de = 0.0;
-                const bool scen = act && sc < (1u << grp);
-                const bool ok = scen && !redo && !capemp && !wall && !cr && de <= th;
+                const double th = (kind != 0 && ncur != n0) ? ((kind == 1 ? lnzv_v - lq : lq - lnzv_v) - lnU) * tinv
+                                                             : thr;
+                const bool cr = compute & (kind != 2) & (gcore | ccr);
+                de = compute ? de : 0.0;
+                const bool scen = act & (sc < (1u << grp));
+                const bool ok = scen & !redo & !capemp & !wall & !cr & (de <= th);
                 const uint64_t redo_m = __ballot(scen && redo);
                 const uint64_t acc_m = __ballot(ok);
                 const uint64_t cap_m = __ballot(scen && !redo && capemp);

@@ -19,7 +19,6 @@ is counted.
 """
 from __future__ import annotations
 
-import math
 import time
 from typing import Dict, Optional
 
@@ -96,40 +95,12 @@ def train(vox, n, steps: int = 10000, batch: int = 256, lr: float = 1e-3, seed: 
     return net
 
 
-def _per_state(state, nvals, S):
-    out = [[] for _ in range(S)]
-    order = np.argsort(state, kind="stable")
-    st = state[order]
-    nv = nvals[order]
-    bounds = np.searchsorted(st, np.arange(S + 1))
-    for s in range(S):
-        out[s] = nv[bounds[s]:bounds[s + 1]]
-    return out
-
-
-def mean_se(series, n_batches: int = 20):
-    """Mean and batch-means standard error of each state's series."""
-    m = np.zeros(len(series))
-    se = np.full(len(series), np.inf)
-    for s, x in enumerate(series):
-        x = np.asarray(x, dtype=np.float64)
-        if len(x) == 0:
-            m[s] = np.nan
-            continue
-        m[s] = x.mean()
-        b = len(x) // n_batches
-        if b >= 1:
-            bm = x[: b * n_batches].reshape(n_batches, b).mean(axis=1)
-            se[s] = bm.std(ddof=1) / math.sqrt(n_batches)
-    return m, se
-
-
 def reference(workload, sweeps: int = 100000, burnin: int = 2000, seed: int = 4, precision: int = regc.FP64,
               chunk: int = 5000):
     """Long plain run: per-state mean N and its standard error (records every sweep)."""
     w = workload.replace(seed=seed, sample_every=1)
     S = w.n_states
-    parts_s, parts_n = [], []
+    series = _Series(S)
     with regc.Regc(w, precision=precision, sample_capacity=chunk * S) as g:
         g.run(burnin)
         g.clear_samples()
@@ -138,42 +109,37 @@ def reference(workload, sweeps: int = 100000, burnin: int = 2000, seed: int = 4,
             k = min(chunk, sweeps - done)
             g.run(k)
             smp = g.samples()
-            parts_s.append(smp["state"])
-            parts_n.append(smp["n"])
+            series.add(smp["state"], smp["n"])
             g.clear_samples()
             done += k
-    return mean_se(_per_state(np.concatenate(parts_s), np.concatenate(parts_n), S))
+    return series.mean_se()
 
 
 class _Series:
-    """Per-state N series held as running prefix sums: batch-means statistics of all
-    samples so far in O(states x batches) per check."""
+    """All (state, N) samples of a run so far, in sample order; their per-state mean
+    and batch-means standard error come from the library (regc_batch_means)."""
 
     def __init__(self, S: int, n_batches: int = 20):
         self.S, self.nb = S, n_batches
-        self.cs = np.zeros((1024, S))       # cs[k] = sum of the first k records
+        self.state = np.zeros(1 << 16, np.int32)
+        self.n = np.zeros(1 << 16, np.int32)
         self.L = 0
 
     def add(self, state, n):
-        rec = np.asarray(n, dtype=np.float64).reshape(-1, self.S)
-        st = np.asarray(state).reshape(-1, self.S)
-        by_state = np.zeros_like(rec)
-        np.put_along_axis(by_state, st, rec, axis=1)
-        k = rec.shape[0]
-        while self.L + k + 1 > self.cs.shape[0]:
-            self.cs = np.concatenate([self.cs, np.zeros_like(self.cs)])
-        self.cs[self.L + 1:self.L + k + 1] = self.cs[self.L] + np.cumsum(by_state, axis=0)
+        k = len(n)
+        while self.L + k > len(self.n):
+            self.state = np.concatenate([self.state, np.zeros_like(self.state)])
+            self.n = np.concatenate([self.n, np.zeros_like(self.n)])
+        self.state[self.L:self.L + k] = state
+        self.n[self.L:self.L + k] = n
         self.L += k
 
     def mean_se(self):
-        L, nb = self.L, self.nb
-        m = self.cs[L] / max(L, 1)
-        b = L // nb
-        if b < 1:
-            return m, np.full(self.S, np.inf)
-        edges = self.cs[np.arange(nb + 1) * b]
-        bm = (edges[1:] - edges[:-1]) / b
-        return m, bm.std(axis=0, ddof=1) / math.sqrt(nb)
+        """Mean and SE per state (SE infinite below n_batches samples)."""
+        if self.L == 0:
+            return np.full(self.S, np.nan), np.full(self.S, np.inf)
+        m, se = regc.batch_means(self.state[:self.L], self.n[:self.L], self.S, self.nb)
+        return m, np.where(np.isnan(se), np.inf, se)
 
 
 def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["regc.Mlp"] = None,

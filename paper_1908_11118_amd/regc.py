@@ -36,7 +36,7 @@ EXPORTS = ["regc_default_opts", "regc_create", "regc_create_batch", "regc_get_la
            "regc_observables_device", "regc_get_observables", "regc_mbar_set_observables", "regc_mbar_observables",
            "regc_track_minima", "regc_get_minima", "regc_aiat_phase", "regc_strerror", "regc_last_error",
            "regc_default_reweight_opts", "regc_reweight", "regc_mlp_step", "regc_proposal_eval",
-           "regc_count_pairs"]
+           "regc_count_pairs", "regc_batch_means"]
 
 
 class RegcError(RuntimeError):
@@ -135,6 +135,8 @@ def lib():
         L.regc_mbar_set_solver.argtypes = [vp, C.c_int, C.c_int]
         L.regc_mbar_solve.argtypes = [vp, C.c_double, C.c_int, _dp, C.POINTER(C.c_int), _dp]
         L.regc_mbar_targets.argtypes = [vp, C.POINTER(Grid), _dp, _dp, _dp, _dp, _dp, _i32p]
+        L.regc_mbar_targets_static.argtypes = [vp, C.POINTER(Grid), _dp, _dp, _dp, _dp, _i32p]
+        L.regc_batch_means.argtypes = [C.c_int64, vp, vp, C.c_int, C.c_int, C.c_int, _dp, _dp, vp]
         L.regc_mbar_timing.argtypes = [vp, _dp, _i64p]
         L.regc_default_reweight_opts.argtypes = [C.POINTER(ReweightOpts)]
         L.regc_default_reweight_opts.restype = None
@@ -674,3 +676,21 @@ def aiat_phase(e_min, mu):
     _check(lib().regc_aiat_phase(_p(e, _dp), len(e) - 1, len(m), _p(m, _dp), _p(out, _i32p)))
     return out
 
+
+
+def batch_means(state, n, n_states: int, n_batches: int = 20):
+    """regc_batch_means: per-state mean N and batch-means SE.  state and n are numpy
+    arrays, or int32 torch tensors on the GPU (read in place, on torch's stream)."""
+    mean, se = np.zeros(n_states), np.zeros(n_states)
+    if hasattr(state, "data_ptr"):
+        assert state.dtype == n.dtype and str(state.dtype) == "torch.int32" and state.is_cuda and n.is_cuda
+        assert state.is_contiguous() and n.is_contiguous() and state.numel() == n.numel()
+        _check(lib().regc_batch_means(state.numel(), C.c_void_p(state.data_ptr()), C.c_void_p(n.data_ptr()),
+                                      n_states, n_batches, 1, _p(mean, _dp), _p(se, _dp), _torch_stream()))
+    else:
+        s = np.ascontiguousarray(state, dtype=np.int32)
+        v = np.ascontiguousarray(n, dtype=np.int32)
+        assert s.shape == v.shape
+        _check(lib().regc_batch_means(len(s), _p(s, _i32p), _p(v, _i32p), n_states, n_batches, 0, _p(mean, _dp),
+                                      _p(se, _dp), _torch_stream()))
+    return mean, se

@@ -202,6 +202,54 @@ def test_reweight_errors_coverage_heat_capacity_match_the_oracle():
     mb.close()
 
 
+def test_batch_means_entry_matches_the_oracle():
+    """regc_batch_means (host and device inputs) against the oracle's batch means on
+    an uneven per-state sample count, a state below the batch count, and rejection of
+    an out-of-range state."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(21)
+    S, ns = 37, 250_000
+    st = rng.integers(0, S - 1, ns).astype(np.int32)          # state S-1 gets a handful only
+    st[:7] = S - 1
+    n = rng.poisson(3.0 + st % 11, ns).astype(np.int32)
+    m_ref, se_ref = oracle.batch_means(S, st, n, 20)
+    m, se = regc.batch_means(st, n, S, 20)
+    assert np.array_equal(np.isnan(m), np.isnan(m_ref)) and np.isnan(m[S - 1])
+    ok = ~np.isnan(m_ref)
+    assert np.allclose(m[ok], m_ref[ok], rtol=1e-14, atol=0)
+    assert np.allclose(se[ok], se_ref[ok], rtol=1e-12, atol=1e-15)
+    md, sed = regc.batch_means(torch.from_numpy(st).cuda(), torch.from_numpy(n).cuda(), S, 20)
+    assert np.array_equal(md[ok], m[ok]) and np.array_equal(sed[ok], se[ok])
+    bad = st.copy()
+    bad[100] = S
+    with pytest.raises(regc.RegcError) as ei:
+        regc.batch_means(bad, n, S, 20)
+    assert ei.value.code == regc.EINVAL
+
+
+def test_running_series_of_the_time_to_accuracy_matches_the_oracle():
+    """The time-to-accuracy runs' sample series (records added chunk by chunk, statistics
+    from regc_batch_means) against the oracle's batch means over all samples, whatever
+    the chunking; infinite SE before 20 samples per state."""
+    from paper_1908_11118_amd.proposal import _Series
+    rng = np.random.default_rng(0)
+    S, recs = 8, 1013
+    state = np.array([rng.permutation(S) for _ in range(recs)]).ravel().astype(np.int32)
+    n = rng.integers(0, 50, recs * S).astype(np.int32)
+    m_ref, se_ref = oracle.batch_means(S, state, n, 20)
+    for chunk in (1, 37, 100, recs):
+        ser = _Series(S)
+        for k in range(0, recs, chunk):
+            ser.add(state[k * S:(k + chunk) * S], n[k * S:(k + chunk) * S])
+        m, se = ser.mean_se()
+        assert np.allclose(m, m_ref, rtol=0, atol=1e-12)
+        assert np.allclose(se, se_ref, rtol=1e-12, atol=1e-12)
+    few = _Series(3)
+    few.add(np.tile(np.arange(3, dtype=np.int32), 10), rng.integers(0, 9, 30).astype(np.int32))
+    m, se = few.mean_se()
+    assert np.all(np.isinf(se)) and np.all(np.isnan(m))
+
+
 def test_reweight_rejects_partial_records():
     w = W.small_lj(n_t=2, n_mu=2, n_max=10)
     mb = regc.Mbar(w.t, w.mu, w.n_max)

@@ -1,37 +1,7 @@
-"""Host-side statistics of the time-to-accuracy measurement (CPU only): the running
-per-state series gives the same mean and batch-means error as the direct
-computation over all samples, whatever the chunking."""
-import numpy as np
-
-from paper_1908_11118_amd.proposal import _Series, _per_state, efficiency_ratio, mean_se
-
-
-def _records(seed, recs, S):
-    rng = np.random.default_rng(seed)
-    state = np.array([rng.permutation(S) for _ in range(recs)]).ravel()
-    n = rng.integers(0, 50, recs * S)
-    return state, n
-
-
-def test_running_series_equals_direct_batch_means():
-    S, recs = 8, 1013
-    state, n = _records(0, recs, S)
-    m_ref, se_ref = mean_se(_per_state(state, n, S))
-    for chunk in (1, 37, 100, recs):
-        ser = _Series(S)
-        for k in range(0, recs, chunk):
-            ser.add(state[k * S:(k + chunk) * S], n[k * S:(k + chunk) * S])
-        m, se = ser.mean_se()
-        assert np.allclose(m, m_ref, rtol=0, atol=1e-12)
-        assert np.allclose(se, se_ref, rtol=1e-12, atol=1e-12)
-
-
-def test_series_before_enough_batches_reports_infinite_error():
-    ser = _Series(3, n_batches=20)
-    state, n = _records(1, 10, 3)
-    ser.add(state, n)
-    m, se = ser.mean_se()
-    assert np.all(np.isinf(se)) and np.all(np.isfinite(m))
+"""Host-side pieces of the benchmark (CPU only): the per-state efficiency ratio of
+two time-to-accuracy runs, the single-GPU guard and the traffic figure's source
+hash."""
+from paper_1908_11118_amd.proposal import efficiency_ratio
 
 
 def test_efficiency_ratio():
