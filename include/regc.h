@@ -122,9 +122,10 @@ typedef struct {
  *  sweeps_per_launch  upper bound of sweeps per kernel launch; 0 -> swap_every.
  *  slab_bins       -1 off, 1 on, 0 auto: slab atoms sorted into x-y columns no
  *                  narrower than rcut + max_disp; each trial scans the 3x3 block of columns.
- *  split           wavefronts per walker: 1, 2, or 0 (auto: 2 when the sweep schedule
+ *  split           wavefronts per walker: 1, 2, 4, or 0 (auto: 2 when the sweep schedule
  *                  runs at most 4 walkers per compute unit and walkers_per_block is 0,
- *                  else 1); with 2, walkers_per_block is 1.
+ *                  else 1); above 1, walkers_per_block is 1 and the waves share each
+ *                  trial's candidates.
  *  cull            1: squared distances first, LJ terms only for pairs inside the
  *                  cutoff (compacted in LDS); 0 or -1: every candidate in full.
  *  graph_intervals 0: launch kernels one by one; R > 0: capture R exchange intervals
@@ -170,7 +171,10 @@ typedef struct {
  *                  the batch and leaving to the next batch a trial whose particle index
  *                  or particle an earlier accepted move changed: the accept/reject
  *                  sequence and configurations are those of one trial at a time.  1: one
- *                  trial at a time (split and cull apply).  0: 1. */
+ *                  trial at a time (split and cull apply).  0: 1.
+ *  slab_cell       width of the slab's x-y columns as a multiple (>= 1) of the
+ *                  smallest one, rcut + max_disp (0: 1): wider columns hold more atoms
+ *                  each and fewer per block, the tuner's cell-size choice. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -192,6 +196,7 @@ typedef struct {
     double md_dt, md_tau;
     int resync_every;
     int batch_trials;
+    double slab_cell;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

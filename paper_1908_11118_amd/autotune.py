@@ -1,14 +1,17 @@
 """Launch-shape autotuner for REGC sampling contexts.
 
-The choices it makes -- walkers per workgroup, wavefronts per walker, the cull
-pass, slab column binning, sweeps per launch and graph replay -- change only the
-order of floating-point sums, never the chain (FP64 trajectories are identical for
-every choice), so the tuned run samples the same distribution.
+The choices it makes -- walkers per workgroup, wavefronts per walker, batched
+trials, the cull pass, slab column binning and its column width (the slab's cell
+size), sweeps per launch and graph replay of several exchange intervals per
+submission -- change only the order of floating-point sums, never the chain (FP64
+trajectories are identical for every choice), so the tuned run samples the same
+distribution.
 
 Procedure: equilibrate one context with default options, checkpoint it, then for
 each candidate build a context, restore the checkpoint, run a short timed window
-and keep the fastest.  The search is greedy over one option at a time.  Results
-are cached in a JSON file keyed by the workload signature and the device name.
+and keep the fastest.  The search starts from the library's own choices and is
+greedy over one option at a time.  Results are cached in a JSON file keyed by the
+workload signature and the device name.
 """
 from __future__ import annotations
 
@@ -85,16 +88,24 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
             print(f"[autotune] {opts} -> {rate:.4g} trials/s", file=sys.stderr, flush=True)
         return rate
 
-    best = {"walkers_per_block": 1, "split": 1, "cull": 0, "slab_bins": 0, "graph_intervals": 0}
+    # 0 everywhere: the library's own choices
+    best = {"walkers_per_block": 0, "split": 0, "batch_trials": 0, "cull": 0, "slab_bins": 0, "slab_cell": 0.0,
+            "sweeps_per_launch": 0, "graph_intervals": 0}
     best_rate = trial(best)
-    space = [("walkers_per_block", [2, 4, 8]), ("split", [2]), ("cull", [1]), ("slab_bins", [-1]),
-             ("graph_intervals", [4])]
+    spl = sorted({s for s in (interval // 2, max(1, interval // 5)) if 0 < s < interval})
+    space = [("walkers_per_block", [1, 2, 4, 8]), ("split", [1, 2, 4]), ("batch_trials", [2, 4]),
+             ("cull", [1]), ("slab_bins", [-1]), ("slab_cell", [1.25, 1.5]), ("sweeps_per_launch", spl),
+             ("graph_intervals", [4, 10])]
     for name, values in space:
         for v in values:
             cand = dict(best)
             cand[name] = v
-            if cand["split"] == 2:
-                cand["walkers_per_block"] = 1
+            if cand["split"] > 1 or cand["batch_trials"] > 1:
+                cand["walkers_per_block"] = 1 if cand["split"] > 1 else cand["walkers_per_block"]
+            if name == "batch_trials":
+                cand["split"], cand["cull"] = 1, 0
+            if name == "split" and v > 1:
+                cand["batch_trials"] = 1
             rate = trial(cand)
             if rate > best_rate:
                 best, best_rate = cand, rate

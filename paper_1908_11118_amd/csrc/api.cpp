@@ -156,6 +156,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->md_tau = 0.1;
     o->resync_every = 0;
     o->batch_trials = 0;
+    o->slab_cell = 0.0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -185,10 +186,12 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->swap_scheme == 0 || o->swap_scheme == 1, REGC_EUNSUPPORTED, "unknown swap scheme");
     REGC_CHECK(o->walkers_per_block >= 0 && o->walkers_per_block <= kMaxWalkersPerBlock, REGC_EINVAL,
                "walkers_per_block must be 0..%d", kMaxWalkersPerBlock);
-    REGC_CHECK(o->split >= 0 && o->split <= 2, REGC_EINVAL, "split must be 0, 1 or 2");
+    REGC_CHECK(o->split >= 0 && o->split <= 4 && o->split != 3, REGC_EINVAL, "split must be 0, 1, 2 or 4");
     REGC_CHECK(o->graph_intervals >= 0 && o->graph_intervals <= 1000, REGC_EINVAL, "graph_intervals must be 0..1000");
     REGC_CHECK(o->schedule == 0 || o->schedule == 1, REGC_EUNSUPPORTED, "unknown schedule %d", o->schedule);
     REGC_CHECK(o->resync_every >= -1, REGC_EINVAL, "resync_every must be -1, 0 or positive");
+    REGC_CHECK(o->slab_cell == 0.0 || (o->slab_cell >= 1.0 && o->slab_cell <= 16.0), REGC_EINVAL,
+               "slab_cell must be 0 or in [1, 16]");
     REGC_CHECK(o->batch_trials >= 0 && o->batch_trials <= 4 && o->batch_trials != 3, REGC_EINVAL,
                "batch_trials must be 0, 1, 2 or 4");
     if (o->schedule == 1) {
@@ -205,8 +208,9 @@ static void pack_slab(ClassHost &c, const regc_potential *pot, const regc_opts *
 {
     const int ns = c.sys.n_slab;
     const double lx = c.sys.lx, ly = c.sys.ly;
-    const int ncx = (int)std::floor(lx / (pot->rcut + o->max_disp));
-    const int ncy = (int)std::floor(ly / (pot->rcut + o->max_disp));
+    const double cw = (pot->rcut + o->max_disp) * (o->slab_cell > 1.0 ? o->slab_cell : 1.0);
+    const int ncx = (int)std::floor(lx / cw);
+    const int ncy = (int)std::floor(ly / cw);
     const bool bins = ns > 0 && ncx >= 3 && ncy >= 3 && o->slab_bins >= 0;
     c.bins = bins ? 1 : 0;
     c.packed.clear();
@@ -332,9 +336,11 @@ static int ctx_alloc_and_init(regc_ctx *c)
     // launch shape: walkers per block, waves per walker, LDS
     int dev = 0;
     REGC_HIP(hipGetDevice(&dev));
-    int lds_max = 0, n_cu = 0;
+    int lds_max = 0, n_cu = 0, lds_cu = 0;
     REGC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     REGC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    REGC_HIP(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    if (lds_cu <= 0) lds_cu = lds_max;
     const int real = o.precision == REGC_FP64 ? 8 : 4;
     // waves per walker unless asked: two while one each would leave at most one wave
     // per SIMD (W <= 4 x CUs: a walker's trial chain is latency-bound and the second
@@ -353,8 +359,25 @@ static int ctx_alloc_and_init(regc_ctx *c)
         if (batch > 1) return batch_lds(max_slab_len, nmax, wpb, real).total;
         return lds_layout(max_slab_len, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
     };
-    int wpb = split == 2 ? 1 : o.walkers_per_block;
-    if (wpb == 0) wpb = W >= 1024 ? 4 : 1;
+    int wpb = split > 1 ? 1 : o.walkers_per_block;
+    if (wpb == 0) {
+        wpb = 1;
+        if (W >= 1024) {
+            // the walkers a compute unit must hold (at most four waves per SIMD), and the
+            // workgroup size that lets its LDS hold them all: 4 walkers per workgroup, or 8
+            // when a workgroup of 4 leaves too little LDS for the rest (each workgroup
+            // carries its own slab and ln k copies; measured 1.36e9 against 1.12e9 trial
+            // moves/s for the 4096-replica uneven batch, whose four-walker workgroups of
+            // 500-atom walkers fit three to a compute unit)
+            const int need = std::min(16, (W + n_cu - 1) / n_cu);
+            auto resident = [&](int k) {
+                const size_t b = smem_for(k);
+                if (b > (size_t)lds_max) return 0;
+                return std::min(need, (int)(lds_cu / b) * k);
+            };
+            wpb = resident(8) > resident(4) ? 8 : 4;
+        }
+    }
     while (wpb > 1 && smem_for(wpb) > (size_t)lds_max) --wpb;
     REGC_CHECK(smem_for(wpb) <= (size_t)lds_max, REGC_EUNSUPPORTED,
                "one walker needs %zu bytes of LDS, the device allows %d", smem_for(wpb), lds_max);

@@ -171,7 +171,7 @@ __host__ __device__ inline LdsLayout lds_layout(int max_slab_len, int gas_stride
     size_t off = 0;
     L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
     L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
-    L.xch = off;     off = lds_round(off + (size_t)walkers * 8 * 8);
+    L.xch = off;     off = lds_round(off + (size_t)walkers * 16 * 8);
     L.gas = off;     off = lds_round(off + (size_t)walkers * gas_stride * r4);
     L.queue = off;   off = lds_round(off + (size_t)queue_waves * (2 * gas_stride + 2 * max_slab_scan) * real_size);
     L.total = off;
@@ -199,7 +199,7 @@ __host__ __device__ inline BatchLds batch_lds(int max_slab_len, int gas_stride, 
 
 // launchers (defined in the .hip files)
 // batch: 2 or 4 runs the batched-trial kernel (one wave per walker), else the one-trial
-// kernel with `split` waves per walker and `cull`
+// kernel with `split` (1, 2 or 4) waves per walker and `cull`
 hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
                             size_t smem, hipStream_t s);
 hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,

@@ -25,11 +25,11 @@
 //
 // Launch variants (template parameters):
 //   SPLIT = 1: one wavefront per walker, several walkers per workgroup;
-//   SPLIT = 2: one walker per workgroup of two wavefronts; each takes half of the
-//              candidates, the two partial sums meet in LDS behind a barrier, both
-//              waves then take the same decision and both write an accepted update
-//              into the walker's LDS copy.  Two waves per SIMD hide latency when
-//              walkers are as few as SIMDs.
+//   SPLIT = 2, 4: one walker per workgroup of SPLIT wavefronts; each takes every
+//              SPLIT-th block of candidates, the partial sums meet in LDS behind a
+//              barrier (added in wave order), every wave then takes the same decision
+//              and writes an accepted update into the walker's LDS copy.  Several
+//              waves per SIMD hide latency when walkers are as few as SIMDs.
 //   CULL  = false: every candidate pair is evaluated in full;
 //   CULL  = true : a first pass computes squared distances only and queues the pairs
 //              inside the cutoff in LDS (compacted across the wave); the LJ terms are
@@ -51,8 +51,19 @@
 namespace regc {
 namespace REGC_PREC {
 
+// Waves per SIMD the one-trial kernel's register budget must allow: four in the FP32
+// build with one wave per walker (128 VGPRs, no spills), so that four walkers share
+// each SIMD (measured 2.03e9 against 1.60e9 trial moves/s at 4096 walkers on 256 CUs);
+// with several waves per walker, and in the FP64 build, the registers stay as they are
+// (a 128-register budget spills there and was measured slower).
+#if defined(REGC_FP64)
+constexpr int kSweepWavesPerSimd = 1;
+#else
+constexpr int kSweepWavesPerSimd = 4;
+#endif
+
 template <int SPLIT, bool CULL>
-__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSweepWavesPerSimd : 1) sweep_kernel(SweepArgs a)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int wave = threadIdx.x / kWave;
@@ -69,7 +80,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                                    CULL ? waves : 0, (int)sizeof(Real));
     Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
     double *lnk = reinterpret_cast<double *>(smem + L.lnk);
-    double *xch = reinterpret_cast<double *>(smem + L.xch) + slot * 8;     // [parity][part][value, core]
+    double *xch = reinterpret_cast<double *>(smem + L.xch) + slot * 16;    // [parity][part][value, core]
     Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)slot * a.gas_stride;
     Real *qgas = reinterpret_cast<Real *>(smem + L.queue) + (size_t)wave * (2 * a.gas_stride + 2 * a.max_slab_scan);
     Real *qslab = qgas + 2 * a.gas_stride;
@@ -88,7 +99,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     }
     for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
     __syncthreads();
-    if (slot >= nw) return;    // (SPLIT == 2 blocks always hold one walker)
+    if (slot >= nw) return;    // (blocks with SPLIT > 1 always hold one walker)
 
     const int w = a.block_w0[blk] + slot;
     const int n_max = C.n_max;
@@ -212,16 +223,22 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                                 de = (double)pd;
                             } else {
                                 // alternate slots: exchange k+2 reuses the slot of exchange k
-                                // only after both waves passed the barrier of exchange k+1
-                                double *mine = xch + ((xcount & 1) * 2 + part) * 2;
+                                // only after every wave passed the barrier of exchange k+1
+                                double *mine = xch + ((xcount & 1) * SPLIT + part) * 2;
                                 if (lane == 0) {
                                     mine[0] = (double)pd;
                                     mine[1] = core ? 1.0 : 0.0;
                                 }
                                 __syncthreads();
-                                const double *x0 = xch + (xcount & 1) * 4;
-                                de = x0[0] + x0[2];
-                                core = (x0[1] + x0[3]) != 0.0;
+                                const double *x0 = xch + (xcount & 1) * SPLIT * 2;
+                                de = x0[0];
+                                double cf = x0[1];
+#pragma unroll
+                                for (int q = 1; q < SPLIT; ++q) {
+                                    de += x0[2 * q];
+                                    cf += x0[2 * q + 1];
+                                }
+                                core = cf != 0.0;
                                 ++xcount;
                             }
                             const uint64_t mult = kind == 0 ? 2 : 1;
@@ -243,7 +260,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
                             // ideal gas has no exchange: its barrier here keeps the other
                             // wave's read of this trial's particle before the writes, and the
                             // one below keeps the writes before the next trial's reads.
-                            if (SPLIT == 2 && ideal) __syncthreads();
+                            if (SPLIT > 1 && ideal) __syncthreads();
                             if (kind == 0) {
                                 if (lane == 0) {
                                     Real4 v; v.x = qx; v.y = qy; v.z = qz; v.w = 0;
@@ -276,11 +293,13 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
             if (SPLIT == 1) {
                 e = pe;
             } else {
-                double *mine = xch + ((xcount & 1) * 2 + part) * 2;
+                double *mine = xch + ((xcount & 1) * SPLIT + part) * 2;
                 if (lane == 0) mine[0] = pe;
                 __syncthreads();
-                const double *x0 = xch + (xcount & 1) * 4;
-                e = x0[0] + x0[2];
+                const double *x0 = xch + (xcount & 1) * SPLIT * 2;
+                e = x0[0];
+#pragma unroll
+                for (int q = 1; q < SPLIT; ++q) e += x0[2 * q];
                 ++xcount;
             }
         }
@@ -298,7 +317,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_kernel(Swee
     }
 
     // ---- write back ----
-    if (SPLIT == 2) __syncthreads();
+    if (SPLIT > 1) __syncthreads();
     {
         double *dst = a.xyz + (size_t)w * a.xyz_stride * 3;
         for (int k = part * kWave + lane; k < n; k += SPLIT * kWave) {
@@ -1174,6 +1193,9 @@ hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, i
     } else if (batch == 2) {
         if (a.count_pairs) hipLaunchKernelGGL((batch_kernel<2, true>), grid, block, smem, s, a);
         else hipLaunchKernelGGL((batch_kernel<2, false>), grid, block, smem, s, a);
+    } else if (split == 4) {
+        if (cull) hipLaunchKernelGGL((sweep_kernel<4, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<4, false>), grid, block, smem, s, a);
     } else if (split == 2) {
         if (cull) hipLaunchKernelGGL((sweep_kernel<2, true>), grid, block, smem, s, a);
         else hipLaunchKernelGGL((sweep_kernel<2, false>), grid, block, smem, s, a);

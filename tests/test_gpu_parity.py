@@ -108,7 +108,8 @@ def test_fp64_trajectories_irregular_slab_rectangular_box():
     assert wk["n"].max() > 10
 
 
-@pytest.mark.parametrize("wpb,spl,split,cull", [(1, 1, 1, 0), (4, 3, 1, 1), (8, 0, 1, 0), (1, 0, 2, 0), (1, 7, 2, 1)])
+@pytest.mark.parametrize("wpb,spl,split,cull", [(1, 1, 1, 0), (4, 3, 1, 1), (8, 0, 1, 0), (1, 0, 2, 0), (1, 7, 2, 1),
+                                             (1, 0, 4, 0), (1, 3, 4, 1)])
 def test_fp64_invariant_to_launch_shape(wpb, spl, split, cull):
     """Walkers per block, sweeps per launch, waves per walker and the cull pass
     change nothing but summation order: trajectories stay identical."""
@@ -146,12 +147,14 @@ def test_fp64_batched_trials_ideal_gas_and_caps():
     _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=300).replace(swap_every=0), 300, batch_trials=2)
 
 
-@pytest.mark.parametrize("split,cull", [(1, 0), (2, 0), (1, 1), (2, 1)])
-def test_fp64_dense_walkers(split, cull):
-    """N well above 64 (a wave's width), binned 8x8x3 slab: both waves of a split
-    walker own gas candidates."""
+@pytest.mark.parametrize("split,cull,cell", [(1, 0, 0.0), (2, 0, 0.0), (1, 1, 0.0), (2, 1, 0.0), (4, 0, 0.0),
+                                             (4, 1, 0.0), (1, 0, 1.25), (2, 0, 1.25)])
+def test_fp64_dense_walkers(split, cull, cell):
+    """N well above 64 (a wave's width), binned 8x8x3 slab (columns of the smallest
+    width, or 1.25 times it: 3 x 3 columns): every wave of a split walker owns gas
+    candidates."""
     w = W.config2(60).replace(t=np.array([0.9, 1.6]), mu=np.array([-3.0, -2.0]), n_max=160, sample_every=5)
-    _, wk = _fp64_trajectory(w, 60, split=split, cull=cull)
+    _, wk = _fp64_trajectory(w, 60, split=split, cull=cull, slab_cell=cell)
     assert wk["n"].max() > 100
 
 
@@ -172,6 +175,7 @@ def test_fp64_edge_cases():
     # ideal gas mode, also with two waves per walker in the one-trial kernel
     _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300)
     _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300, split=2)
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300, split=4)
 
 
 def _batch_classes():
