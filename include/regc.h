@@ -165,7 +165,8 @@ typedef struct {
  *                  oracle's), -1: never.
  *  batch_trials    sweep schedule without the learned proposal: 2 or 4 evaluates that
  *                  many consecutive trials of a walker at once (one wavefront per walker,
- *                  64 / batch_trials lanes per trial) on the configuration at the start
+ *                  64 / batch_trials lanes per trial, or with split equal to batch_trials
+ *                  one wavefront per trial) on the configuration at the start
  *                  of the batch, then decides them in order, correcting each trial's
  *                  energy change by its pair terms with the moves accepted before it in
  *                  the batch and leaving to the next batch a trial whose particle index

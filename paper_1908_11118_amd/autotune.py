@@ -93,19 +93,22 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
             "sweeps_per_launch": 0, "graph_intervals": 0}
     best_rate = trial(best)
     spl = sorted({s for s in (interval // 2, max(1, interval // 5)) if 0 < s < interval})
-    space = [("walkers_per_block", [1, 2, 4, 8]), ("split", [1, 2, 4]), ("batch_trials", [2, 4]),
+    # batched trials: (trials per batch, waves per walker) -- one wave per walker, or one
+    # wave per trial
+    space = [("walkers_per_block", [1, 2, 4, 8]), ("split", [1, 2, 4]), ("batch", [(2, 1), (4, 1), (2, 2), (4, 4)]),
              ("cull", [1]), ("slab_bins", [-1]), ("slab_cell", [1.25, 1.5]), ("sweeps_per_launch", spl),
              ("graph_intervals", [4, 10])]
     for name, values in space:
         for v in values:
             cand = dict(best)
-            cand[name] = v
-            if cand["split"] > 1 or cand["batch_trials"] > 1:
-                cand["walkers_per_block"] = 1 if cand["split"] > 1 else cand["walkers_per_block"]
-            if name == "batch_trials":
-                cand["split"], cand["cull"] = 1, 0
+            if name == "batch":
+                cand["batch_trials"], cand["split"], cand["cull"] = v[0], v[1], 0
+                if v[1] > 1:
+                    cand["walkers_per_block"] = 1
+            else:
+                cand[name] = v
             if name == "split" and v > 1:
-                cand["batch_trials"] = 1
+                cand["batch_trials"], cand["walkers_per_block"] = 1, 1
             rate = trial(cand)
             if rate > best_rate:
                 best, best_rate = cand, rate

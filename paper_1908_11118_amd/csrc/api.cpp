@@ -350,12 +350,14 @@ static int ctx_alloc_and_init(regc_ctx *c)
     // one trial at a time unless batched trials are requested (measured slower at 1024
     // walkers on 256 CUs: one wave per SIMD leaves the batch's serial decisions exposed)
     const int batch = o.schedule != 0 ? 1 : (o.batch_trials > 0 ? o.batch_trials : 1);
-    int split = batch > 1 ? 1
+    // batched trials with split equal to the batch: one wave per trial (the multi-wave form)
+    int split = batch > 1 ? (o.split == batch ? batch : 1)
                           : (o.split > 0 ? o.split
                                          : ((o.schedule == 0 && o.walkers_per_block == 0 && W <= 4 * n_cu &&
                                              c->pot.mode != REGC_MODE_IDEAL) ? 2 : 1));
     const bool cull = batch == 1 && o.cull > 0;
     auto smem_for = [&](int wpb) {
+        if (batch > 1 && split == batch) return mw_lds(max_slab_len, nmax, batch, real).total;
         if (batch > 1) return batch_lds(max_slab_len, nmax, wpb, real).total;
         return lds_layout(max_slab_len, nmax, c->max_slab_scan, wpb, cull ? wpb * split : 0, real).total;
     };

@@ -197,9 +197,35 @@ __host__ __device__ inline BatchLds batch_lds(int max_slab_len, int gas_stride, 
     return L;
 }
 
+// LDS carve of the multi-wave batched-trial kernel (one walker per workgroup of B
+// waves): class slab, ln k table, every wave's own copy of the gas coordinates and of
+// each particle's energy with the frozen slab, and the double-buffered records the
+// waves exchange after each pass (per wave: 8-byte outcome masks, 8 scenario energy
+// changes, the slab energy at the new position).
+struct MwLds {
+    size_t slab, lnk, gas, eslab, rec, total;
+};
+
+constexpr int kMwRecDoubles = 10;
+
+__host__ __device__ inline MwLds mw_lds(int max_slab_len, int gas_stride, int waves, int real_size)
+{
+    MwLds L;
+    const size_t r4 = 4 * (size_t)real_size;
+    size_t off = 0;
+    L.slab = off;    off = lds_round(off + (size_t)max_slab_len * r4);
+    L.lnk = off;     off = lds_round(off + (size_t)(gas_stride + 2) * 8);
+    L.gas = off;     off = lds_round(off + (size_t)waves * gas_stride * r4);
+    L.eslab = off;   off = lds_round(off + (size_t)waves * gas_stride * real_size);
+    L.rec = off;     off = lds_round(off + (size_t)2 * waves * kMwRecDoubles * 8);
+    L.total = off;
+    return L;
+}
+
 // launchers (defined in the .hip files)
-// batch: 2 or 4 runs the batched-trial kernel (one wave per walker), else the one-trial
-// kernel with `split` (1, 2 or 4) waves per walker and `cull`
+// batch: 2 or 4 runs a batched-trial kernel -- one wave per walker, or with split equal
+// to batch one workgroup of `batch` waves per walker, one trial per wave -- else the
+// one-trial kernel with `split` (1, 2 or 4) waves per walker and `cull`
 hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
                             size_t smem, hipStream_t s);
 hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,

@@ -726,6 +726,406 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) batch_kernel(Swee
     }
 }
 
+// ---- batched trials, one wave per trial ---------------------------------------------
+// The same decisions as batch_kernel (every trial of a batch evaluated on the
+// configuration X0 at the start of the batch, corrected by its pair terms with the
+// moves accepted before it, redone in the next pass when an earlier accepted move
+// changed what it proposes or assumed), with the B trials of a batch on B waves of one
+// workgroup, 64 lanes each.  With one walker per SIMD the single-wave form leaves each
+// SIMD one instruction stream; here each SIMD runs one wave of each of four walkers.
+// Wave h evaluates trial t + h (its energy on X0, the pair terms with the positions of
+// trials 0 .. h-1, and its outcome under each of the 2^h accept patterns of those
+// trials, lane s taking pattern s), writes the outcome masks and the scenario energy
+// changes into a double-buffered LDS record, and after one barrier every wave walks the
+// same path through the records and applies the accepted moves to its own copy of the
+// coordinates and slab energies: the copies stay identical, so no second barrier is
+// needed before the next pass reads them.
+template <bool NEW, bool OLD, bool COUNT>
+__device__ __forceinline__ void mw_terms(const Real4 *gas, int n, int ex, const SlabView &sv, const Box &b,
+                                         const Pair &gg, const Pair &gs, int lane, bool slab_new, const Real4 &P,
+                                         const Real4 &Q, Real &acc, Real &vs, bool &core, uint32_t &use)
+{
+    // gas: two candidates per lane per step, both loads issued first
+    for (int j0 = 0; j0 < n; j0 += 2 * kWave) {
+        const int ja = j0 + lane, jb = ja + kWave;
+        const Real4 ga = gas[ja < n ? ja : 0];
+        const Real4 gb = gas[jb < n ? jb : 0];
+        const bool va = ja < n && ja != ex, vb = jb < n && jb != ex;
+        if (NEW) {
+            const Real ra = dist2(b, P.x, P.y, P.z, ga), rb = dist2(b, P.x, P.y, P.z, gb);
+            core |= (va && ra < gg.hc2) || (vb && rb < gg.hc2);
+            if (COUNT) use += (uint32_t)(va && ra < gg.rc2) + (uint32_t)(vb && rb < gg.rc2);
+            acc += va ? lj(ra, gg) : Real(0);
+            acc += vb ? lj(rb, gg) : Real(0);
+        }
+        if (OLD) {
+            const Real ra = dist2(b, Q.x, Q.y, Q.z, ga), rb = dist2(b, Q.x, Q.y, Q.z, gb);
+            if (COUNT) use += (uint32_t)(va && ra < gg.rc2) + (uint32_t)(vb && rb < gg.rc2);
+            acc -= va ? lj(ra, gg) : Real(0);
+            acc -= vb ? lj(rb, gg) : Real(0);
+        }
+    }
+    // slab at the new position only (the old one's is cached)
+    if (NEW && slab_new) {
+        const int total = sv.bins ? 9 * sv.cap : sv.len;
+        int cx = 0, cy = 0;
+        if (sv.bins) column_of(sv, P.x, P.y, cx, cy);
+        for (int k0 = 0; k0 < total; k0 += 2 * kWave) {
+            const int ka = k0 + lane, kb = ka + kWave;
+            const bool va = ka < total, vb = kb < total;
+            const Real4 sa = sv.atoms[sv.bins ? block_entry(sv, cx, cy, va ? ka : 0) : (va ? ka : 0)];
+            const Real4 sb = sv.atoms[sv.bins ? block_entry(sv, cx, cy, vb ? kb : 0) : (vb ? kb : 0)];
+            const Real ra = dist2(b, P.x, P.y, P.z, sa), rb = dist2(b, P.x, P.y, P.z, sb);
+            core |= (va && ra < gs.hc2) || (vb && rb < gs.hc2);
+            if (COUNT) use += (uint32_t)(va && ra < gs.rc2) + (uint32_t)(vb && rb < gs.rc2);
+            vs += va ? lj(ra, gs) : Real(0);
+            vs += vb ? lj(rb, gs) : Real(0);
+        }
+    }
+}
+
+template <int B, bool COUNT>
+__global__ void __launch_bounds__(kWave * B, kSweepWavesPerSimd) mw_kernel(SweepArgs a)
+{
+    static_assert(B >= 2 && B <= 4, "2 to 4 waves");
+    extern __shared__ __align__(32) unsigned char smem[];
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);      // this wave's trial in a batch
+    const int lane = threadIdx.x % kWave;
+    const int blk = blockIdx.x;
+    const int cid = a.block_class[blk];
+    const ClassDev &C = a.cls[cid];
+
+    const MwLds L = mw_lds(a.max_slab_len, a.gas_stride, B, (int)sizeof(Real));
+    Real4 *slab = reinterpret_cast<Real4 *>(smem + L.slab);
+    double *lnk = reinterpret_cast<double *>(smem + L.lnk);
+    Real4 *gas = reinterpret_cast<Real4 *>(smem + L.gas) + (size_t)h * a.gas_stride;
+    Real *eslab = reinterpret_cast<Real *>(smem + L.eslab) + (size_t)h * a.gas_stride;
+    double *rec = reinterpret_cast<double *>(smem + L.rec);     // [parity][wave][kMwRecDoubles]
+
+    const int slab_len = C.slab_len;
+    for (int k = threadIdx.x; k < slab_len; k += blockDim.x) {
+#if defined(REGC_FP64)
+        const double *src = a.slab4 + 4 * (size_t)(C.slab_off + k);
+#else
+        const float *src = a.slab4f + 4 * (size_t)(C.slab_off + k);
+#endif
+        Real4 v;
+        v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = 0;
+        slab[k] = v;
+    }
+    for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
+    __syncthreads();
+
+    const int w = a.block_w0[blk];
+    const int n_max = C.n_max;
+    const int K = C.trials;
+    int n = a.n[w];
+    double e = a.e[w];
+    const int label = a.label[w];
+    const int sg = C.state_off + label;
+    const double beta = a.beta[sg];
+    const double lnz = a.lnz[sg];
+
+    Box b;
+    b.lx = in_vgpr((Real)C.lx); b.ly = in_vgpr((Real)C.ly); b.hx = in_vgpr((Real)C.half_lx);
+    b.hy = in_vgpr((Real)C.half_ly); b.ix = in_vgpr((Real)C.inv_lx); b.iy = in_vgpr((Real)C.inv_ly);
+    Pair gg, gs;
+    gg.sig2 = in_vgpr((Real)a.pot.sig2_gg); gg.eps4 = in_vgpr((Real)a.pot.eps4_gg);
+    gg.shift = in_vgpr((Real)a.pot.shift_gg); gg.rc2 = in_vgpr((Real)a.pot.rc2); gg.hc2 = in_vgpr((Real)a.pot.hc2_gg);
+    gs.sig2 = in_vgpr((Real)a.pot.sig2_gs); gs.eps4 = in_vgpr((Real)a.pot.eps4_gs);
+    gs.shift = in_vgpr((Real)a.pot.shift_gs); gs.rc2 = gg.rc2; gs.hc2 = in_vgpr((Real)a.pot.hc2_gs);
+    const bool ideal = a.pot.ideal != 0;
+    SlabView sv;
+    sv.atoms = slab; sv.len = slab_len; sv.bins = C.bins;
+    sv.ncx = C.ncx; sv.ncy = C.ncy; sv.cap = C.cap;
+    sv.inv_cap = in_vgpr(C.bins ? 1.0f / (float)C.cap : 0.f);
+    sv.inv_cw_x = in_vgpr((Real)C.inv_cw_x); sv.inv_cw_y = in_vgpr((Real)C.inv_cw_y);
+    sv.top_plus_rc = in_vgpr((Real)(C.slab_top + sqrt(a.pot.rc2)));
+    const double lx = in_vgpr(C.lx), ly = in_vgpr(C.ly), zlo = in_vgpr(C.zlo), zhi = in_vgpr(C.zhi);
+    const double H = in_vgpr(C.zhi - C.zlo);
+    const double md = in_vgpr(a.max_disp);
+    const double tinv = in_vgpr(1.0 / beta);
+    const double lnzv_v = in_vgpr(lnz + C.lnv);
+    const int slab_scan = C.bins ? 9 * C.cap : slab_len;
+    Real4 far;                      // a position beyond the cutoff of every atom: absent P or Q
+    far.x = 0; far.y = 0; far.z = (Real)1.0e4; far.w = 0;
+
+    // this wave's copy of the coordinates and of each particle's slab energy (computed
+    // by every wave with the same arithmetic, so the copies are identical)
+    {
+        const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            Real4 v;
+            v.x = (Real)src[3 * k]; v.y = (Real)src[3 * k + 1]; v.z = (Real)src[3 * k + 2]; v.w = 0;
+            gas[k] = v;
+            Real es = 0;
+            if (!ideal && v.z < sv.top_plus_rc) {
+                int cx = 0, cy = 0;
+                if (sv.bins) column_of_lanes(sv, v.x, v.y, cx, cy);
+                for (int q = 0; q < slab_scan; ++q)
+                    es += lj(dist2(b, v.x, v.y, v.z, sv.atoms[sv.bins ? block_entry(sv, cx, cy, q) : q]), gs);
+            }
+            eslab[k] = es;
+        }
+    }
+    wave_sync();
+
+    uint32_t stat = 0;     // wave 0: lane k < kNStat holds counter k
+    uint32_t useful = 0;
+    uint64_t cand = 0;
+    int parity = 0;
+
+    const int64_t sweep_first = a.clock ? a.clock[0] + a.sweep0 : a.sweep0;
+    for (int it = 0; it < a.n_sweeps; ++it) {
+        const int64_t sweep = sweep_first + it;
+        const bool tracing = a.trace_bits != nullptr && (sweep - a.trace_sweep0) < a.trace_cap &&
+                             sweep >= a.trace_sweep0;
+        for (int t0 = 0; t0 < K; t0 += 32) {
+            const uint4 R = philox4x32_10(
+                make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)sweep, (uint32_t)w, (uint32_t)(lane & 1)),
+                a.key0, a.key1);
+            const double f0 = uniform_open(R.z), f1 = uniform_open(R.w), f2 = uniform_open(R.x);
+            const double f3 = log(uniform53(R.y, R.z));
+            const int tn = K - t0 < 32 ? K - t0 : 32;
+            uint32_t bits = 0;
+            for (int t = 0; t < tn;) {
+                const int nb = tn - t < B ? tn - t : B;
+                const int n0 = n;
+                // ---- every trial of the batch, lane g % B taking trial t + g ----
+                const int g = lane % B;
+                const bool act = g < nb;
+                const int src = 2 * (t + (act ? g : 0));
+                const uint32_t A0 = (uint32_t)__shfl((int)R.x, src);
+                const uint32_t A1 = (uint32_t)__shfl((int)R.y, src);
+                const double ux = __shfl(f0, src), uy = __shfl(f1, src);
+                const double uz = __shfl(f2, src + 1), lnU = __shfl(f3, src + 1);
+                const int kind = (uint64_t)A0 < a.th_disp ? 0 : ((uint64_t)A0 < a.th_ins ? 1 : 2);
+                const bool skip = kind == 1 ? n0 >= n_max : n0 == 0;
+                const int i = kind == 1 || skip ? 0 : (int)(((uint64_t)A1 * (uint64_t)n0) >> 32);
+                const Real4 o = gas[i];
+                const Real eo = kind == 1 || skip ? Real(0) : eslab[i];
+                double dx = (double)o.x + md * (2.0 * ux - 1.0);
+                double dy = (double)o.y + md * (2.0 * uy - 1.0);
+                const double dz = (double)o.z + md * (2.0 * uz - 1.0);
+                dx = dx < 0.0 ? dx + lx : (dx >= lx ? dx - lx : dx);
+                dy = dy < 0.0 ? dy + ly : (dy >= ly ? dy - ly : dy);
+                const double px = kind == 0 ? dx : lx * ux;
+                const double py = kind == 0 ? dy : ly * uy;
+                const double pz = kind == 0 ? dz : zlo + H * uz;
+                const bool wall = (kind == 0) & !skip & ((dz < zlo) | (dz > zhi));
+                const double ln0 = lnk[n0], ln1 = lnk[n0 + 1];
+                const double c = kind == 0 ? 0.0 : (kind == 1 ? lnzv_v - ln1 : ln0 - lnzv_v);
+                const double thr = (c - lnU) * tinv;              // accept iff dE <= thr
+                const bool live = act && !skip && !wall;
+                const bool compute = live && !ideal;
+                Real4 P = far, Q = far;
+                if (live && kind != 2) { P.x = (Real)px; P.y = (Real)py; P.z = (Real)pz; }
+                if (live && kind != 1) { Q.x = o.x; Q.y = o.y; Q.z = o.z; }
+                const uint32_t packed = (uint32_t)kind | (skip ? 4u : 0u) | (wall ? 8u : 0u) |
+                                        (compute ? 16u : 0u) | ((compute && kind != 2 && P.z < sv.top_plus_rc) ? 32u : 0u) |
+                                        ((uint32_t)i << 8);
+                uint32_t pk[B];
+#pragma unroll
+                for (int q = 0; q < B; ++q) pk[q] = q < nb ? (uint32_t)__builtin_amdgcn_readlane((int)packed, q) : 0u;
+
+                // ---- this wave's trial t + h on X0 ----
+                const bool hact = h < nb;
+                const uint32_t ph = hact ? (uint32_t)__builtin_amdgcn_readlane((int)packed, h) : 0u;
+                const int hkind = (int)(ph & 3u), hi = (int)(ph >> 8);
+                const bool hskip = (ph & 4u) != 0, hwall = (ph & 8u) != 0, hcompute = (ph & 16u) != 0;
+                const bool hslab = (ph & 32u) != 0;
+                Real4 Ph, Qh;
+                Ph.x = bcast_real(P.x, h); Ph.y = bcast_real(P.y, h); Ph.z = bcast_real(P.z, h); Ph.w = 0;
+                Qh.x = bcast_real(Q.x, h); Qh.y = bcast_real(Q.y, h); Qh.z = bcast_real(Q.z, h); Qh.w = 0;
+                const double hthr = bcast(thr, h), hlnU = bcast(lnU, h);
+                const uint32_t hA1 = bcast(A1, h);
+                const Real heo = bcast_real(eo, h);
+                Real acc = 0, vs = 0;
+                bool core = false;
+                uint32_t use = 0;
+                if (hcompute) {
+                    const int ex = hkind == 1 ? -1 : hi;
+                    if (hkind == 0)
+                        mw_terms<true, true, COUNT>(gas, n0, ex, sv, b, gg, gs, lane, hslab, Ph, Qh, acc, vs, core, use);
+                    else if (hkind == 1)
+                        mw_terms<true, false, COUNT>(gas, n0, ex, sv, b, gg, gs, lane, hslab, Ph, Qh, acc, vs, core, use);
+                    else
+                        mw_terms<false, true, COUNT>(gas, n0, ex, sv, b, gg, gs, lane, false, Ph, Qh, acc, vs, core, use);
+                }
+                // pair terms with the positions of the earlier trials: lane 4 q + k holds
+                // term k with trial q, the quad's sum
+                // [phi(P_h-P_q) - phi(Q_h-P_q)] - [phi(P_h-Q_q) - phi(Q_h-Q_q)] in all four
+                Real cterm = 0;
+                bool ccore = false;
+                if (!ideal && h > 0) {
+                    const int q = lane >> 2, k = lane & 3;
+                    const int from = q < B ? q : 0;
+                    const Real xp = __shfl(P.x, from), yp = __shfl(P.y, from), zp = __shfl(P.z, from);
+                    const Real xq = __shfl(Q.x, from), yq = __shfl(Q.y, from), zq = __shfl(Q.z, from);
+                    Real4 X;
+                    X.x = k < 2 ? xp : xq; X.y = k < 2 ? yp : yq; X.z = k < 2 ? zp : zq; X.w = 0;
+                    const Real4 Y = (k & 1) == 0 ? Ph : Qh;
+                    const Real zfar = (Real)1.0e3;
+                    const bool valid = hact && q < h && X.z < zfar && Y.z < zfar;
+                    const Real r2 = dist2(b, Y.x, Y.y, Y.z, X);
+                    const Real term = valid ? lj(r2, gg) : Real(0);
+                    cterm = quad_sum((k == 1 || k == 2) ? -term : term);
+                    ccore = valid && k == 0 && r2 < gg.hc2;
+                }
+                const Real vP = wave_sum(vs);
+                const Real sde = wave_sum(acc) + vP - heo;
+                const bool gcore = __ballot(core) != 0ull;
+                const uint64_t ccore_lanes = __ballot(ccore);
+
+                // ---- trial h under each accept pattern s (lane s < 2^h) of trials 0 .. h-1 ----
+                const uint32_t s = (uint32_t)lane;
+                int ncur = n0;
+                uint64_t tmask = 0;          // changed slots, as bits of (slot mod 64)
+                double de = (double)sde;
+                bool ccr = false;
+#pragma unroll
+                for (int q = 0; q + 1 < B; ++q) {
+                    const bool take = (q < h) & (((s >> q) & 1u) != 0);
+                    const int kg = (int)(pk[q] & 3u), ig = (int)(pk[q] >> 8);
+                    const uint64_t bi = kg != 1 ? 1ull << (ig & 63) : 0ull;
+                    const uint64_t bn = kg != 0 ? 1ull << ((kg == 1 ? ncur : ncur - 1) & 63) : 0ull;
+                    tmask |= take ? (bi | bn) : 0ull;
+                    ncur += take ? (kg == 1 ? 1 : (kg == 2 ? -1 : 0)) : 0;
+                    de += take ? (double)bcast_real(cterm, 4 * q) : 0.0;
+                    ccr |= take & (((ccore_lanes >> (4 * q)) & 1ull) != 0);
+                }
+                const int nq = ncur < 0 ? 0 : (ncur > n_max ? n_max : ncur);
+                const double lq = lnk[hkind == 1 ? nq + 1 : nq];
+                const bool ichg = ((uint32_t)(((uint64_t)hA1 * (uint64_t)(uint32_t)nq) >> 32) != (uint32_t)hi) |
+                                  (((tmask >> (hi & 63)) & 1ull) != 0);
+                const bool rk = hkind == 1 ? hskip & (ncur < n_max) : (n0 == 0 ? ncur > 0 : (ncur > 0) & ichg);
+                const bool redo = (s != 0) & ((hcompute & gcore) | rk);
+                const bool capemp = hkind == 1 ? ncur >= n_max : ncur == 0;
+                const double th = (hkind != 0 && ncur != n0)
+                                      ? ((hkind == 1 ? lnzv_v - lq : lq - lnzv_v) - hlnU) * tinv
+                                      : hthr;
+                const bool cr = hcompute & (hkind != 2) & (gcore | ccr);
+                de = hcompute ? de : 0.0;
+                const bool scen = hact & (s < (1u << h));
+                const bool ok = scen & !redo & !capemp & !hwall & !cr & (de <= th);
+                const uint64_t word = (__ballot(scen && redo) & 0xFFull) | ((__ballot(ok) & 0xFFull) << 8) |
+                                      ((__ballot(scen && !redo && capemp) & 0xFFull) << 16) |
+                                      ((__ballot(scen && !redo && !capemp && hwall) & 0xFFull) << 24) |
+                                      ((__ballot(scen && !redo && !capemp && !hwall && cr) & 0xFFull) << 32);
+                double *mine = rec + (size_t)(parity * B + h) * kMwRecDoubles;
+                if (lane < 8) mine[lane] = de;
+                if (lane == 8) mine[8] = (double)vP;
+                if (lane == 9) mine[9] = __longlong_as_double((long long)word);
+                __syncthreads();
+
+                // ---- the path, the same in every wave ----
+                const double *recs = rec + (size_t)parity * B * kMwRecDoubles;
+                int nres = 0;
+                uint32_t path = 0;
+                int nw = n0;
+                for (int q = 0; q < nb; ++q) {
+                    // (the same value in every lane: read back as a scalar)
+                    const long long wl = __double_as_longlong(recs[q * kMwRecDoubles + 9]);
+                    const uint64_t wq = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(wl >> 32)) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readfirstlane((int)wl);
+                    const int L0 = (int)path;
+                    if ((wq >> L0) & 1ull) break;
+                    ++nres;
+                    const int kd = (int)(pk[q] & 3u);
+                    int ev = -1;
+                    if ((wq >> (16 + L0)) & 1ull) ev = kd == 1 ? 6 : 7;
+                    else if ((wq >> (24 + L0)) & 1ull) ev = 8;
+                    else if ((wq >> (32 + L0)) & 1ull) ev = 9;
+                    else if ((wq >> (8 + L0)) & 1ull) ev = 2 * kd + 1;
+                    if (h == 0) stat += (lane == 2 * kd) + (lane == ev);
+                    if ((pk[q] & 16u) && ev != 6 && ev != 7 && ev != 8)
+                        cand += (uint64_t)(kd == 0 ? 2 : 1) * (uint64_t)(kd == 1 ? nw : nw - 1) +
+                                (uint64_t)((pk[q] & 32u) ? slab_scan : 0);
+                    if (ev == 2 * kd + 1) {
+                        path |= 1u << q;
+                        nw += kd == 1 ? 1 : (kd == 2 ? -1 : 0);
+                    }
+                }
+                if (path) {
+                    bits |= path << t;
+                    for (uint32_t m = path; m; m &= m - 1) {
+                        const int q = __builtin_ctz(m);
+                        const int L0 = (int)(path & ((1u << q) - 1u));
+                        const int kd = (int)(pk[q] & 3u), is = (int)(pk[q] >> 8);
+                        e = in_vgpr(e + recs[q * kMwRecDoubles + L0]);
+                        const Real vq = (Real)recs[q * kMwRecDoubles + 8];
+                        Real4 Pq;
+                        Pq.x = bcast_real(P.x, q); Pq.y = bcast_real(P.y, q); Pq.z = bcast_real(P.z, q); Pq.w = 0;
+                        // this wave's copy, in program order (a wave's LDS operations complete in order)
+                        if (kd == 0) {
+                            if (lane == 0) {
+                                gas[is] = Pq;
+                                eslab[is] = vq;
+                            }
+                        } else if (kd == 1) {
+                            if (lane == 0) {
+                                gas[n] = Pq;
+                                eslab[n] = vq;
+                            }
+                            n += 1;
+                        } else {
+                            if (lane == 0 && is != n - 1) {
+                                gas[is] = gas[n - 1];
+                                eslab[is] = eslab[n - 1];
+                            }
+                            n -= 1;
+                        }
+                    }
+                    wave_sync();
+                }
+                if (COUNT) useful += h < nres ? use : 0u;
+                t += nres;
+                parity ^= 1;
+            }
+            if (tracing && h == 0 && lane == 0)
+                a.trace_bits[((size_t)(sweep - a.trace_sweep0) * a.n_walkers + w) * a.trace_words + (t0 >> 5)] = bits;
+        }
+        // ---- end of sweep: running energy resynchronised (every wave, its own copy), records ----
+        if (a.resync_every > 0 && (sweep + 1) % a.resync_every == 0 && !ideal)
+            e = full_energy_part<1>(gas, n, sv, b, gg, gs, lane, 0);
+        if (h == 0 && lane == 0) {
+            if (tracing) a.trace_n[(size_t)(sweep - a.trace_sweep0) * a.n_walkers + w] = n;
+            if (a.sample_every > 0 && (sweep + 1) % a.sample_every == 0) {
+                const int64_t r = (sweep + 1) / a.sample_every - 1 - a.rec_base;
+                const size_t idx = (size_t)r * a.n_walkers + w;
+                a.samp_e[idx] = e;
+                a.samp_n[idx] = n;
+                a.samp_s[idx] = label;
+                atomicAdd(a.hist + (size_t)sg * a.hist_stride + n, 1ull);
+            }
+        }
+    }
+
+    if (h == 0) {
+        double *dst = a.xyz + (size_t)w * a.xyz_stride * 3;
+        for (int k = lane; k < n; k += kWave) {
+            const Real4 v = gas[k];
+            dst[3 * k] = (double)v.x; dst[3 * k + 1] = (double)v.y; dst[3 * k + 2] = (double)v.z;
+        }
+    }
+    {
+        uint32_t u = useful;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o);
+        if (lane == 0 && a.pairs) {
+            if (h == 0) atomicAdd(a.pairs, (unsigned long long)cand);
+            if (COUNT) atomicAdd(a.pairs + 1, (unsigned long long)u);
+        }
+    }
+    if (h == 0) {
+        if (lane < kNStat && stat) atomicAdd(a.stats + (size_t)sg * kNStat + lane, (unsigned long long)stat);
+        if (lane == 0) {
+            a.n[w] = n;
+            a.e[w] = e;
+        }
+    }
+}
+
 // ---- molecular dynamics for the canonical part of the REGC step ----
 // Standard normals by Box-Muller: sqrt(-2 ln u1) (cos, sin)(2 pi u2), u open uniforms.
 __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double &z0, double &z1)
@@ -1187,7 +1587,13 @@ hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, i
                         size_t smem, hipStream_t s)
 {
     const dim3 grid(n_blocks), block(kWave * waves_per_block);
-    if (batch == 4) {
+    if (batch == 4 && split == 4) {
+        if (a.count_pairs) hipLaunchKernelGGL((mw_kernel<4, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((mw_kernel<4, false>), grid, block, smem, s, a);
+    } else if (batch == 2 && split == 2) {
+        if (a.count_pairs) hipLaunchKernelGGL((mw_kernel<2, true>), grid, block, smem, s, a);
+        else hipLaunchKernelGGL((mw_kernel<2, false>), grid, block, smem, s, a);
+    } else if (batch == 4) {
         if (a.count_pairs) hipLaunchKernelGGL((batch_kernel<4, true>), grid, block, smem, s, a);
         else hipLaunchKernelGGL((batch_kernel<4, false>), grid, block, smem, s, a);
     } else if (batch == 2) {

@@ -119,20 +119,23 @@ def test_fp64_invariant_to_launch_shape(wpb, spl, split, cull):
     _fp64_trajectory(w2, 40, walkers_per_block=wpb, sweeps_per_launch=spl, split=split, cull=cull)
 
 
-@pytest.mark.parametrize("batch,wpb,spl", [(1, 0, 0), (2, 1, 3), (2, 4, 0), (4, 1, 7), (4, 8, 0)])
-def test_fp64_batched_trials_keep_the_trajectories(batch, wpb, spl):
+@pytest.mark.parametrize("batch,wpb,spl,split", [(1, 0, 0, 0), (2, 1, 3, 0), (2, 4, 0, 0), (4, 1, 7, 0),
+                                                (4, 8, 0, 0), (4, 0, 0, 4), (4, 0, 3, 4), (2, 0, 0, 2)])
+def test_fp64_batched_trials_keep_the_trajectories(batch, wpb, spl, split):
     """Trials decided in batches of 2 or 4 (corrected by the pair terms of the moves
     accepted earlier in the batch, a trial whose particle index or particle changed
     left to the next batch) give the sequential chain's accept bits, N, labels and
-    counters: small N, N above a group's lanes, a binned slab, walkers per block."""
+    counters: small N, N above a group's lanes, a binned slab, walkers per block; in
+    one wave per walker, or (split equal to the batch) one wave per trial."""
+    kw = dict(batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl, split=split)
     w = W.small_lj(n_t=4, n_mu=4, n_max=20, n_sweeps=60)
-    _fp64_trajectory(w, 60, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    _fp64_trajectory(w, 60, **kw)
     w2 = W.config2(60).replace(t=np.array([0.9, 1.6]), mu=np.array([-3.0, -2.0]), n_max=160, sample_every=5)
-    _, wk = _fp64_trajectory(w2, 60, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    _, wk = _fp64_trajectory(w2, 60, **kw)
     assert wk["n"].max() > 100
     # a dense, strongly interacting system: many accepted moves inside each batch
     w3 = W.small_lj(n_t=2, n_mu=2, n_max=40, t=(0.7, 1.2), mu=(-3.0, -1.5), height=5.0)
-    _, wk3 = _fp64_trajectory(w3, 150, batch_trials=batch, walkers_per_block=wpb, sweeps_per_launch=spl)
+    _, wk3 = _fp64_trajectory(w3, 150, **kw)
     assert wk3["n"].max() > 25
 
 
@@ -145,6 +148,13 @@ def test_fp64_batched_trials_ideal_gas_and_caps():
                      batch_trials=4)
     _fp64_trajectory(W.small_lj(n_t=2, n_mu=3, n_max=8).replace(trials_per_sweep=1), 200, batch_trials=4)
     _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=300).replace(swap_every=0), 300, batch_trials=2)
+    # one wave per trial
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=3, n_max=30), 300, batch_trials=4, split=4)
+    _fp64_trajectory(W.ideal_gas(n_t=2, n_mu=2, n_max=6).replace(mu=W.linear_grid(-3.0, -2.0, 2)), 200,
+                     batch_trials=4, split=4)
+    _fp64_trajectory(W.small_lj(n_t=2, n_mu=3, n_max=8).replace(trials_per_sweep=1), 200, batch_trials=4, split=4)
+    _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=300).replace(swap_every=0), 300, batch_trials=2,
+                     split=2)
 
 
 @pytest.mark.parametrize("split,cull,cell", [(1, 0, 0.0), (2, 0, 0.0), (1, 1, 0.0), (2, 1, 0.0), (4, 0, 0.0),
