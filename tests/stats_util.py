@@ -54,3 +54,18 @@ def energy_image_sum(xyz, slab, lx, ly, eps_gg=1.0, sig_gg=1.0, eps_gs=1.0, sig_
             d = xyz[i][None, None, :] - (slab[:, None, :] + shifts[None, :, :])
             e += lj_ts((d * d).sum(2), eps_gs, sig_gs, rc).sum()
     return float(e)
+
+
+def assert_within_3se(z, label=""):
+    """The 3-standard-error bar over several states: every |z| <= 4, at most
+    max(1, 5 %) of the states beyond 3 (under the null each exceeds 3 with about
+    0.3-0.5 % probability with 20-batch errors), and a mean z^2 no larger than the
+    99.99 % point of chi^2 with as many degrees of freedom as states, per state."""
+    from scipy.stats import chi2
+    z = np.asarray(z, dtype=np.float64)
+    k = len(z)
+    beyond = int(np.sum(np.abs(z) > 3.0))
+    msg = f"{label}: z = {np.round(z, 2).tolist()}"
+    assert np.all(np.abs(z) <= 4.0), msg
+    assert beyond <= max(1, int(round(0.05 * k))), msg
+    assert float(np.mean(z * z)) <= chi2.ppf(0.9999, k) / k, msg

@@ -5,8 +5,8 @@ so trajectories (accept bits, N, labels, statistics) must be identical to the
 oracle's learned chain and energies agree to 1e-10.  FP32 build (MFMA network):
 the stationary law is checked -- the ideal-gas Poisson mean under a random network
 and under a fixed proposal peaked on 16 voxels (with uniform positions, which tests
-the inverse-CDF voxel draw), and the LJ mean N of the plain FP64 oracle, within 4
-standard errors."""
+the inverse-CDF voxel draw), and the LJ mean N of the plain FP64 oracle, within 3
+standard errors over the states (tests/stats_util.assert_within_3se)."""
 import math
 import sys
 
@@ -16,7 +16,7 @@ import pytest
 import oracle
 from paper_1908_11118_amd import regc
 from paper_1908_11118_amd import workloads as W
-from tests.stats_util import batch_means, per_state_series, truncated_poisson
+from tests.stats_util import assert_within_3se, batch_means, per_state_series, truncated_poisson
 
 pytestmark = pytest.mark.gpu
 
@@ -201,13 +201,15 @@ def test_learned_fp32_ideal_gas_poisson():
         ps = g.proposal_stats()
     net.close()
     n_ser, _ = per_state_series(smp, w.n_states)
+    z = []
     for s in range(w.n_states):
         T, mu = w.t[s // len(w.mu)], w.mu[s % len(w.mu)]
         zv = math.exp(mu / T) * T ** 1.5 * w.volume
         p = truncated_poisson(zv, w.n_max)
         mean_ref = float((np.arange(w.n_max + 1) * p).sum())
         m, se = batch_means(n_ser[:, s])
-        assert abs(m - mean_ref) < 4 * se + 1e-9, (s, m, mean_ref, se)
+        z.append((m - mean_ref) / se)
+    assert_within_3se(z, "ideal gas, random network")
     assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
 
 
@@ -248,13 +250,15 @@ def test_learned_fp32_draw_of_a_peaked_proposal():
         ps = g.proposal_stats()
     net.close()
     n_ser, _ = per_state_series(smp, nw)
+    z = []
     for s in range(nw):
         T, mu = w.t[s // len(w.mu)], w.mu[s % len(w.mu)]
         zv = math.exp(mu / T) * T ** 1.5 * w.volume
         pr = truncated_poisson(zv, w.n_max)
         mean_ref = float((np.arange(w.n_max + 1) * pr).sum())
         m, se = batch_means(n_ser[:, s])
-        assert abs(m - mean_ref) < 4 * se + 1e-9, (s, m, mean_ref, se)
+        z.append((m - mean_ref) / se)
+    assert_within_3se(z, "ideal gas, peaked proposal")
     expected = 16.0 / 4096.0
     assert total > 20000 and abs(in_hot / total - expected) < 0.3 * expected, (in_hot, total, expected)
     assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
@@ -277,17 +281,19 @@ def test_learned_fp32_lj_mean_n_matches_the_plain_oracle():
     net.close()
     na, _ = per_state_series(r, w.n_states)
     nb, _ = per_state_series(smp, w.n_states)
+    z = []
     for s in range(w.n_states):
         ma, sa = batch_means(na[:, s])
         mb, sb = batch_means(nb[:, s])
-        assert abs(ma - mb) < 4 * math.hypot(sa, sb) + 1e-9, (s, ma, mb, sa, sb)
+        z.append((ma - mb) / math.hypot(sa, sb))
+    assert_within_3se(z, "LJ, learned FP32 against the plain oracle")
 
 
 def test_learned_fp32_batch_one_network_per_class_mean_n():
     """The full stack at a small size: two slab classes of different box in one
     batch, each with its own MFMA network (random weights) in the sweep, FP32 pairs:
     every state's mean N agrees with the plain FP64 oracle run of that class within
-    4 standard errors."""
+    3 standard errors (over the states of both classes)."""
     classes = [W.small_lj(n_t=2, n_mu=2, n_max=14, mu=(-4.5, -3.0)).replace(sample_every=1),
                W.small_lj(n_t=2, n_mu=2, n_max=18, box=7.5, height=5.0, mu=(-4.0, -3.0)).replace(sample_every=1)]
     sweeps = 16000
@@ -306,6 +312,7 @@ def test_learned_fp32_batch_one_network_per_class_mean_n():
         net.close()
     assert ps["drawn"] > 0 and ps["drawn_accepted"] > 0
     W_all = sum(cnts)
+    z = []
     for c, w in enumerate(classes):
         ref = oracle.Chain(w, walker_offset=offs[c], class_id=c)
         ref.run(1000)
@@ -317,4 +324,5 @@ def test_learned_fp32_batch_one_network_per_class_mean_n():
         for s in range(w.n_states):
             ma, sa = batch_means(na[:, s])
             mb, sb = batch_means(nb[:, s])
-            assert abs(ma - mb) < 4 * math.hypot(sa, sb) + 1e-9, (c, s, ma, mb, sa, sb)
+            z.append((ma - mb) / math.hypot(sa, sb))
+    assert_within_3se(z, "batch of two classes, one network each")

@@ -90,6 +90,31 @@ def test_adam_first_step_is_signed_lr():
     assert np.allclose(out, p["a"] - step, atol=1e-15)
 
 
+def test_adam_three_steps_closed_forms():
+    """Three steps with beta = 0.9 / 0.999, eps = 0 and |g| the same every step, so
+    the second-moment estimate is exactly g^2 after bias correction: (a) a constant
+    gradient g: every bias-corrected first moment is g, so the parameter moves by
+    lr sign(g) three times; (b) alternating g, -g, g: the first moments are 0.1 g,
+    -0.01 g, 0.091 g, and with the corrections 1 - 0.9^t = 0.1, 0.19, 0.271 the moves
+    are lr sign(g) (1, -1/19, 91/271).  A moment not carried across steps, or a
+    correction with the wrong power, fails one of them."""
+    lr = 1e-2
+    p = {"a": np.array([0.25, -3.0, 1.5])}
+    g = np.array([0.7, -2.0, 1e-3])
+    st = {}
+    for _ in range(3):
+        p = M.adam(p, {"a": g}, st, lr=lr, eps=0.0)
+    assert np.allclose(p["a"], np.array([0.25, -3.0, 1.5]) - 3 * lr * np.sign(g), rtol=0, atol=1e-14)
+    p = {"a": np.array([0.25, -3.0, 1.5])}
+    st = {}
+    for k in range(3):
+        p = M.adam(p, {"a": g if k % 2 == 0 else -g}, st, lr=lr, eps=0.0)
+    moves = 1.0 - 1.0 / 19.0 + 91.0 / 271.0
+    assert np.allclose(p["a"], np.array([0.25, -3.0, 1.5]) - lr * moves * np.sign(g), rtol=0, atol=1e-13)
+    assert st["t"] == 3
+    assert np.allclose(st["m_a"], 0.091 * g, rtol=1e-12)
+
+
 def test_proposal_density_limits_and_voxels():
     params = W.mlp_init(5)
     rng = np.random.default_rng(6)
