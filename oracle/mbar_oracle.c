@@ -233,7 +233,9 @@ void orc_batch_means(int S, int64_t ns, const int32_t *st, const int32_t *nn, in
     for (int64_t i = 0; i < ns; ++i) rank[i] = count[st[i]]++;
     for (int64_t i = 0; i < ns; ++i) {
         const int s = st[i];
-        const int b = (int)((rank[i] * n_batches) / count[s]);
+        /* batch b holds series positions floor(b n / B) .. floor((b + 1) n / B) - 1 */
+        int b = 0;
+        while ((int64_t)(b + 1) * count[s] / n_batches <= rank[i]) ++b;
         bsum[(size_t)s * n_batches + b] += (double)nn[i];
         bcnt[(size_t)s * n_batches + b] += 1;
         total[s] += (double)nn[i];

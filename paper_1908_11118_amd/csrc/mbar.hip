@@ -434,29 +434,52 @@ __global__ void mbar_obs_eval(int nT, int nMu, int nN, int n_obs, const double *
 // ---- errors of the estimates ----
 // Batch means: per-state series position of every sample (samples sorted stably by
 // state), batch b = floor(rank B / n_s), integer sums of N per (state, batch).
-// per-state sample counts; bad when a state is out of range or an N negative
-__global__ void bm_count(int64_t ns, const int32_t *st, const int32_t *n, int S, unsigned long long *omega, int *bad)
+// bad when a state is out of range or an N negative
+__global__ void bm_check(int64_t ns, const int32_t *st, const int32_t *n, int S, int *bad)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = st[i];
-        if (k < 0 || k >= S || n[i] < 0) {
-            atomicOr(bad, 1);
-            continue;
-        }
-        atomicAdd(omega + k, 1ull);
+        if (k < 0 || k >= S || n[i] < 0) atomicOr(bad, 1);
     }
 }
 
-__global__ void bm_accumulate(int64_t ns, int B, const int32_t *sorted_state, const int32_t *sorted_idx,
-                              const int32_t *n_orig, const int64_t *state_start, const int64_t *state_count,
-                              unsigned long long *bsum, unsigned long long *bcnt)
+// Start and length of every state's run in the keys sorted by state (lower bounds).
+__global__ void bm_bounds(int64_t ns, int S, const uint32_t *sorted_state, int64_t *state_start, int64_t *state_count)
 {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < ns; p += (int64_t)gridDim.x * blockDim.x) {
-        const int s = sorted_state[p];
-        const int64_t rank = p - state_start[s], cnt = state_count[s];
-        const int b = (int)((rank * B) / cnt);
-        atomicAdd(bsum + (size_t)s * B + b, (unsigned long long)n_orig[sorted_idx[p]]);
-        atomicAdd(bcnt + (size_t)s * B + b, 1ull);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    auto lower = [&](uint32_t key) {
+        int64_t lo = 0, hi = ns;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (sorted_state[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int64_t a = lower((uint32_t)s), b = lower((uint32_t)s + 1u);
+    state_start[s] = a;
+    state_count[s] = b - a;
+}
+
+// One workgroup per (state, batch): the batch is a contiguous range of the sorted
+// order, its sum of N a block reduction of integers (exact in any order).
+__global__ void bm_segments(int B, const int32_t *sorted_idx, const int32_t *n_orig, const int64_t *state_start,
+                            const int64_t *state_count, unsigned long long *bsum, unsigned long long *bcnt)
+{
+    __shared__ unsigned long long part[4];
+    const int bin = blockIdx.x, s = bin / B, b = bin % B;
+    const int64_t cnt = state_count[s];
+    const int64_t lo = state_start[s] + (b * cnt) / B, hi = state_start[s] + ((b + 1) * cnt) / B;
+    unsigned long long acc = 0;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) acc += (unsigned long long)n_orig[sorted_idx[p]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bsum[bin] = part[0] + part[1] + part[2] + part[3];
+        bcnt[bin] = (unsigned long long)(hi - lo);
     }
 }
 
@@ -1186,22 +1209,19 @@ static int batch_means_dev(hipStream_t s, int64_t ns, const int32_t *st_d, const
     DevBuf<uint32_t> keys, keys_out;
     DevBuf<int32_t> idx, idx_out;
     DevBuf<int64_t> start_d, count_d;
-    DevBuf<unsigned long long> bsum, bcnt, omega;
+    DevBuf<unsigned long long> bsum, bcnt;
     DevBuf<int> bad;
     int rc;
     if ((rc = keys.alloc(ns)) || (rc = keys_out.alloc(ns)) || (rc = idx.alloc(ns)) || (rc = idx_out.alloc(ns)) ||
         (rc = start_d.alloc(S)) || (rc = count_d.alloc(S)) || (rc = bsum.alloc((size_t)S * B)) ||
-        (rc = bcnt.alloc((size_t)S * B)) || (rc = omega.alloc(S)) || (rc = bad.alloc(1)))
+        (rc = bcnt.alloc((size_t)S * B)) || (rc = bad.alloc(1)))
         return rc;
     const int grid = (int)std::min<int64_t>((ns + 255) / 256, 4096);
-    // per-state counts (and the validation of the inputs) first
-    std::vector<unsigned long long> cnt(S);
+    // the inputs are checked before they are used as sort keys
     int h_bad = 0;
-    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S, omega.p);
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, 0, bad.p);
-    hipLaunchKernelGGL(bm_count, dim3(grid), dim3(256), 0, s, ns, st_d, n_d, S, omega.p, bad.p);
+    hipLaunchKernelGGL(bm_check, dim3(grid), dim3(256), 0, s, ns, st_d, n_d, S, bad.p);
     REGC_HIP(hipGetLastError());
-    REGC_HIP(hipMemcpyAsync(cnt.data(), omega.p, sizeof(unsigned long long) * S, hipMemcpyDeviceToHost, s));
     REGC_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
     REGC_HIP(hipStreamSynchronize(s));
     REGC_CHECK(!h_bad, REGC_EINVAL, "a sample's state is outside 0..%d or its N is negative", S - 1);
@@ -1217,19 +1237,10 @@ static int batch_means_dev(hipStream_t s, int64_t ns, const int32_t *st_d, const
     if ((rc = temp.alloc(temp_bytes))) return rc;
     REGC_HIP(hipcub::DeviceRadixSort::SortPairs(temp.p, temp_bytes, keys.p, keys_out.p, idx.p, idx_out.p, (int)ns, 0,
                                                 end_bit, s));
-    std::vector<int64_t> start(S), count(S);
-    int64_t acc = 0;
-    for (int k = 0; k < S; ++k) {
-        start[k] = acc;
-        count[k] = (int64_t)cnt[k];
-        acc += count[k];
-    }
-    REGC_HIP(hipMemcpyAsync(start_d.p, start.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
-    REGC_HIP(hipMemcpyAsync(count_d.p, count.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S * B, bsum.p);
-    hipLaunchKernelGGL(fill_u64, dim3(64), dim3(256), 0, s, (int64_t)S * B, bcnt.p);
-    hipLaunchKernelGGL(bm_accumulate, dim3(grid), dim3(256), 0, s, ns, B, (const int32_t *)keys_out.p, idx_out.p, n_d,
-                       start_d.p, count_d.p, bsum.p, bcnt.p);
+    hipLaunchKernelGGL(bm_bounds, dim3((S + 255) / 256), dim3(256), 0, s, ns, S, keys_out.p, start_d.p, count_d.p);
+    REGC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bm_segments, dim3(S * B), dim3(256), 0, s, B, idx_out.p, n_d, start_d.p, count_d.p, bsum.p,
+                       bcnt.p);
     REGC_HIP(hipGetLastError());
     hipLaunchKernelGGL(bm_finish, dim3((S + 255) / 256), dim3(256), 0, s, S, B, bsum.p, bcnt.p, count_d.p, mean_d,
                        se_d);

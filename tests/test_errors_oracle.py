@@ -34,11 +34,14 @@ def test_batch_means_of_a_constructed_series():
 
 def test_batch_means_uneven_batches_and_too_few_samples():
     # 41 samples in 4 batches: positions floor(b*41/4) .. -> batch sizes 10, 10, 10, 11
-    x = np.arange(41)
+    # (a series whose batch means change when one sample moves between batches)
+    x = np.arange(41) ** 2
     mean, se = oracle.batch_means(1, np.zeros(41, np.int32), x, 4)
     bm = [x[0:10].mean(), x[10:20].mean(), x[20:30].mean(), x[30:41].mean()]
     assert mean[0] == x.mean()
-    assert abs(se[0] - np.std(bm, ddof=1) / 2.0) < 1e-13
+    assert abs(se[0] - np.std(bm, ddof=1) / 2.0) < 1e-12 * se[0]
+    other = [x[0:11].mean(), x[11:21].mean(), x[21:31].mean(), x[31:41].mean()]
+    assert abs(np.std(other, ddof=1) / 2.0 - se[0]) > 1e-3 * se[0]
     m2, s2 = oracle.batch_means(1, np.zeros(3, np.int32), np.arange(3), 4)
     assert math.isnan(m2[0]) and math.isnan(s2[0])
 
