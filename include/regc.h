@@ -175,7 +175,14 @@ typedef struct {
  *                  trial at a time (split and cull apply).  0: 1.
  *  slab_cell       width of the slab's x-y columns as a multiple (>= 1) of the
  *                  smallest one, rcut + max_disp (0: 1): wider columns hold more atoms
- *                  each and fewer per block, the tuner's cell-size choice. */
+ *                  each and fewer per block, the tuner's cell-size choice.
+ *  persistent      R > 0: up to R whole exchange intervals per kernel launch, the
+ *                  exchange steps inside the launch between grid-wide barriers (a
+ *                  cooperative launch: every workgroup resident at once, else
+ *                  EUNSUPPORTED); sweep schedule only, without graph replay, cull,
+ *                  batched trials, the learned proposal, observables or minima
+ *                  (those runs use separate launches).  0: off.  The accept/reject
+ *                  sequence is that of separate launches. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -198,6 +205,7 @@ typedef struct {
     int resync_every;
     int batch_trials;
     double slab_cell;
+    int persistent;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

@@ -2,8 +2,8 @@
 
 The choices it makes -- walkers per workgroup, wavefronts per walker, batched
 trials, the cull pass, slab column binning and its column width (the slab's cell
-size), sweeps per launch and graph replay of several exchange intervals per
-submission -- change only the order of floating-point sums, never the chain (FP64
+size), sweeps per launch, graph replay of several exchange intervals per submission
+and persistent launches of several intervals -- change only the order of floating-point sums, never the chain (FP64
 trajectories are identical for every choice), so the tuned run samples the same
 distribution.
 
@@ -82,7 +82,12 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
     table: List[Dict] = []
 
     def trial(opts):
-        rate = _measure(wl, precision, blob, opts, measure_sweeps)
+        try:
+            rate = _measure(wl, precision, blob, opts, measure_sweeps)
+        except regc.RegcError as err:        # a shape this device or workload cannot run
+            if err.code not in (regc.EUNSUPPORTED, regc.EINVAL):
+                raise
+            rate = 0.0
         table.append({"options": dict(opts), "trials_per_s": rate})
         if verbose:
             print(f"[autotune] {opts} -> {rate:.4g} trials/s", file=sys.stderr, flush=True)
@@ -90,14 +95,14 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
 
     # 0 everywhere: the library's own choices
     best = {"walkers_per_block": 0, "split": 0, "batch_trials": 0, "cull": 0, "slab_bins": 0, "slab_cell": 0.0,
-            "sweeps_per_launch": 0, "graph_intervals": 0}
+            "sweeps_per_launch": 0, "graph_intervals": 0, "persistent": 0}
     best_rate = trial(best)
     spl = sorted({s for s in (interval // 2, max(1, interval // 5)) if 0 < s < interval})
     # batched trials: (trials per batch, waves per walker) -- one wave per walker, or one
     # wave per trial
     space = [("walkers_per_block", [1, 2, 4, 8]), ("split", [1, 2, 4]), ("batch", [(2, 1), (4, 1), (2, 2), (4, 4)]),
              ("cull", [1]), ("slab_bins", [-1]), ("slab_cell", [1.25, 1.5]), ("sweeps_per_launch", spl),
-             ("graph_intervals", [4, 10])]
+             ("graph_intervals", [4, 10]), ("persistent", [10])]
     for name, values in space:
         for v in values:
             cand = dict(best)
@@ -109,6 +114,10 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
                 cand[name] = v
             if name == "split" and v > 1:
                 cand["batch_trials"], cand["walkers_per_block"] = 1, 1
+            if name == "persistent":
+                # whole exchange intervals in one cooperative launch: no graph, cull or batching
+                cand["graph_intervals"], cand["cull"], cand["batch_trials"] = 0, 0, min(cand["batch_trials"], 1)
+                cand["split"] = min(cand["split"], 2)
             rate = trial(cand)
             if rate > best_rate:
                 best, best_rate = cand, rate

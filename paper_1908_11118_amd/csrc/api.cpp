@@ -96,6 +96,9 @@ struct regc_ctx {
 
     // graph replay of whole exchange intervals
     DevBuf<int64_t> clock_d;
+    DevBuf<unsigned int> gbar_d;   // grid barrier of the persistent launch: arrivals, generation
+    DevBuf<int> gerr_d;            // set when a grid barrier wait exceeded its bound
+    bool persist_used = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -157,6 +160,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->resync_every = 0;
     o->batch_trials = 0;
     o->slab_cell = 0.0;
+    o->persistent = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -192,6 +196,11 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->resync_every >= -1, REGC_EINVAL, "resync_every must be -1, 0 or positive");
     REGC_CHECK(o->slab_cell == 0.0 || (o->slab_cell >= 1.0 && o->slab_cell <= 16.0), REGC_EINVAL,
                "slab_cell must be 0 or in [1, 16]");
+    REGC_CHECK(o->persistent >= 0, REGC_EINVAL, "persistent must be 0 or positive");
+    REGC_CHECK(o->persistent == 0 || (o->schedule == 0 && o->graph_intervals == 0 && o->batch_trials <= 1 &&
+                                      o->cull <= 0 && o->split <= 2 && o->swap_every > 0),
+               REGC_EINVAL, "persistent launches need the sweep schedule with exchanges, one trial at a time, "
+                            "split 0, 1 or 2, no cull and no graph replay");
     REGC_CHECK(o->batch_trials >= 0 && o->batch_trials <= 4 && o->batch_trials != 3, REGC_EINVAL,
                "batch_trials must be 0, 1, 2 or 4");
     if (o->schedule == 1) {
@@ -449,8 +458,11 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->hist_d.alloc((size_t)W * (nmax + 1))) || (rc = c->stats_d.alloc((size_t)W * kNStat)) ||
         (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) || (rc = c->pairs_d.alloc(2)) ||
         (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
-        (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)) || (rc = c->clock_d.alloc(1)))
+        (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)) || (rc = c->clock_d.alloc(1)) ||
+        (rc = c->gbar_d.alloc(2)) || (rc = c->gerr_d.alloc(1)))
         return rc;
+    REGC_HIP(hipMemset(c->gbar_d.p, 0, sizeof(unsigned int) * 2));
+    REGC_HIP(hipMemset(c->gerr_d.p, 0, sizeof(int)));
     if (o.schedule == 1 && o.md_steps > 0) {
         if ((rc = c->vel_d.alloc((size_t)W * nmax * 3)) || (rc = c->tv_d.alloc(W))) return rc;
         REGC_HIP(hipMemset(c->vel_d.p, 0, sizeof(double) * (size_t)W * nmax * 3));
@@ -573,7 +585,7 @@ static bool learned_on(const regc_ctx *c)
     return false;
 }
 
-static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream, bool use_clock)
+static SweepArgs sweep_args(regc_ctx *c, int64_t sweep0, int n, bool use_clock)
 {
     SweepArgs a{};
     a.cls = c->cls_d.p;
@@ -620,6 +632,12 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     a.count_pairs = c->count_pairs ? 1 : 0;
     a.resync_every = c->opts.resync_every > 0 ? c->opts.resync_every
                                               : (c->opts.resync_every == 0 && c->opts.precision == REGC_FP32PAIR ? 100 : 0);
+    return a;
+}
+
+static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream, bool use_clock)
+{
+    SweepArgs a = sweep_args(c, sweep0, n, use_clock);
     int rc;
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_sweep, true))) return rc;
@@ -669,7 +687,7 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
     return REGC_OK;
 }
 
-static int launch_exchange(regc_ctx *c, int64_t q, hipStream_t stream, bool use_clock)
+static SwapArgs swap_args(regc_ctx *c, int64_t q, bool use_clock)
 {
     SwapArgs a{};
     a.cls = c->cls_d.p;
@@ -689,11 +707,52 @@ static int launch_exchange(regc_ctx *c, int64_t q, hipStream_t stream, bool use_
     a.clock = use_clock ? c->clock_d.p : nullptr;
     a.interval = c->opts.swap_every;
     a.swap_every = c->opts.swap_every;
+    return a;
+}
+
+static int launch_exchange(regc_ctx *c, int64_t q, hipStream_t stream, bool use_clock)
+{
+    SwapArgs a = swap_args(c, q, use_clock);
     int rc;
     const bool ev = c->timing && !use_clock;
     if (ev && (rc = record_event(c, c->ev_swap, true))) return rc;
     REGC_HIP(launch_swap(a, (int)c->cls.size(), stream));
     if (ev && (rc = record_event(c, c->ev_swap, false))) return rc;
+    return REGC_OK;
+}
+
+// `intervals` whole exchange intervals from sweep0 (an interval boundary) in one
+// cooperative launch of the persistent sweep kernel, the exchange steps inside it.
+static int launch_persistent(regc_ctx *c, int64_t sweep0, int intervals)
+{
+    const int se = c->opts.swap_every;
+    SweepArgs a = sweep_args(c, sweep0, intervals * se, false);
+    a.sw = swap_args(c, 0, false);
+    a.swap_every = se;
+    a.n_class = (int)c->cls.size();
+    a.gbar = c->gbar_d.p;
+    a.gerr = c->gerr_d.p;
+    int max_blocks = 0;
+    const int wpb_waves = c->wpb * c->split;
+    if (c->opts.precision == REGC_FP64)
+        REGC_HIP(persist_capacity_f64(wpb_waves, c->split, c->smem, &max_blocks));
+    else
+        REGC_HIP(persist_capacity_f32(wpb_waves, c->split, c->smem, &max_blocks));
+    REGC_CHECK(max_blocks >= c->nblocks, REGC_EUNSUPPORTED,
+               "a persistent launch needs all %d workgroups resident at once; the device holds %d", c->nblocks,
+               max_blocks);
+    REGC_CHECK(a.n_class <= c->nblocks, REGC_EUNSUPPORTED, "fewer workgroups than classes");
+    int rc;
+    // the barrier starts from zero arrivals (also after a launch that reported a
+    // timed-out wait)
+    REGC_HIP(hipMemsetAsync(c->gbar_d.p, 0, sizeof(unsigned int) * 2, c->stream));
+    if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
+    if (c->opts.precision == REGC_FP64)
+        REGC_HIP(launch_sweep_persist_f64(a, c->nblocks, wpb_waves, c->split, c->smem, c->stream));
+    else
+        REGC_HIP(launch_sweep_persist_f32(a, c->nblocks, wpb_waves, c->split, c->smem, c->stream));
+    if (c->timing && (rc = record_event(c, c->ev_sweep, false))) return rc;
+    c->persist_used = true;
     return REGC_OK;
 }
 
@@ -840,9 +899,18 @@ extern "C" int regc_run(regc_ctx *c, int64_t n_sweeps)
         return REGC_OK;
     }
     int64_t left = n_sweeps;
+    const bool persist = o.persistent > 0 && !learned_on(c) && !c->obs_on && !c->min_on;
     auto eager = [&](int64_t count) -> int {
         int64_t rem = count;
         while (rem > 0) {
+            if (persist && c->sweep % o.swap_every == 0 && rem >= o.swap_every) {
+                const int k = (int)std::min<int64_t>(o.persistent, rem / o.swap_every);
+                const int rc = launch_persistent(c, c->sweep, k);
+                if (rc) return rc;
+                c->sweep += (int64_t)k * o.swap_every;
+                rem -= (int64_t)k * o.swap_every;
+                continue;
+            }
             int64_t chunk = rem;
             if (o.swap_every > 0) chunk = std::min<int64_t>(chunk, o.swap_every - c->sweep % o.swap_every);
             const int spl = o.sweeps_per_launch > 0 ? o.sweeps_per_launch : (o.swap_every > 0 ? o.swap_every : 100);
@@ -1189,6 +1257,11 @@ extern "C" int regc_sync(regc_ctx *c)
 {
     REGC_CHECK(c, REGC_EINVAL, "null context");
     REGC_HIP(hipStreamSynchronize(c->stream));
+    if (c->persist_used) {
+        int err = 0;
+        REGC_HIP(hipMemcpy(&err, c->gerr_d.p, sizeof(int), hipMemcpyDeviceToHost));
+        REGC_CHECK(!err, REGC_EHIP, "a grid barrier of a persistent launch waited past its bound");
+    }
     return REGC_OK;
 }
 

@@ -39,6 +39,22 @@ struct PotDev {
     int ideal;
 };
 
+struct SwapArgs {
+    const ClassDev *cls;
+    int32_t *label;
+    int32_t *wos;                // [S_total] global walker holding global state
+    const int32_t *n;
+    const double *e;
+    const double *beta, *lnz;
+    uint32_t key0, key1;
+    int64_t q;                   // exchange step index
+    const int64_t *clock;        // if set: q = (clock[0] + interval) / swap_every - 1
+    int interval, swap_every;
+    int scheme;
+    unsigned long long *att, *acc;   // [4][S_total]
+    int S_total;
+};
+
 struct SweepArgs {
     const ClassDev *cls;
     const int *block_class;      // per block
@@ -78,6 +94,13 @@ struct SweepArgs {
     int max_slab_scan;              // most slab candidates one trial scans (max over classes)
     int resync_every;               // > 0: running energy recomputed after every resync_every-th sweep
     int count_pairs;                // batched kernel: count the pair terms inside the cutoff
+    // persistent launch: the exchange step inside the launch after every swap_every-th
+    // sweep, between two grid-wide barriers (gbar: arrival count, generation; gerr set
+    // when a barrier wait exceeded its bound)
+    SwapArgs sw;
+    int swap_every, n_class;
+    unsigned int *gbar;
+    int *gerr;
 };
 
 // Structural observables of every walker at a sample point (see regc.h).
@@ -125,21 +148,6 @@ __host__ __device__ inline size_t md_lds_bytes(int gas_stride, int walkers)
     return (size_t)walkers * gas_stride * 48;
 }
 
-struct SwapArgs {
-    const ClassDev *cls;
-    int32_t *label;
-    int32_t *wos;                // [S_total] global walker holding global state
-    const int32_t *n;
-    const double *e;
-    const double *beta, *lnz;
-    uint32_t key0, key1;
-    int64_t q;                   // exchange step index
-    const int64_t *clock;        // if set: q = (clock[0] + interval) / swap_every - 1
-    int interval, swap_every;
-    int scheme;
-    unsigned long long *att, *acc;   // [4][S_total]
-    int S_total;
-};
 
 struct EnergyArgs {
     const ClassDev *cls;
@@ -230,6 +238,15 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int n_blocks, int waves_per_bloc
                             size_t smem, hipStream_t s);
 hipError_t launch_sweep_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, bool cull, int batch,
                             size_t smem, hipStream_t s);
+// persistent form of the one-trial kernel (split 1 or 2, no cull): a cooperative launch
+// of whole exchange intervals; fails when the grid cannot be resident at once
+hipError_t launch_sweep_persist_f64(const SweepArgs &a, int n_blocks, int waves_per_block, int split, size_t smem,
+                                    hipStream_t s);
+hipError_t launch_sweep_persist_f32(const SweepArgs &a, int n_blocks, int waves_per_block, int split, size_t smem,
+                                    hipStream_t s);
+// workgroups of the persistent form that fit the device at once
+hipError_t persist_capacity_f64(int waves_per_block, int split, size_t smem, int *max_blocks);
+hipError_t persist_capacity_f32(int waves_per_block, int split, size_t smem, int *max_blocks);
 hipError_t launch_paper_f64(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
                             hipStream_t s);
 hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,

@@ -35,14 +35,19 @@
 //              inside the cutoff in LDS (compacted across the wave); the LJ terms are
 //              evaluated on the queue only.
 #include "sweep_dev.h"
+#include "swap_dev.h"
 
 #if defined(REGC_FP64)
 #define SWEEP_LAUNCH launch_sweep_f64
+#define PERSIST_LAUNCH launch_sweep_persist_f64
+#define PERSIST_CAPACITY persist_capacity_f64
 #define PAPER_LAUNCH launch_paper_f64
 #define ENERGY_KERNEL energy_kernel_f64
 #define ENERGY_LAUNCH launch_energy_f64
 #else
 #define SWEEP_LAUNCH launch_sweep_f32
+#define PERSIST_LAUNCH launch_sweep_persist_f32
+#define PERSIST_CAPACITY persist_capacity_f32
 #define PAPER_LAUNCH launch_paper_f32
 #define ENERGY_KERNEL energy_kernel_f32
 #define ENERGY_LAUNCH launch_energy_f32
@@ -62,8 +67,46 @@ constexpr int kSweepWavesPerSimd = 1;
 constexpr int kSweepWavesPerSimd = 4;
 #endif
 
-template <int SPLIT, bool CULL>
-__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSweepWavesPerSimd : 1) sweep_kernel(SweepArgs a)
+// Grid-wide barrier of the persistent launch (every workgroup resident: cooperative
+// launch).  Thread 0 of each workgroup arrives on gbar[0]; the last to arrive resets it
+// and advances the generation gbar[1], which the others wait for.  A wait is bounded:
+// past the bound the workgroup sets gerr and goes on, so the launch always ends (the
+// host then reports the run as failed).
+constexpr unsigned kGridSpinLimit = 1u << 26;
+
+__device__ __forceinline__ void grid_sync(const SweepArgs &a)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *bar = a.gbar;
+        const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins == kGridSpinLimit) {
+                    atomicOr(a.gerr, 1);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// The one-trial sweep (template body of sweep_kernel and sweep_persist_kernel).
+// PERSIST: whole exchange intervals in one launch; after every swap_every-th sweep
+// each walker publishes N and E, the workgroups meet at a grid barrier, workgroup c
+// (wave 0) runs the exchange step of class c, they meet again, and every walker
+// reads its new state.
+template <int SPLIT, bool CULL, bool PERSIST>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int wave = threadIdx.x / kWave;
@@ -99,7 +142,14 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSwe
     }
     for (int k = threadIdx.x; k < a.gas_stride + 2; k += blockDim.x) lnk[k] = a.lnk[k];
     __syncthreads();
-    if (slot >= nw) return;    // (blocks with SPLIT > 1 always hold one walker)
+    if (slot >= nw) {          // (blocks with SPLIT > 1 always hold one walker)
+        if (PERSIST)           // a wave without a walker still meets every grid barrier
+            for (int k = 0; k < a.n_sweeps / a.swap_every; ++k) {
+                grid_sync(a);
+                grid_sync(a);
+            }
+        return;
+    }
 
     const int w = a.block_w0[blk] + slot;
     const int n_max = C.n_max;
@@ -108,11 +158,11 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSwe
     // ---- walker state into LDS / registers ----
     int n = a.n[w];
     double e = a.e[w];
-    const int label = a.label[w];
-    const int sg = C.state_off + label;
-    const double beta = a.beta[sg];
-    const double lnz = a.lnz[sg];
-    const double lnzv = in_vgpr(lnz + C.lnv);
+    int label = a.label[w];
+    int sg = C.state_off + label;
+    double beta = a.beta[sg];
+    double lnz = a.lnz[sg];
+    double lnzv = in_vgpr(lnz + C.lnv);
     {
         const double *src = a.xyz + (size_t)w * a.xyz_stride * 3;
         for (int k = part * kWave + lane; k < n; k += SPLIT * kWave) {
@@ -142,7 +192,7 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSwe
     const double lx = in_vgpr(C.lx), ly = in_vgpr(C.ly), zlo = in_vgpr(C.zlo), zhi = in_vgpr(C.zhi);
     const double H = in_vgpr(C.zhi - C.zlo);
     const double md = in_vgpr(a.max_disp);
-    const double tinv = in_vgpr(1.0 / beta);
+    double tinv = in_vgpr(1.0 / beta);
     const int slab_scan = C.bins ? 9 * C.cap : slab_len;
 
     uint32_t stat = 0;     // lane k < kNStat holds counter k
@@ -314,6 +364,30 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSwe
                 atomicAdd(a.hist + (size_t)sg * a.hist_stride + n, 1ull);
             }
         }
+        if (PERSIST && (sweep + 1) % a.swap_every == 0) {
+            // ---- the exchange step inside the launch ----
+            if (part == 0) {
+                if (lane < kNStat && stat) atomicAdd(a.stats + (size_t)sg * kNStat + lane, (unsigned long long)stat);
+                if (lane == 0) {
+                    a.n[w] = n;
+                    a.e[w] = e;
+                }
+                __threadfence();       // this wave's stores visible to every workgroup
+            }
+            stat = 0;
+            grid_sync(a);
+            if (blk < a.n_class && threadIdx.x < kWave) {
+                swap_class<true>(a.sw, blk, (sweep + 1) / a.swap_every - 1, lane, kWave);
+                __threadfence();
+            }
+            grid_sync(a);
+            label = __hip_atomic_load(a.label + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sg = C.state_off + label;
+            beta = a.beta[sg];
+            lnz = a.lnz[sg];
+            lnzv = in_vgpr(lnz + C.lnv);
+            tinv = in_vgpr(1.0 / beta);
+        }
     }
 
     // ---- write back ----
@@ -341,6 +415,19 @@ __global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSwe
             a.e[w] = e;
         }
     }
+}
+
+template <int SPLIT, bool CULL>
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSweepWavesPerSimd : 1)
+    sweep_kernel(SweepArgs a)
+{
+    sweep_body<SPLIT, CULL, false>(a);
+}
+
+template <int SPLIT>
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock) sweep_persist_kernel(SweepArgs a)
+{
+    sweep_body<SPLIT, false, true>(a);
 }
 
 // ---- batched trials -------------------------------------------------------------
@@ -1610,6 +1697,32 @@ hipError_t SWEEP_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, i
         else hipLaunchKernelGGL((sweep_kernel<1, false>), grid, block, smem, s, a);
     }
     return hipGetLastError();
+}
+
+static const void *persist_kernel(int split)
+{
+    return split == 2 ? reinterpret_cast<const void *>(&sweep_persist_kernel<2>)
+                      : reinterpret_cast<const void *>(&sweep_persist_kernel<1>);
+}
+
+hipError_t PERSIST_LAUNCH(const SweepArgs &a, int n_blocks, int waves_per_block, int split, size_t smem,
+                          hipStream_t s)
+{
+    SweepArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel(persist_kernel(split), dim3(n_blocks), dim3(kWave * waves_per_block), args,
+                                      (unsigned)smem, s);
+}
+
+hipError_t PERSIST_CAPACITY(int waves_per_block, int split, size_t smem, int *max_blocks)
+{
+    int dev = 0, n_cu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persist_kernel(split), kWave * waves_per_block, smem);
+    *max_blocks = per * n_cu;
+    return e;
 }
 
 }  // namespace regc

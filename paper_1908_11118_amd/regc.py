@@ -84,7 +84,8 @@ class Opts(C.Structure):
                 ("slab_bins", C.c_int), ("split", C.c_int), ("cull", C.c_int),
                 ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
                 ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double), ("resync_every", C.c_int),
-                ("batch_trials", C.c_int), ("slab_cell", C.c_double)]
+                ("batch_trials", C.c_int), ("slab_cell", C.c_double),
+                ("persistent", C.c_int)]
 
 
 _lib = None
@@ -214,6 +215,7 @@ class Regc:
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
                  walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
                  cull: int = 0, graph_intervals: int = 0, resync_every: int = 0, batch_trials: int = 0, slab_cell: float = 0.0,
+                 persistent: int = 0,
                  stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
@@ -246,6 +248,7 @@ class Regc:
         o.resync_every = resync_every
         o.batch_trials = batch_trials
         o.slab_cell = slab_cell
+        o.persistent = persistent
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:

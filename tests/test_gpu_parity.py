@@ -198,15 +198,15 @@ def _batch_classes():
 
 
 @pytest.mark.parametrize("graph", [0, 2])
-def test_fp64_uneven_batch(graph):
+def test_fp64_uneven_batch(graph, persistent=0, **kw):
     """Three classes of different slab, box, n_max and grid in the same launches:
     each class's trajectories equal a lone oracle simulation with the batch's
     Philox stream offsets; with graph replay of whole exchange intervals too."""
     classes = _batch_classes()
     sweeps = 63
-    _say(f"[batch] {len(classes)} classes, graph={graph}")
+    _say(f"[batch] {len(classes)} classes, graph={graph} persistent={persistent} {kw}")
     with regc.Regc(classes, precision=regc.FP64, trace_capacity=sweeps, graph_intervals=graph,
-                   sample_capacity=0) as g:
+                   sample_capacity=0, persistent=persistent, **kw) as g:
         g.run(25)
         g.run(sweeps - 25)
         bits, nps = g.trace(sweeps)
@@ -636,6 +636,30 @@ def test_fp64_minima_and_aiat_map_match_the_oracle():
         assert np.array_equal(xyz[N, :N], ref.min_xyz[N, :N]), N
     mu = np.linspace(-9.0, -1.0, 161)
     assert np.array_equal(regc.aiat_phase(e_min, mu), oracle.aiat_phase(ref.min_e, mu))
+
+
+@pytest.mark.parametrize("persist,split,wpb", [(1, 0, 0), (4, 2, 0), (3, 1, 4), (2, 1, 1)])
+def test_fp64_persistent_launch_keeps_the_trajectories(persist, split, wpb):
+    """Whole exchange intervals in one cooperative launch, the exchange steps inside
+    it between grid barriers: accept bits, N, labels, samples and exchange counters
+    equal the oracle's -- one class (two or one waves per walker, a partly filled
+    workgroup of four walkers), an odd grid with the diagonal scheme, and the uneven
+    batch of three classes (runs that do not start on an interval boundary)."""
+    w = W.small_lj(n_t=4, n_mu=4, n_max=20, n_sweeps=60)
+    _fp64_trajectory(w, 60, persistent=persist, split=split, walkers_per_block=wpb)
+    w3 = W.config3_classes()[0].replace(t=W.linear_grid(0.6, 1.8, 3), mu=W.linear_grid(-6.0, -2.5, 5),
+                                        n_max=60, swap_scheme=1, sample_every=3)
+    _fp64_trajectory(w3, 100, persistent=persist, split=split, walkers_per_block=wpb)
+    test_fp64_uneven_batch(0, persistent=persist, split=split, walkers_per_block=wpb)
+
+
+def test_persistent_launch_option_errors():
+    w = W.small_lj(n_t=2, n_mu=2, n_max=10)
+    for bad in (dict(persistent=2, graph_intervals=2), dict(persistent=2, cull=1), dict(persistent=2, batch_trials=4),
+                dict(persistent=2, split=4), dict(persistent=-1)):
+        with pytest.raises(regc.RegcError) as ei:
+            regc.Regc(w, **bad)
+        assert ei.value.code == regc.EINVAL, bad
 
 
 def test_fp64_minima_per_class_of_a_batch():
