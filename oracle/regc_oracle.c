@@ -422,6 +422,7 @@ int orc_obs_count(const orc_config *c)
 
 void orc_observables(const orc_config *c, const double *xyz, int n, double *out)
 {
+    if (c->obs_dz <= 0.0) return;     /* no observables configured (orc_obs_count is 0) */
     const int nz = (int)ceil((c->zhi - c->zlo) / c->obs_dz);
     const int no = nz + c->obs_nr + 1;
     for (int k = 0; k < no; ++k) out[k] = 0.0;
