@@ -182,7 +182,15 @@ typedef struct {
  *                  EUNSUPPORTED); sweep schedule only, without graph replay, cull,
  *                  batched trials, the learned proposal, observables or minima
  *                  (those runs use separate launches).  0: off.  The accept/reject
- *                  sequence is that of separate launches. */
+ *                  sequence is that of separate launches.
+ *  balance         one-trial sweep kernel: 1: before every sweep launch a small kernel
+ *                  orders each class's walkers by their current particle count and deals
+ *                  them round-robin to the class's workgroups, so that every workgroup
+ *                  holds walkers of all costs and the compute units finish together
+ *                  (classes whose walker count is not a multiple of the walkers per
+ *                  workgroup keep their order); -1: walkers in index order; 0 (default):
+ *                  1 when there are more than four walkers per compute unit, else -1.
+ *                  Which wave runs a walker does not change its trials or results. */
 typedef struct {
     uint64_t seed;
     int precision;
@@ -206,6 +214,7 @@ typedef struct {
     int batch_trials;
     double slab_cell;
     int persistent;
+    int balance;
 } regc_opts;
 
 typedef struct regc_ctx regc_ctx;

@@ -3,9 +3,10 @@
 The choices it makes -- walkers per workgroup, wavefronts per walker, batched
 trials, the cull pass, slab column binning and its column width (the slab's cell
 size), sweeps per launch, graph replay of several exchange intervals per submission
-and persistent launches of several intervals -- change only the order of floating-point sums, never the chain (FP64
-trajectories are identical for every choice), so the tuned run samples the same
-distribution.
+persistent launches of several intervals, and the walker order dealt by particle count
+(which wave runs which walker) -- change only the order of floating-point sums, never
+the chain (FP64 trajectories are identical for every choice), so the tuned run
+samples the same distribution.
 
 Procedure: equilibrate one context with default options, checkpoint it, then for
 each candidate build a context, restore the checkpoint, run a short timed window
@@ -95,14 +96,14 @@ def autotune(workloads, precision: int = regc.FP32PAIR, warm_sweeps: int = 500, 
 
     # 0 everywhere: the library's own choices
     best = {"walkers_per_block": 0, "split": 0, "batch_trials": 0, "cull": 0, "slab_bins": 0, "slab_cell": 0.0,
-            "sweeps_per_launch": 0, "graph_intervals": 0, "persistent": 0}
+            "sweeps_per_launch": 0, "graph_intervals": 0, "persistent": 0, "balance": 0}
     best_rate = trial(best)
     spl = sorted({s for s in (interval // 2, max(1, interval // 5)) if 0 < s < interval})
     # batched trials: (trials per batch, waves per walker) -- one wave per walker, or one
     # wave per trial
     space = [("walkers_per_block", [1, 2, 4, 8]), ("split", [1, 2, 4]), ("batch", [(2, 1), (4, 1), (2, 2), (4, 4)]),
              ("cull", [1]), ("slab_bins", [-1]), ("slab_cell", [1.25, 1.5]), ("sweeps_per_launch", spl),
-             ("graph_intervals", [4, 10]), ("persistent", [10])]
+             ("graph_intervals", [4, 10]), ("persistent", [10]), ("balance", [1, -1])]
     for name, values in space:
         for v in values:
             cand = dict(best)

@@ -49,12 +49,14 @@ struct regc_ctx {
     hipStream_t stream = nullptr;
     int wpb = 1, split = 1, nblocks = 0, max_slab_len = 0, max_slab_scan = 0;
     bool cull = false;
+    bool balance = false;   // walker order by cost before each one-trial sweep launch
     int batch = 1;     // trials per pass of the sweep kernel (1: one-trial kernel)
     bool count_pairs = false;   // batched kernel: count pair terms inside the cutoff
     size_t smem = 0;
 
     DevBuf<ClassDev> cls_d;
     DevBuf<int> block_class_d, block_w0_d, block_nw_d, walker_class_d, unb_off_d, unb_len_d;
+    DevBuf<int> wslot_d;       // walker order of the one-trial sweep launches (balance)
     DevBuf<int32_t> n_d, label_d, wos_d;
     DevBuf<double> e_d, xyz_d, beta_d, lnz_d, lnk_d, slab4_d, unb_d;
     DevBuf<float> slab4f_d;
@@ -161,6 +163,7 @@ extern "C" void regc_default_opts(regc_opts *o)
     o->batch_trials = 0;
     o->slab_cell = 0.0;
     o->persistent = 0;
+    o->balance = 0;
 }
 
 static int validate(const regc_potential *pot, const regc_system *sys, const regc_grid *grid, const regc_opts *o)
@@ -197,6 +200,7 @@ static int validate(const regc_potential *pot, const regc_system *sys, const reg
     REGC_CHECK(o->slab_cell == 0.0 || (o->slab_cell >= 1.0 && o->slab_cell <= 16.0), REGC_EINVAL,
                "slab_cell must be 0 or in [1, 16]");
     REGC_CHECK(o->persistent >= 0, REGC_EINVAL, "persistent must be 0 or positive");
+    REGC_CHECK(o->balance >= -1 && o->balance <= 1, REGC_EINVAL, "balance must be -1, 0 or 1");
     REGC_CHECK(o->persistent == 0 || (o->schedule == 0 && o->graph_intervals == 0 && o->batch_trials <= 1 &&
                                       o->cull <= 0 && o->split <= 2 && o->swap_every > 0),
                REGC_EINVAL, "persistent launches need the sweep schedule with exchanges, one trial at a time, "
@@ -395,6 +399,12 @@ static int ctx_alloc_and_init(regc_ctx *c)
     c->wpb = wpb;
     c->split = split;
     c->cull = cull;
+    // walker order by cost: on by default where several walkers share a SIMD (the
+    // SIMDs' throughput is the limit, and neighbouring states with similar particle
+    // counts in one workgroup left compute units idle while others ran: 4096-replica
+    // uneven batch 14.9 -> 11.6 ms per launch), off at one walker per SIMD, where each
+    // chain's latency is the limit and the extra launch only costs (1 %, 1024 walkers)
+    c->balance = o.balance > 0 || (o.balance == 0 && W > 4 * n_cu);
     c->batch = batch;
     c->smem = smem_for(wpb);
     if (o.schedule == 1 && o.md_steps > 0) {
@@ -459,7 +469,7 @@ static int ctx_alloc_and_init(regc_ctx *c)
         (rc = c->att_d.alloc((size_t)4 * W)) || (rc = c->acc_d.alloc((size_t)4 * W)) || (rc = c->pairs_d.alloc(2)) ||
         (rc = c->trace_bits_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W * c->words)) ||
         (rc = c->trace_n_d.alloc((size_t)std::max<int64_t>(c->trace_cap, 0) * W)) || (rc = c->clock_d.alloc(1)) ||
-        (rc = c->gbar_d.alloc(2)) || (rc = c->gerr_d.alloc(1)))
+        (rc = c->gbar_d.alloc(2)) || (rc = c->gerr_d.alloc(1)) || (rc = c->wslot_d.alloc(W)))
         return rc;
     REGC_HIP(hipMemset(c->gbar_d.p, 0, sizeof(unsigned int) * 2));
     REGC_HIP(hipMemset(c->gerr_d.p, 0, sizeof(int)));
@@ -678,10 +688,15 @@ static int launch_sweeps(regc_ctx *c, int64_t sweep0, int n, hipStream_t stream,
             REGC_HIP(launch_learned_f64(a, l, c->learn_smem, stream));
         else
             REGC_HIP(launch_learned_f32(a, l, c->learn_smem, stream));
-    } else if (c->opts.precision == REGC_FP64) {
-        REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
     } else {
-        REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
+        if (c->batch == 1 && c->balance) {
+            REGC_HIP(launch_balance(c->cls_d.p, (int)c->cls.size(), c->n_d.p, c->wpb, c->wslot_d.p, stream));
+            a.wslot = c->wslot_d.p;
+        }
+        if (c->opts.precision == REGC_FP64)
+            REGC_HIP(launch_sweep_f64(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
+        else
+            REGC_HIP(launch_sweep_f32(a, c->nblocks, c->wpb * c->split, c->split, c->cull, c->batch, c->smem, stream));
     }
     if (ev && (rc = record_event(c, c->ev_sweep, false))) return rc;
     return REGC_OK;
@@ -747,6 +762,10 @@ static int launch_persistent(regc_ctx *c, int64_t sweep0, int intervals)
     // timed-out wait)
     REGC_HIP(hipMemsetAsync(c->gbar_d.p, 0, sizeof(unsigned int) * 2, c->stream));
     if (c->timing && (rc = record_event(c, c->ev_sweep, true))) return rc;
+    if (c->balance) {
+        REGC_HIP(launch_balance(c->cls_d.p, (int)c->cls.size(), c->n_d.p, c->wpb, c->wslot_d.p, c->stream));
+        a.wslot = c->wslot_d.p;
+    }
     if (c->opts.precision == REGC_FP64)
         REGC_HIP(launch_sweep_persist_f64(a, c->nblocks, wpb_waves, c->split, c->smem, c->stream));
     else

@@ -60,6 +60,8 @@ struct SweepArgs {
     const int *block_class;      // per block
     const int *block_w0;         // first global walker of the block
     const int *block_nw;         // walkers in the block
+    const int *wslot;            // if set: the walker at block position block_w0 + slot
+                                 // is wslot[block_w0 + slot] (a permutation within each class)
     int n_walkers;               // total walkers
     PotDev pot;
     int32_t *n;
@@ -252,6 +254,7 @@ hipError_t launch_paper_f64(const SweepArgs &a, const PaperArgs &p, int n_blocks
 hipError_t launch_paper_f32(const SweepArgs &a, const PaperArgs &p, int n_blocks, int waves_per_block, size_t smem,
                             hipStream_t s);
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s);
+hipError_t launch_balance(const ClassDev *cls, int n_class, const int32_t *n, int wpb, int *wslot, hipStream_t s);
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_minima(const MinArgs &a, hipStream_t s);
 hipError_t launch_clock_advance(int64_t *clock, int n, hipStream_t s);

@@ -44,6 +44,59 @@ hipError_t launch_clock_set(int64_t *clock, int64_t value, hipStream_t s)
     return hipGetLastError();
 }
 
+// Walker order of a sweep launch, one workgroup per class: the class's walkers are
+// ranked by their current particle count (the cost of their trials; counts bucketed
+// into 64 ranges, descending, ties in arrival order) and dealt round-robin to the
+// class's workgroups, rank r to workgroup r mod nb, slot r / nb.  Every workgroup
+// then holds walkers from the whole range of costs, instead of neighbouring states
+// of the grid with similar particle counts, and the compute units finish together.
+// Classes whose walker count is not a multiple of the workgroup size keep the
+// identity order.  The order decides only which wave runs which walker: every
+// walker's trials, random numbers and results are the same in any order.
+__global__ void __launch_bounds__(1024) balance_kernel(const ClassDev *cls, const int32_t *n, int wpb, int *wslot)
+{
+    constexpr int kBuckets = 64;
+    __shared__ int start[kBuckets];
+    const ClassDev &C = cls[blockIdx.x];
+    const int off = C.walker_off, S = C.n_walkers, nv = C.n_max + 1;
+    if (S % wpb != 0) {
+        for (int k = threadIdx.x; k < S; k += blockDim.x) wslot[off + k] = off + k;
+        return;
+    }
+    auto bucket = [&](int v) {
+        v = v < 0 ? 0 : (v >= nv ? nv - 1 : v);
+        return (int)(((int64_t)v * kBuckets) / nv);
+    };
+    if (threadIdx.x < kBuckets) start[threadIdx.x] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < S; k += blockDim.x) atomicAdd(&start[bucket(n[off + k])], 1);
+    __syncthreads();
+    if (threadIdx.x < kBuckets) {
+        // walkers in buckets above this one: suffix sums over the 64 lanes
+        const int lane = threadIdx.x;
+        const int h = start[lane];
+        int s = h;
+#pragma unroll
+        for (int o = 1; o < kBuckets; o <<= 1) {
+            const int t = __shfl_down(s, o);
+            s += lane + o < kBuckets ? t : 0;
+        }
+        start[lane] = s - h;
+    }
+    __syncthreads();
+    const int nb = S / wpb;
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+        const int r = atomicAdd(&start[bucket(n[off + k])], 1);
+        wslot[off + (r % nb) * wpb + r / nb] = off + k;
+    }
+}
+
+hipError_t launch_balance(const ClassDev *cls, int n_class, const int32_t *n, int wpb, int *wslot, hipStream_t s)
+{
+    hipLaunchKernelGGL(balance_kernel, dim3(n_class), dim3(1024), 0, s, cls, n, wpb, wslot);
+    return hipGetLastError();
+}
+
 hipError_t launch_swap(const SwapArgs &a, int n_class, hipStream_t s)
 {
     hipLaunchKernelGGL(swap_kernel, dim3(n_class), dim3(256), 0, s, a);

@@ -151,7 +151,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         return;
     }
 
-    const int w = a.block_w0[blk] + slot;
+    const int w = a.wslot ? a.wslot[a.block_w0[blk] + slot] : a.block_w0[blk] + slot;
     const int n_max = C.n_max;
     const int K = C.trials;
 

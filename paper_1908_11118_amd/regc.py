@@ -85,7 +85,8 @@ class Opts(C.Structure):
                 ("graph_intervals", C.c_int), ("schedule", C.c_int), ("x0", C.c_double), ("mc_cycles", C.c_int),
                 ("md_steps", C.c_int), ("md_dt", C.c_double), ("md_tau", C.c_double), ("resync_every", C.c_int),
                 ("batch_trials", C.c_int), ("slab_cell", C.c_double),
-                ("persistent", C.c_int)]
+                ("persistent", C.c_int),
+                ("balance", C.c_int)]
 
 
 _lib = None
@@ -215,7 +216,7 @@ class Regc:
     def __init__(self, workloads, precision: int = FP64, sample_capacity: int = 0, trace_capacity: int = 0,
                  walkers_per_block: int = 0, sweeps_per_launch: int = 0, slab_bins: int = 0, split: int = 0,
                  cull: int = 0, graph_intervals: int = 0, resync_every: int = 0, batch_trials: int = 0, slab_cell: float = 0.0,
-                 persistent: int = 0,
+                 persistent: int = 0, balance: int = 0,
                  stream=None):
         wl = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         w0 = wl[0]
@@ -249,6 +250,7 @@ class Regc:
         o.batch_trials = batch_trials
         o.slab_cell = slab_cell
         o.persistent = persistent
+        o.balance = balance
         self.opts = o
         h = C.c_void_p()
         if len(wl) == 1:

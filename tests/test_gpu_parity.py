@@ -230,6 +230,16 @@ def test_fp64_uneven_batch(graph, persistent=0, **kw):
         assert np.array_equal(rec_n, r["n"])
 
 
+@pytest.mark.parametrize("wpb,graph,persistent", [(2, 0, 0), (4, 2, 0), (2, 0, 1)])
+def test_fp64_balanced_walker_order_keeps_the_trajectories(wpb, graph, persistent):
+    """The walker order dealt by particle count before every launch (forced on; with
+    four walkers per workgroup the 6-walker class keeps its order) changes only which
+    wave runs which walker: every class still follows the oracle trial by trial, also
+    under graph replay and inside persistent launches.  A walker left out or run twice
+    in a launch would break its trajectory."""
+    test_fp64_uneven_batch(graph, persistent=persistent, balance=1, walkers_per_block=wpb)
+
+
 def test_checkpoint_restore_continues_identically():
     w = W.small_lj(n_t=2, n_mu=4, n_max=20)
     _say("[checkpoint] small_lj 2x4")
@@ -656,7 +666,7 @@ def test_fp64_persistent_launch_keeps_the_trajectories(persist, split, wpb):
 def test_persistent_launch_option_errors():
     w = W.small_lj(n_t=2, n_mu=2, n_max=10)
     for bad in (dict(persistent=2, graph_intervals=2), dict(persistent=2, cull=1), dict(persistent=2, batch_trials=4),
-                dict(persistent=2, split=4), dict(persistent=-1)):
+                dict(persistent=2, split=4), dict(persistent=-1), dict(balance=2), dict(balance=-2)):
         with pytest.raises(regc.RegcError) as ei:
             regc.Regc(w, **bad)
         assert ei.value.code == regc.EINVAL, bad
