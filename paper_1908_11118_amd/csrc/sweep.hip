@@ -58,9 +58,11 @@ namespace REGC_PREC {
 
 // Waves per SIMD the one-trial kernel's register budget must allow: four in the FP32
 // build with one wave per walker (128 VGPRs, no spills), so that four walkers share
-// each SIMD (measured 2.03e9 against 1.60e9 trial moves/s at 4096 walkers on 256 CUs);
-// with several waves per walker, and in the FP64 build, the registers stay as they are
-// (a 128-register budget spills there and was measured slower).
+// each SIMD (measured 2.03e9 against 1.60e9 trial moves/s at 4096 walkers on 256 CUs),
+// and with four waves per walker (128 VGPRs and a few spilled bytes: 1024 walkers are
+// 4096 waves, which fit at once only at four per SIMD; 3.10 against 4.46 ms per
+// launch); with two waves per walker, and in the FP64 build, the registers stay as
+// they are (a 128-register budget spills there and was measured slower).
 #if defined(REGC_FP64)
 constexpr int kSweepWavesPerSimd = 1;
 #else
@@ -418,7 +420,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 }
 
 template <int SPLIT, bool CULL>
-__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT == 1 ? kSweepWavesPerSimd : 1)
+__global__ void __launch_bounds__(kWave * kMaxWalkersPerBlock, SPLIT != 2 ? kSweepWavesPerSimd : 1)
     sweep_kernel(SweepArgs a)
 {
     sweep_body<SPLIT, CULL, false>(a);
