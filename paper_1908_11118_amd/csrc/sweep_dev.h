@@ -156,6 +156,13 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// A condition that every lane of the wave holds alike, as a wave-uniform value: the
+// branch on it is a scalar branch.
+__device__ __forceinline__ bool uniform(bool c)
+{
+    return __builtin_amdgcn_readfirstlane((int)c) != 0;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -324,6 +331,17 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
     Real acc = 0;
     bool core = false;
     int ng = 0, ns = 0;
+    if (SPLIT == 2 && uniform(n > STEP && n <= 2 * STEP)) {
+        // two blocks for this wave (more than 128 atoms, two waves): both reads issued
+        // before the terms, one LDS round trip instead of two on the trial's chain (the
+        // walkers with the most atoms are the last to finish a launch)
+        const int j = part * kWave + lane, j2 = j + STEP;
+        const bool v1 = j < n, v2 = j2 < n;
+        const Real4 ga = gas[v1 ? j : 0];
+        const Real4 gb = gas[v2 ? j2 : 0];
+        candidate<NEW, OLD, CULL>(b, gg, v1 && j != skip, ga, px, py, pz, qx, qy, qz, acc, core, useful, qgas, ng);
+        candidate<NEW, OLD, CULL>(b, gg, v2 && j2 != skip, gb, px, py, pz, qx, qy, qz, acc, core, useful, qgas, ng);
+    } else
     for (int j0 = part * U * kWave; j0 < n; j0 += STEP) {
         const int j = j0 + lane;
         const bool v1 = j < n;

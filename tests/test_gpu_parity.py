@@ -168,11 +168,13 @@ def test_fp64_dense_walkers(split, cull, cell):
     assert wk["n"].max() > 100
 
 
-def test_fp64_walkers_above_two_wave_widths():
-    """N above 128 up to the cap: the gas loop of one wave per walker runs more than
-    one step of two candidates per lane."""
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_fp64_walkers_above_two_wave_widths(split):
+    """N above 128 up to the cap: with one wave per walker the gas loop runs more than
+    one step of two candidates per lane; with two waves each wave takes its two blocks
+    in one pass; with four, one block each."""
     w = W.config2(40).replace(t=np.array([0.8, 1.2]), mu=np.array([-2.0, -1.0]), n_max=210, sample_every=4)
-    _, wk = _fp64_trajectory(w, 40)
+    _, wk = _fp64_trajectory(w, 40, split=split)
     assert wk["n"].max() > 150
 
 
