@@ -520,11 +520,14 @@ def learned_leg(args):
     out["reference"] = {"sweeps": args.learned_reference, "precision": "FP64", "seconds": time.perf_counter() - t,
                         "max_se": float(ref_se.max())}
     blob = P.equilibrated_state(w)
+    # both forms run until the target is met or --learned-seconds of GPU time are spent
+    # (no sweep cap: the plain form's worst state, at the condensation step, has a noisy
+    # error estimate and can need more than 2e5 sweeps)
     plain = P.time_to_accuracy(w, blob, ref_m, ref_se, tau=args.learned_tau, max_seconds=args.learned_seconds,
-                               log=say)
+                               max_sweeps=10 ** 8, log=say)
     say(f"[learned] plain: reached={plain['reached']} t={plain['t_acc_s']:.2f} s sweeps={plain['sweeps']}")
     learned = P.time_to_accuracy(w, blob, ref_m, ref_se, net=net, alpha=args.learned_alpha, tau=args.learned_tau,
-                                 max_seconds=args.learned_seconds, log=say)
+                                 max_seconds=args.learned_seconds, max_sweeps=10 ** 8, log=say)
     say(f"[learned] learned: reached={learned['reached']} t={learned['t_acc_s']:.2f} s sweeps={learned['sweeps']}")
     net.close()
     keep = ("reached", "t_acc_s", "sweeps", "max_se", "frac_within", "chi2", "ins_acc", "ms_per_sweep")

@@ -53,7 +53,8 @@ extern "C" {
 #define REGC_MODE_IDEAL 1  /* no interactions (epsilon = 0): ideal gas */
 
 #define REGC_FP64 0        /* all arithmetic in FP64 (trajectory-parity mode) */
-#define REGC_FP32PAIR 1    /* pair terms in FP32; energies, decisions, swaps in FP64 */
+#define REGC_FP32PAIR 1    /* coordinates, trial positions and pair terms in FP32; energies,
+                              decisions, swaps in FP64 */
 
 /* per-state counters returned by regc_get_stats, REGC_NSTAT per state */
 #define REGC_NSTAT 10

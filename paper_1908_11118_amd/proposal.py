@@ -149,7 +149,10 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
     """Runs from the checkpoint `blob` (written by equilibrated_state with the same
     seed) until the accuracy target is met or max_sweeps / max_seconds of GPU time
     are spent; returns {"t_acc_s", "sweeps", "reached", "max_se", "frac_within",
-    "chi2", "ins_acc", ...}.  (Sweeps are REGC steps for the paper's schedule.)"""
+    "chi2", "ins_acc", ...}.  (Sweeps are REGC steps for the paper's schedule.)  The
+    target is checked after every `chunk` sweeps up to 16 chunks, then every
+    sixteenth of the sweeps so far (rounded to chunks), so that long runs check it
+    about a hundred times."""
     w = workload.replace(seed=seed, sample_every=1)
     S = w.n_states
     series = _Series(S)
@@ -161,7 +164,7 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
         if net is not None and alpha > 0:
             g.set_proposal(net, alpha)
         st0 = g.stats()["stats"].copy()
-        done = 0
+        done, next_check, checks = 0, chunk, 0
         while done < max_sweeps:
             g.sync()
             t0 = time.perf_counter()
@@ -172,6 +175,10 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
             smp = g.samples()
             g.clear_samples()
             series.add(smp["state"], smp["n"])
+            if done < next_check and done < max_sweeps and t_gpu < max_seconds:
+                continue
+            next_check = done + max(chunk, (done // 16) // chunk * chunk)
+            checks += 1
             m, se = series.mean_se()
             z = (m - ref_mean) / np.sqrt(se ** 2 + ref_se ** 2)
             within = float(np.mean(np.abs(z) <= 3.0))
@@ -179,7 +186,7 @@ def time_to_accuracy(workload, blob: bytes, ref_mean, ref_se, net: Optional["reg
             res = {"reached": bool(np.all(se <= tau) and within >= frac and chi2 <= max_chi2),
                    "t_acc_s": t_gpu, "sweeps": done, "max_se": float(np.max(se)), "frac_within": within,
                    "chi2": chi2}
-            if log and (done // chunk) % 40 == 0:
+            if log and checks % 10 == 0:
                 log(f"[t_acc] alpha={alpha} sweeps={done} t={t_gpu:.2f}s max_se={res['max_se']:.3f} "
                     f"within={within:.3f} chi2={chi2:.2f}")
             if res["reached"] or t_gpu >= max_seconds:
