@@ -319,12 +319,13 @@ __device__ __forceinline__ void candidate(const Box &b, const Pair &pp, bool m, 
 // (all j < n except `skip`) and over the slab candidates of phi(|p - r|) (NEW)
 // minus phi(|q - r|) (OLD).  The wave with index `part` of SPLIT takes every
 // SPLIT-th block of candidates; trip counts are wave-uniform.  Returns the
-// wave-uniform partial sum; `core_out` is this wave's hard-core flag.
-template <bool NEW, bool OLD, int SPLIT, bool CULL>
+// wave-uniform partial sum; `core_out` is this wave's hard-core flag.  PRE (one wave
+// per walker): `pre` holds the first step's two gas atoms per lane, read by the caller.
+template <bool NEW, bool OLD, int SPLIT, bool CULL, bool PRE = false>
 __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip, const SlabView &sv, const Box &b,
                                               const Pair &gg, const Pair &gs, int lane, int part, Real px, Real py,
                                               Real pz, Real qx, Real qy, Real qz, Real *qgas, Real *qslab,
-                                              bool &core_out, uint32_t &useful)
+                                              bool &core_out, uint32_t &useful, const Real4 *pre = nullptr)
 {
     constexpr int U = SPLIT == 1 ? 2 : 1;   // candidates per lane per step
     constexpr int STEP = SPLIT * U * kWave;
@@ -343,6 +344,15 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
         candidate<NEW, OLD, CULL>(b, gg, v2 && j2 != skip, gb, px, py, pz, qx, qy, qz, acc, core, useful, qgas, ng);
     } else
     for (int j0 = part * U * kWave; j0 < n; j0 += STEP) {
+        if (PRE && j0 == 0) {
+            // the first step's atoms were read by the caller ahead of the proposal
+            const int j = lane, j2 = lane + kWave;
+            candidate<NEW, OLD, CULL>(b, gg, j < n && j != skip, pre[0], px, py, pz, qx, qy, qz, acc, core, useful,
+                                      qgas, ng);
+            candidate<NEW, OLD, CULL>(b, gg, j2 < n && j2 != skip, pre[1], px, py, pz, qx, qy, qz, acc, core,
+                                      useful, qgas, ng);
+            continue;
+        }
         const int j = j0 + lane;
         const bool v1 = j < n;
         const Real4 ga = gas[v1 ? j : 0];
