@@ -242,6 +242,38 @@ def test_fp64_balanced_walker_order_keeps_the_trajectories(wpb, graph, persisten
     test_fp64_uneven_batch(graph, persistent=persistent, balance=1, walkers_per_block=wpb)
 
 
+def test_fp64_balanced_walker_order_many_workgroups():
+    """The walker order dealt over several workgroups per class: two classes of 64
+    walkers (8 x 8 states) in workgroups of 8, walkers spread from empty to dense, so
+    that the counting sort sees many particle counts and every workgroup receives one
+    walker of each eighth of the ranks; each class still follows the oracle trial by
+    trial."""
+    c3 = W.config3_classes()
+    classes = [c3[0].replace(t=W.linear_grid(0.6, 1.8, 8), mu=W.linear_grid(-6.0, -2.0, 8), n_max=60),
+               W.small_lj(n_t=8, n_mu=8, n_max=30, mu=(-5.0, -2.0))]
+    classes = [w.replace(sample_every=5, swap_every=10) for w in classes]
+    sweeps = 40
+    _say("[batch] 2 classes x 64 walkers, walker order forced on, 8 walkers per workgroup")
+    with regc.Regc(classes, precision=regc.FP64, trace_capacity=sweeps, sample_capacity=0, balance=1,
+                   walkers_per_block=8) as g:
+        g.run(sweeps)
+        bits, nps = g.trace(sweeps)
+        wk = g.walkers()
+        st = g.stats()
+        offs, cnts = g.offsets, g.counts
+    assert len(set(wk["n"].tolist())) > 10
+    for c, w in enumerate(classes):
+        ref = oracle.Chain(w, walker_offset=offs[c], class_id=c)
+        r = ref.run(sweeps, trace=True)
+        sl = slice(offs[c], offs[c] + cnts[c])
+        words = r["bits"].shape[2]
+        where = _first_divergence(bits[:, sl, :words], r["bits"], nps[:, sl], r["trace_n"])
+        assert where is None, f"class {c}: {where}"
+        assert np.array_equal(wk["n"][sl], ref.n) and np.array_equal(wk["label"][sl], ref.label)
+        assert np.allclose(wk["e"][sl], ref.e, rtol=1e-10, atol=1e-9)
+        assert np.array_equal(st["stats"][sl], ref.stats)
+
+
 def test_checkpoint_restore_continues_identically():
     w = W.small_lj(n_t=2, n_mu=4, n_max=20)
     _say("[checkpoint] small_lj 2x4")
