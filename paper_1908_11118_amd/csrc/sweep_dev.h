@@ -349,8 +349,9 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
             const int j = lane, j2 = lane + kWave;
             candidate<NEW, OLD, CULL>(b, gg, j < n && j != skip, pre[0], px, py, pz, qx, qy, qz, acc, core, useful,
                                       qgas, ng);
-            candidate<NEW, OLD, CULL>(b, gg, j2 < n && j2 != skip, pre[1], px, py, pz, qx, qy, qz, acc, core,
-                                      useful, qgas, ng);
+            if (n > kWave)     // (a second block with no atom in it contributes nothing)
+                candidate<NEW, OLD, CULL>(b, gg, j2 < n && j2 != skip, pre[1], px, py, pz, qx, qy, qz, acc, core,
+                                          useful, qgas, ng);
             continue;
         }
         const int j = j0 + lane;
