@@ -178,6 +178,29 @@ def test_fp64_walkers_above_two_wave_widths(split):
     assert wk["n"].max() > 150
 
 
+def test_fp64_pair_counters_agree_across_launch_shapes():
+    """The candidate and in-cutoff pair counts behind the roofline figures are properties
+    of the trajectory: with FP64 trajectories identical for every one-trial launch shape
+    (one, two or four waves per walker, the cull pass), both counts must be too, and the
+    ideal gas evaluates no pairs at all."""
+    w = W.config2(40).replace(t=np.array([0.8, 1.2]), mu=np.array([-2.0, -1.0]), n_max=210, sample_every=4)
+    counts = {}
+    for kw in (dict(split=1), dict(split=2), dict(split=4), dict(split=1, cull=1), dict(split=2, cull=1)):
+        _say(f"[pair counts] {kw}")
+        with regc.Regc(w, precision=regc.FP64, sample_capacity=0, **kw) as g:
+            g.run(30)
+            counts[tuple(sorted(kw.items()))] = g.pair_counts()
+            n_max_seen = int(g.walkers()["n"].max())
+    assert n_max_seen > 130   # some walkers beyond two wave widths, some steps ragged
+    vals = set(counts.values())
+    assert len(vals) == 1, counts
+    cand, useful = vals.pop()
+    assert 0 < useful < cand
+    with regc.Regc(W.ideal_gas(n_t=2, n_mu=3, n_max=30), precision=regc.FP64, sample_capacity=0) as g:
+        g.run(50)
+        assert g.pair_counts() == (0, 0)
+
+
 def test_fp64_edge_cases():
     # N capped at 1, one state, no exchange, K = 1 trial per sweep
     _fp64_trajectory(W.small_lj(n_t=1, n_mu=1, n_max=1, n_sweeps=500).replace(swap_every=0), 500)
