@@ -392,6 +392,9 @@ __device__ __forceinline__ Real partial_delta(const Real4 *gas, int n, int skip,
                 candidate<NEW, OLD, CULL>(b, gs, vv[u], g[u], px, py, pz, qx, qy, qz, acc, core, useful, qslab, ns);
         }
     }
+    // (two waves per walker: the issue priority of the serial part of the trial, from
+    // the wave reduction on; the sweep kernel lowered it for the pair loop)
+    if (SPLIT == 2) __builtin_amdgcn_s_setprio(2);
     core_out = __any(core);
     if (CULL) {
         useful += lane == 0 ? (uint32_t)(ng + ns) : 0u;
