@@ -329,8 +329,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                             // the rest of the trial (the reduction, the exchange between the
                             // waves, the decision, the update and the next proposal) at a higher
                             // one, so that where two walkers share a SIMD the one on its serial
-                            // path issues first (config 2: 2.43 -> 2.38 ms per launch)
-                            if (SPLIT == 2) __builtin_amdgcn_s_setprio(0);
+                            // path issues first (config 2: 2.43 -> 2.38 ms per launch; four waves
+                            // per walker: 2.93 -> 2.71 ms)
+                            if (SPLIT >= 2) __builtin_amdgcn_s_setprio(0);
                             if (kind == 0)
                                 pd = partial_delta<true, true, SPLIT, CULL, SPLIT == 1>(gas, n, i, sv, b, gg, gs, lane, part, qx,
                                                                             qy, qz, o.x, o.y, o.z, qgas, qslab, core,
@@ -343,6 +344,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                                 pd = partial_delta<false, true, SPLIT, CULL, SPLIT == 1>(gas, n, i, sv, b, gg, gs, lane, part,
                                                                              o.x, o.y, o.z, o.x, o.y, o.z, qgas,
                                                                              qslab, core, useful, pre);
+                            if (SPLIT == 4) __builtin_amdgcn_s_setprio(2);   // (two waves: from the reduction on)
                             if (SPLIT == 1) {
                                 de = (double)pd;
                             } else {
