@@ -230,6 +230,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         const bool tracing = a.trace_bits != nullptr && (sweep - a.trace_sweep0) < a.trace_cap &&
                              sweep >= a.trace_sweep0;
         for (int t0 = 0; t0 < K; t0 += 32) {
+            // (several waves per walker: the batch's random numbers, bulk vector work, at
+            // the lowest issue priority like the pair loop; config 2: 2.39 -> 2.36 ms)
+            if (SPLIT >= 2) __builtin_amdgcn_s_setprio(0);
             // lane-parallel Philox: lane 2j -> block A of trial t0+j, lane 2j+1 -> block B
             const uint4 R = philox4x32_10(
                 make_uint4((uint32_t)(t0 + (lane >> 1)), (uint32_t)sweep, (uint32_t)w, (uint32_t)(lane & 1)),
@@ -242,6 +245,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             const float g0 = (float)f0, g1 = (float)f1, g2 = (float)f2;     // FP32 build: x, y, z uniforms
 #endif
             const int tn = K - t0 < 32 ? K - t0 : 32;
+            if (SPLIT >= 2) __builtin_amdgcn_s_setprio(2);
             uint32_t bits = 0;
             for (int tt = 0; tt < tn; ++tt) {
                 const uint32_t A0 = bcast(R.x, 2 * tt), A1 = bcast(R.y, 2 * tt);
